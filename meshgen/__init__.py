@@ -1,0 +1,351 @@
+"""Seeded synthetic surface meshes (inputs only).
+
+This module builds the closed, oriented triangle meshes that both the CPU
+oracle and the GPU library consume.  It holds none of the loop-shrinking
+method's arithmetic: no field, threshold, front or event logic lives here,
+only geometry generation (parametric torus, signed-distance surfaces
+extracted by marching tetrahedra), vertex welding, jitter and seed choice.
+
+Every mesh is returned as ``Mesh(xyz float64[V,3], tri int32[F,3], seed)``
+with triangles oriented so that their normals point out of the solid
+(counter-clockwise seen from outside).
+
+Workloads (the paper's detailed scanned models are not available, so these
+synthetic surfaces of known genus stand in for them):
+
+* ``torus_grid``      -- 64x32 parametric torus, R=1, r=0.4, N(0,1e-3) jitter
+* ``pretzel``         -- genus-3 union of three tori (R=1, r=0.35, centres
+                         x=-1.6,0,1.6), level-0 surface on a 256^3 sample grid
+                         fitted per axis to the bounding box plus 2 cells,
+                         N(0,1e-4) jitter
+* ``sdf_surface``     -- any signed-distance function at any grid size
+                         (small spheres, tori, multi-tori for tests)
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "Mesh", "torus_grid", "marching_tets", "sdf_surface", "pretzel",
+    "sdf_sphere", "sdf_torus", "sdf_union_tori", "sdf_box", "jittered",
+    "pick_seed", "euler_characteristic", "pretzel_sdf", "multi_torus",
+]
+
+
+@dataclass
+class Mesh:
+    xyz: np.ndarray          # float64 [V,3]
+    tri: np.ndarray          # int32   [F,3], outward oriented
+    seed: int = 0            # seed vertex chosen from the generator's PRNG
+    name: str = ""
+
+    @property
+    def nv(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def nf(self) -> int:
+        return int(self.tri.shape[0])
+
+
+def euler_characteristic(tri: np.ndarray, nv: int) -> int:
+    """V - E + F of a triangle mesh (edges counted once)."""
+    t = np.asarray(tri, dtype=np.int64)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    e.sort(axis=1)
+    ne = np.unique(e[:, 0] * nv + e[:, 1]).size
+    return int(nv - ne + t.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# parametric torus
+# ---------------------------------------------------------------------------
+def torus_grid(n_major: int = 64, n_minor: int = 32, R: float = 1.0,
+               r: float = 0.4, jitter: float = 1e-3, rng_seed: int = 0,
+               jitter_first: bool = True) -> Mesh:
+    """Regular torus grid: vertex (i,j) has id ``n_minor*i + j`` and sits at
+    ((R + r cos phi_j) cos th_i, (R + r cos phi_j) sin th_i, r sin phi_j),
+    th_i = 2 pi i / n_major, phi_j = 2 pi j / n_minor.  Each grid quad
+    (i,j),(i+1,j),(i+1,j+1),(i,j+1) is split along its (i,j)-(i+1,j+1)
+    diagonal.  One PRNG stream draws the N(0, jitter^2) coordinate noise
+    first, then the seed vertex."""
+    i = np.arange(n_major)
+    j = np.arange(n_minor)
+    th = 2.0 * np.pi * i / n_major
+    ph = 2.0 * np.pi * j / n_minor
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    x = (R + r * np.cos(PH)) * np.cos(TH)
+    y = (R + r * np.cos(PH)) * np.sin(TH)
+    z = r * np.sin(PH)
+    xyz = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(np.float64)
+    I, J = np.meshgrid(i, j, indexing="ij")
+    I = I.ravel()
+    J = J.ravel()
+    I1 = (I + 1) % n_major
+    J1 = (J + 1) % n_minor
+    v00 = n_minor * I + J
+    v10 = n_minor * I1 + J
+    v11 = n_minor * I1 + J1
+    v01 = n_minor * I + J1
+    t1 = np.stack([v00, v10, v11], axis=1)
+    t2 = np.stack([v00, v11, v01], axis=1)
+    tri = np.empty((2 * t1.shape[0], 3), dtype=np.int32)
+    tri[0::2] = t1
+    tri[1::2] = t2
+    rng = np.random.default_rng(rng_seed)
+    xyz = xyz + rng.normal(0.0, jitter, size=xyz.shape)
+    seed = int(rng.integers(xyz.shape[0]))
+    return Mesh(xyz, tri, seed, f"torus{n_major}x{n_minor}")
+
+
+# ---------------------------------------------------------------------------
+# signed distance functions (negative inside the solid)
+# ---------------------------------------------------------------------------
+def sdf_sphere(c=(0.0, 0.0, 0.0), rad=1.0):
+    c = np.asarray(c, dtype=np.float64)
+
+    def f(x, y, z):
+        return np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) - rad
+    return f
+
+
+def sdf_torus(c=(0.0, 0.0, 0.0), R=1.0, r=0.35):
+    """Torus in the xy-plane around centre c."""
+    c = np.asarray(c, dtype=np.float64)
+
+    def f(x, y, z):
+        q = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2) - R
+        return np.sqrt(q * q + (z - c[2]) ** 2) - r
+    return f
+
+
+def sdf_union_tori(centres, R=1.0, r=0.35):
+    parts = [sdf_torus(c, R, r) for c in centres]
+
+    def f(x, y, z):
+        out = parts[0](x, y, z)
+        for p in parts[1:]:
+            out = np.minimum(out, p(x, y, z))
+        return out
+    return f
+
+
+def sdf_box(half=(1.0, 1.0, 1.0)):
+    h = np.asarray(half, dtype=np.float64)
+
+    def f(x, y, z):
+        qx = np.abs(x) - h[0]
+        qy = np.abs(y) - h[1]
+        qz = np.abs(z) - h[2]
+        outside = np.sqrt(np.maximum(qx, 0) ** 2 + np.maximum(qy, 0) ** 2 +
+                          np.maximum(qz, 0) ** 2)
+        inside = np.minimum(np.maximum(qx, np.maximum(qy, qz)), 0.0)
+        return outside + inside
+    return f
+
+
+# ---------------------------------------------------------------------------
+# marching tetrahedra
+# ---------------------------------------------------------------------------
+# Corner (dx,dy,dz) of a grid cell has local index dx + 2 dy + 4 dz.  The cell
+# is cut into 6 tetrahedra along its main diagonal 000-111 (one per ordering
+# of the three axes); neighbouring cells then agree on every shared face
+# diagonal, so the extracted surface is watertight.
+def _cell_tets():
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        p = [0, 0, 0]
+        corners = [0]
+        for ax in perm:
+            p[ax] = 1
+            corners.append(p[0] + 2 * p[1] + 4 * p[2])
+        # orientation sign of (e_p0, e_p0+e_p1, e_p0+e_p1+e_p2) = parity(perm)
+        inv = sum(1 for a in range(3) for b in range(a + 1, 3) if perm[a] > perm[b])
+        if inv % 2 == 1:
+            corners[2], corners[3] = corners[3], corners[2]
+        tets.append(corners)
+    return np.array(tets, dtype=np.int64)          # [6,4], positive volume
+
+
+def _even(p):
+    inv = sum(1 for a in range(4) for b in range(a + 1, 4) if p[a] > p[b])
+    return inv % 2 == 0
+
+
+def _tet_case_table():
+    """For each of the 16 inside-patterns of a positively oriented tet
+    (bit i set = local vertex i inside), up to two triangles, each given by
+    three tet edges (pairs of local vertex indices), oriented so the normal
+    points from the inside vertices toward the outside ones."""
+    table = np.full((16, 2, 3, 2), -1, dtype=np.int64)
+    ntri = np.zeros(16, dtype=np.int64)
+    for case in range(16):
+        ins = [i for i in range(4) if case >> i & 1]
+        outs = [i for i in range(4) if not case >> i & 1]
+        if len(ins) in (0, 4):
+            continue
+        if len(ins) in (1, 3):
+            lone = ins[0] if len(ins) == 1 else outs[0]
+            rest = [i for i in range(4) if i != lone]
+            p = [lone] + rest
+            if not _even(p):
+                p = [lone, rest[1], rest[0], rest[2]]
+            a, b, c, d = p
+            tri = [(a, b), (a, c), (a, d)]          # normal points away from a
+            if len(ins) == 3:                       # a is outside: flip
+                tri = [tri[0], tri[2], tri[1]]
+            table[case, 0] = tri
+            ntri[case] = 1
+        else:
+            p = ins + outs
+            if not _even(p):
+                p = [ins[0], ins[1], outs[1], outs[0]]
+            a, b, c, d = p
+            table[case, 0] = [(a, c), (a, d), (b, d)]
+            table[case, 1] = [(a, c), (b, d), (b, c)]
+            ntri[case] = 2
+    return table, ntri
+
+
+_TETS = _cell_tets()
+_CASES, _NTRI = _tet_case_table()
+
+
+def marching_tets(f, lo, hi, shape, chunk_cells: int = 1 << 21) -> Mesh:
+    """Level-0 surface of ``f`` sampled on a regular grid of ``shape`` points
+    spanning [lo, hi] (per axis).  Inside means f < 0; a sample equal to 0
+    counts as outside.  Vertices sit on crossed tet edges at the linear
+    interpolation of f and are welded by their grid-edge key, then numbered
+    in ascending key order (grid order, spatially local)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    nx, ny, nz = (int(s) for s in shape)
+    h = (hi - lo) / (np.array([nx, ny, nz], dtype=np.float64) - 1.0)
+    xs = lo[0] + h[0] * np.arange(nx)
+    ys = lo[1] + h[1] * np.arange(ny)
+    zs = lo[2] + h[2] * np.arange(nz)
+    # grid point (i,j,k) -> linear id i*ny*nz + j*nz + k
+    F = np.empty((nx, ny, nz), dtype=np.float64)
+    Y, Z = np.meshgrid(ys, zs, indexing="ij")
+    for i in range(nx):
+        F[i] = f(np.full_like(Y, xs[i]), Y, Z)
+    neg = F < 0
+    # cells with a sign change among their 8 corners
+    c = neg[:-1, :-1, :-1].astype(np.int8)
+    anyin = np.zeros((nx - 1, ny - 1, nz - 1), dtype=bool)
+    allin = np.ones((nx - 1, ny - 1, nz - 1), dtype=bool)
+    for dx in (0, 1):
+        for dy in (0, 1):
+            for dz in (0, 1):
+                s = neg[dx:nx - 1 + dx, dy:ny - 1 + dy, dz:nz - 1 + dz]
+                anyin |= s
+                allin &= s
+    del c
+    cells = np.flatnonzero(anyin & ~allin)
+    del anyin, allin
+    ci, rem = np.divmod(cells, (ny - 1) * (nz - 1))
+    cj, ck = np.divmod(rem, nz - 1)
+    base = ci * ny * nz + cj * nz + ck
+    corner_off = np.array([dx * ny * nz + dy * nz + dz
+                           for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)],
+                          dtype=np.int64)
+    # corner_off index = dx + 2dy + 4dz
+    Ff = F.ravel()
+    negf = neg.ravel()
+    keys_all = []
+    for s0 in range(0, base.size, chunk_cells):
+        b = base[s0:s0 + chunk_cells]
+        for t in range(6):
+            g = b[:, None] + corner_off[_TETS[t]][None, :]      # [n,4] grid ids
+            ins = negf[g]
+            case = ins[:, 0] * 1 + ins[:, 1] * 2 + ins[:, 2] * 4 + ins[:, 3] * 8
+            for k in (0, 1):
+                sel = _NTRI[case] > k
+                if not np.any(sel):
+                    continue
+                cs = case[sel]
+                gs = g[sel]
+                e = _CASES[cs, k]                                # [m,3,2]
+                ga = np.take_along_axis(gs, e[:, :, 0], axis=1)
+                gb = np.take_along_axis(gs, e[:, :, 1], axis=1)
+                kmin = np.minimum(ga, gb)
+                kmax = np.maximum(ga, gb)
+                keys_all.append(kmin * (nx * ny * nz) + kmax)    # [m,3]
+    keys = np.concatenate(keys_all, axis=0)
+    uk, inv = np.unique(keys.ravel(), return_inverse=True)
+    tri = inv.reshape(-1, 3).astype(np.int32)
+    npts = nx * ny * nz
+    ga = uk // npts
+    gb = uk % npts
+    fa = Ff[ga]
+    fb = Ff[gb]
+    t = fa / (fa - fb)
+
+    def coords(gid):
+        i, r = np.divmod(gid, ny * nz)
+        j, k = np.divmod(r, nz)
+        return np.stack([xs[i], ys[j], zs[k]], axis=1)
+    pa = coords(ga)
+    pb = coords(gb)
+    xyz = pa + t[:, None] * (pb - pa)
+    return Mesh(xyz.astype(np.float64), tri, 0, "mt")
+
+
+def jittered(m: Mesh, sigma: float, rng_seed: int, name: str = "") -> Mesh:
+    """N(0, sigma^2) coordinate noise, then a seed vertex, from one stream."""
+    rng = np.random.default_rng(rng_seed)
+    xyz = m.xyz + rng.normal(0.0, sigma, size=m.xyz.shape)
+    seed = int(rng.integers(m.nv))
+    return Mesh(xyz, m.tri, seed, name or m.name)
+
+
+def pick_seed(m: Mesh, rng_seed: int) -> Mesh:
+    rng = np.random.default_rng(rng_seed)
+    return Mesh(m.xyz, m.tri, int(rng.integers(m.nv)), m.name)
+
+
+def _fitted_grid(lo, hi, n, margin=2):
+    """Per-axis sample grid of n points covering [lo,hi] with ``margin``
+    empty cells on each side."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    n = np.asarray(n, dtype=np.int64)
+    h = (hi - lo) / (n - 1 - 2 * margin)
+    return lo - margin * h, hi + margin * h
+
+
+def sdf_surface(f, lo, hi, n, sigma=0.0, rng_seed=0, name="", margin=2):
+    if np.isscalar(n):
+        n = (n, n, n)
+    glo, ghi = _fitted_grid(lo, hi, n, margin)
+    m = marching_tets(f, glo, ghi, n)
+    return jittered(m, sigma, rng_seed, name)
+
+
+PRETZEL_CENTRES = ((-1.6, 0.0, 0.0), (0.0, 0.0, 0.0), (1.6, 0.0, 0.0))
+
+
+def pretzel_sdf(R=1.0, r=0.35):
+    return sdf_union_tori(PRETZEL_CENTRES, R, r)
+
+
+def multi_torus(g: int, n: int, R: float = 1.0, r: float = 0.35,
+                spacing: float = 1.6, sigma: float = 1e-4, rng_seed: int = 0) -> Mesh:
+    """Chain of ``g`` tori at ``spacing`` along x (genus g for g>=1 with
+    spacing < 2R), level-0 surface on an n^3 grid fitted per axis."""
+    cx = (np.arange(g) - (g - 1) / 2.0) * spacing
+    centres = [(float(x), 0.0, 0.0) for x in cx]
+    f = sdf_union_tori(centres, R, r)
+    lo = (cx[0] - R - r, -R - r, -r)
+    hi = (cx[-1] + R + r, R + r, r)
+    return sdf_surface(f, lo, hi, n, sigma, rng_seed, f"torus_chain{g}_{n}")
+
+
+def pretzel(n: int = 256, sigma: float = 1e-4, rng_seed: int = 0) -> Mesh:
+    """Genus-3 pretzel: level 0 of min over three tori SDFs (R=1, r=0.35,
+    centres x = -1.6, 0, 1.6), n samples per axis fitted to the bounding box
+    plus two cells, N(0, sigma^2) jitter, then a seed vertex."""
+    return multi_torus(3, n, 1.0, 0.35, 1.6, sigma, rng_seed)
