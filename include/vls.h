@@ -1,0 +1,205 @@
+/*
+ * vls.h -- C ABI of the MI355X library for the initial pass of the
+ * variational loop-shrinking method (Weinrauch, Seidel, Mlakar, Steinberger,
+ * Zayer, "A Variational Loop Shrinking Analogy for Handle and Tunnel
+ * Detection and Reeb Graph Construction on Surfaces", ACM TOG).
+ *
+ * Problem statement (Introduction; Section "Variational Loop Shrinking"):
+ * a closed orientable triangle mesh goes in; handle loops, tunnel loops and
+ * the Reeb graph swept by a diffusion front grown from one seed location
+ * come out.  Every computing step runs in HIP kernels on the GPU; the host
+ * side only validates the mesh, builds its adjacency, launches, and copies
+ * results back.
+ *
+ * Conventions
+ *   - Plain C, no exceptions cross the ABI.  Every call returns a
+ *     vls_status (0 = VLS_OK, negative = error); the context keeps a
+ *     human-readable detail for its last failure (vls_last_error).
+ *   - Inputs are copied at *_create; handles are opaque and owned by the
+ *     library until *_destroy.  Result arrays are caller-allocated and use a
+ *     two-call protocol: call with cap = 0 to get the size in *n_out, then
+ *     again with enough capacity; too small a capacity fails with
+ *     VLS_E_BUFFER_TOO_SMALL and still reports the size.
+ *   - Host pointers are marked (host); device pointers (device).
+ *   - Results depend only on (mesh, params): not on launch shape, stream or
+ *     other work on the device.  The field is computed in FP64 with a fixed
+ *     evaluation order (no contraction, IEEE sqrt), so it is reproducible
+ *     bit for bit.
+ *   - One context per host thread.
+ */
+#ifndef VLS_H
+#define VLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vls_status;
+enum {
+    VLS_OK = 0,
+    VLS_E_INVALID_ARG = -1,
+    VLS_E_MESH_NOT_MANIFOLD = -2,     /* a vertex link is not one cycle, or a degenerate triangle */
+    VLS_E_MESH_HAS_BOUNDARY = -3,     /* an edge lacks its opposite half-edge                    */
+    VLS_E_MESH_NOT_CONNECTED = -4,    /* more than one component, or an unused vertex            */
+    VLS_E_MESH_NOT_ORIENTABLE = -5,   /* a directed edge occurs twice                            */
+    VLS_E_SEED_INVALID = -6,          /* the initial region has swept genus != 0 or no boundary  */
+    VLS_E_STALLED = -7,               /* no insertion for stall_steps, or max_steps reached      */
+    VLS_E_OUT_OF_MEMORY = -8,
+    VLS_E_DEVICE = -9,                /* a HIP runtime call failed                               */
+    VLS_E_BUFFER_TOO_SMALL = -10,
+    VLS_E_CAPACITY = -11,             /* an internal device buffer bound was exceeded            */
+    VLS_E_TOO_LARGE = -12,            /* mesh beyond the 32-bit index range                      */
+    VLS_E_INVARIANT = -13             /* a topological invariant failed (see vls_last_error)     */
+};
+
+/* Reeb node types (Section "Initial Pass": branching and collision;
+   Section "Reeb Graph Extraction"). */
+enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANISH = 3,
+       VLS_NODE_DEGENERATE = 4 };
+
+/* flags */
+#define VLS_RECORD_FIELD 1u   /* keep FP64 snapshots of the field at ckpt_steps */
+
+/*
+ * Parameters.  Defaults (vls_params_default) are the paper's coefficients
+ * (Section "Mathematical representation and data structure", "Implementation
+ * details": e = 1/30, mu = 1/4, a = 1/25, w = a/5) and the readings of the
+ * points it leaves open: threshold tau = 0.5, time step dt = 50/dmax
+ * (dt_mode 0) or the literal 0.25/dmax (dt_mode 1), seed region = hop ball
+ * of radius 2 around seed_vertex.
+ */
+typedef struct vls_params {
+    uint32_t struct_size;      /* sizeof(vls_params)                                      */
+    int32_t dt_mode;           /* 0: dt = 50/dmax, 1: dt = 0.25/dmax                     */
+    double tau, mu, a, w, e;   /* threshold and equation coefficients                    */
+    int64_t seed_vertex;       /* >= 0: seed vertex id; < 0: chosen from rng_seed        */
+    uint64_t rng_seed;         /* seed_vertex = splitmix64(rng_seed) mod nv when < 0      */
+    int32_t seed_radius;       /* hop radius of the initial region (>= 0)                */
+    int32_t stall_steps;       /* VLS_E_STALLED after this many steps without insertion  */
+    int64_t max_steps;         /* VLS_E_STALLED when reached                              */
+    uint32_t flags;            /* VLS_RECORD_FIELD                                        */
+    int32_t n_ckpt;            /* number of entries in ckpt_steps                         */
+    const int64_t *ckpt_steps; /* (host) steps whose field is kept (with VLS_RECORD_FIELD) */
+    int32_t grid;              /* persistent workgroups; 0 = chosen by the library        */
+    int32_t block;             /* threads per workgroup: 256 (0 = default)                */
+} vls_params;
+
+struct vls_context;
+struct vls_mesh;
+struct vls_result;
+
+void vls_params_default(vls_params *p);
+const char *vls_status_string(vls_status s);
+/* detail text of the last failing call on ctx (never NULL; "" if none) */
+const char *vls_last_error(const struct vls_context *ctx);
+
+/* Context: binds a HIP device and a stream.  hip_stream is a hipStream_t
+   (e.g. PyTorch's current stream); NULL creates a private stream.  All
+   library work of this context is enqueued on that stream. */
+vls_status vls_context_create(int device, void *hip_stream, struct vls_context **out);
+vls_status vls_context_destroy(struct vls_context *ctx);
+
+/*
+ * Mesh setup (step S0: closed, connected, orientable 2-manifold; the paper
+ * precomputes the mesh operator once, Section "Mathematical representation
+ * and data structure", "Implementation details").
+ *   nv   number of vertices, xyz (host) [nv][3] FP64 positions
+ *   nf   number of triangles, tri (host) [nf][3] vertex ids, consistently
+ *        oriented (counter-clockwise seen from outside)
+ * Copies, validates, builds the adjacency (ascending and counter-clockwise
+ * vertex links, reverse and successor half-edge maps) and uploads it.
+ * Errors: VLS_E_MESH_* when the mesh is not a closed connected orientable
+ * manifold; VLS_E_TOO_LARGE when 3*nf >= 2^31.
+ */
+vls_status vls_mesh_create(struct vls_context *ctx, int64_t nv, const double *xyz,
+                           int64_t nf, const int32_t *tri, struct vls_mesh **out);
+/* ne = edges, dmax = maximum vertex degree, euler_genus = (2 - (V-E+F))/2 */
+vls_status vls_mesh_info(const struct vls_mesh *m, int64_t *nv, int64_t *ne, int64_t *nf,
+                         int32_t *dmax, int32_t *euler_genus);
+vls_status vls_mesh_destroy(struct vls_mesh *m);
+
+/*
+ * The initial pass (Section "Initial Pass"), blocking.  Runs the seed
+ * initialisation, then the persistent step kernel until every vertex is
+ * inside, then the Reeb-position and tunnel post-passes, and copies the
+ * results to host memory owned by *out.  A run that stalls still returns a
+ * result whose summary carries run_status = VLS_E_STALLED and the events
+ * recorded so far; the call then returns VLS_E_STALLED.
+ */
+vls_status vls_run(struct vls_context *ctx, const struct vls_mesh *m, const vls_params *p,
+                   struct vls_result **out);
+
+typedef struct {
+    int32_t n_handles;         /* handle loops emitted (merges: fronts involved minus one)   */
+    int32_t n_tunnels;         /* tunnel candidates, one per handle loop                      */
+    int32_t euler_genus;       /* (2 - chi(mesh))/2                                           */
+    int32_t swept_genus;       /* (2 - chi_t - b_t)/2 at the last step                        */
+    int32_t reeb_nodes, reeb_edges, n_degenerate;
+    int32_t n_events;
+    int64_t steps;             /* diffusion steps taken                                       */
+    int64_t active_vertex_updates;  /* sum over steps of the updated vertex count             */
+    int64_t active_degree_sum;      /* sum of the degrees of those updates                    */
+    int64_t n_inside;
+    int64_t seed_vertex;
+    vls_status run_status;
+    int32_t grid, block;       /* launch shape used                                           */
+    double kernel_ms;          /* device time of the persistent step kernel (HIP events)     */
+    double total_ms;           /* device time of the whole pass, seed to post-passes          */
+} vls_summary;
+vls_status vls_result_summary(const struct vls_result *r, vls_summary *s);
+
+/* Event log: one record of 16 int64 per saddle/vanish insertion, in rank
+   order: step, vertex, node type, k (lower arcs; 0 for vanish), s (fronts
+   involved), m (fronts after), h (handles), x (extra cycles), Reeb node
+   index, closure round, vanish flag, offset into the front-id list,
+   reserved[4].  The front-id list holds, per event, its s involved front
+   ids (ascending) followed by its m new front ids. */
+vls_status vls_result_events(const struct vls_result *r, int64_t cap, int64_t *rec,
+                             int64_t *n_out);
+vls_status vls_result_event_fronts(const struct vls_result *r, int64_t cap, int64_t *ids,
+                                   int64_t *n_out);
+
+/*
+ * Loops.  kind 0 = handle loop i: the ordered crossed edges
+ * (inside, outside) of the front just before the merge, starting at the
+ * smallest (inside*nv + outside) key (Section "Initial Pass": the involved
+ * fronts before the merge, the longest one ignored); pts = crossing points
+ * on those edges at the threshold, length = closed polyline length.
+ * kind 1 = tunnel candidate i (the streamline traced back against the
+ * diffusion, Introduction / Section "Tunnel loop pass"): a closed vertex
+ * cycle v, a_i, parent(a_i), ..., common ancestor, ..., a_0 written into
+ * edges_uv[*][0] (edges_uv[*][1] = next vertex); pts/length for its vertex
+ * polyline.  kind 2 = every involved loop of every merge (handle loops and
+ * the ignored longest one), in event order.
+ */
+vls_status vls_result_loop(const struct vls_result *r, int32_t kind, int32_t i, int64_t cap,
+                           int32_t *edges_uv, double *pts, double *length, int64_t *n_out);
+/* per-loop info for kind 0 or 2: event index, front id, kept (1 = handle loop) */
+vls_status vls_result_loop_info(const struct vls_result *r, int32_t kind, int32_t i,
+                                int64_t *event, int64_t *front_id, int32_t *kept);
+
+typedef struct { int32_t type, vertex, in_deg, out_deg, extra_cycles; int32_t pad; int64_t step; double xyz[3]; } vls_reeb_node;
+typedef struct { int32_t src, dst, front_id; } vls_reeb_edge;
+/* Reeb graph (Section "Reeb Graph Extraction"): node 0 is the seed, node
+   i+1 the i-th event; a node sits at the mean position of the distinct
+   vertices of the front triangles of the fronts involved; edge = front,
+   from its birth node to its death node (dst = -1 if still alive). */
+vls_status vls_result_reeb(const struct vls_result *r, int64_t cap_n, vls_reeb_node *nodes,
+                           int64_t cap_e, vls_reeb_edge *edges, int64_t *n_nodes, int64_t *n_edges);
+
+/* Field snapshot at step (one of ckpt_steps, with VLS_RECORD_FIELD), or the
+   final field for step < 0.  rho (host) [nv] FP64. */
+vls_status vls_result_field(const struct vls_result *r, int64_t step, double *rho);
+/* Per vertex: insertion step (INT32_MAX if never inside), closure round,
+   parent (streamline predecessor, -1 for the seed).  Any pointer may be NULL. */
+vls_status vls_result_vertices(const struct vls_result *r, int32_t *step, int32_t *round,
+                               int32_t *parent);
+vls_status vls_result_destroy(struct vls_result *r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLS_H */

@@ -1,0 +1,783 @@
+// vls_api.cpp -- host side of the C ABI declared in include/vls.h: mesh
+// validation and adjacency construction (step S0), device buffers, the run
+// sequence (init, seed, persistent step kernel, post-passes) and the result
+// objects.  All arithmetic of the method runs in the kernels of
+// vls_kernels.hip; this file only moves data and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "vls.h"
+#include "vls_internal.h"
+
+using namespace vls;
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct vls_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+};
+
+struct DeviceBuf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+struct RunBuffers;   // per-mesh cached device state
+
+struct vls_mesh {
+    vls_context *ctx = nullptr;
+    int64_t nv = 0, nf = 0, ne = 0, nnz = 0;
+    int32_t dmax = 0;
+    int32_t euler_genus = 0;
+    std::vector<double> xyz;             // host copy (for seed-node position)
+    DMesh d{};
+    std::vector<void *> allocs;
+    RunBuffers *rb = nullptr;
+};
+
+struct vls_result {
+    vls_summary sum{};
+    int64_t nv = 0;
+    std::vector<int64_t> ev;             // [n][16]
+    std::vector<int64_t> ev_ids;
+    std::vector<double> node_pos;        // [n_events][3]
+    std::vector<double> seed_xyz;        // [3]
+    std::vector<int32_t> front_birth, front_death;
+    std::vector<int64_t> lp;             // [n_loops][8]
+    std::vector<int32_t> lp_he;          // [*][2]
+    std::vector<double> lp_pts;          // [*][3]
+    std::vector<int32_t> tn;             // [n_tunnels][4]
+    std::vector<int64_t> tn_off;         // [n_tunnels+1]
+    std::vector<int32_t> tn_v;
+    std::vector<double> tn_len;          // [n_tunnels] vertex polyline lengths
+    std::vector<double> mesh_xyz;        // for tunnel polylines
+    std::vector<int32_t> step, round, parent;
+    std::vector<double> rho_final;
+    std::vector<int64_t> ckpt_steps;
+    std::vector<double> ckpt;            // [n_ckpt][nv]
+    std::vector<int32_t> ckpt_ok;
+};
+
+static vls_status set_err(vls_context *ctx, vls_status s, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return set_err(ctx, VLS_E_DEVICE, "%s failed: %s (%s:%d)", #call,                 \
+                           hipGetErrorString(e_), __FILE__, __LINE__);                         \
+    } while (0)
+
+extern "C" {
+
+void vls_params_default(vls_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(vls_params);
+    p->dt_mode = 0;
+    p->tau = 0.5;
+    p->mu = 0.25;
+    p->a = 1.0 / 25.0;
+    p->w = (1.0 / 25.0) / 5.0;
+    p->e = 1.0 / 30.0;
+    p->seed_vertex = 0;
+    p->rng_seed = 0;
+    p->seed_radius = 2;
+    p->stall_steps = 200000;
+    p->max_steps = 10000000;
+    p->flags = 0;
+    p->n_ckpt = 0;
+    p->ckpt_steps = nullptr;
+    p->grid = 0;
+    p->block = 256;
+}
+
+const char *vls_status_string(vls_status s) {
+    switch (s) {
+    case VLS_OK: return "VLS_OK";
+    case VLS_E_INVALID_ARG: return "VLS_E_INVALID_ARG";
+    case VLS_E_MESH_NOT_MANIFOLD: return "VLS_E_MESH_NOT_MANIFOLD";
+    case VLS_E_MESH_HAS_BOUNDARY: return "VLS_E_MESH_HAS_BOUNDARY";
+    case VLS_E_MESH_NOT_CONNECTED: return "VLS_E_MESH_NOT_CONNECTED";
+    case VLS_E_MESH_NOT_ORIENTABLE: return "VLS_E_MESH_NOT_ORIENTABLE";
+    case VLS_E_SEED_INVALID: return "VLS_E_SEED_INVALID";
+    case VLS_E_STALLED: return "VLS_E_STALLED";
+    case VLS_E_OUT_OF_MEMORY: return "VLS_E_OUT_OF_MEMORY";
+    case VLS_E_DEVICE: return "VLS_E_DEVICE";
+    case VLS_E_BUFFER_TOO_SMALL: return "VLS_E_BUFFER_TOO_SMALL";
+    case VLS_E_CAPACITY: return "VLS_E_CAPACITY";
+    case VLS_E_TOO_LARGE: return "VLS_E_TOO_LARGE";
+    case VLS_E_INVARIANT: return "VLS_E_INVARIANT";
+    default: return "VLS_E_UNKNOWN";
+    }
+}
+
+const char *vls_last_error(const vls_context *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+vls_status vls_context_create(int device, void *hip_stream, vls_context **out) {
+    if (!out) return VLS_E_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VLS_E_DEVICE;
+    auto *c = new (std::nothrow) vls_context;
+    if (!c) return VLS_E_OUT_OF_MEMORY;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete c; return VLS_E_DEVICE; }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return VLS_E_DEVICE; }
+        c->own_stream = true;
+    }
+    *out = c;
+    return VLS_OK;
+}
+
+vls_status vls_context_destroy(vls_context *ctx) {
+    if (!ctx) return VLS_E_INVALID_ARG;
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return VLS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// mesh validation and adjacency (S0)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct HostAdj {
+    std::vector<int32_t> rp, adj, cyc, src, rev, succ, nin;
+    int32_t dmax = 0;
+};
+
+// Builds the counter-clockwise links: triangle (a,b,c) contributes the link
+// edge b->c to a, c->a to b, a->b to c.  A closed oriented 2-manifold has,
+// at every vertex, link edges forming a single cycle.
+vls_status build_adjacency(vls_context *ctx, int64_t nv, int64_t nf, const int32_t *tri, HostAdj &h) {
+    for (int64_t i = 0; i < 3 * nf; ++i)
+        if (tri[i] < 0 || tri[i] >= nv)
+            return set_err(ctx, VLS_E_INVALID_ARG, "triangle %lld references vertex %d outside [0,%lld)",
+                           (long long)(i / 3), tri[i], (long long)nv);
+    std::vector<int64_t> cnt(nv + 1, 0);
+    for (int64_t i = 0; i < 3 * nf; ++i) cnt[tri[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) {
+        if (cnt[v + 1] == 0) return set_err(ctx, VLS_E_MESH_NOT_CONNECTED, "vertex %lld is in no triangle", (long long)v);
+        cnt[v + 1] += cnt[v];
+    }
+    const int64_t nnz = cnt[nv];
+    if (nnz >= (int64_t)1 << 31) return set_err(ctx, VLS_E_TOO_LARGE, "3*nf = %lld exceeds the 32-bit index range", (long long)nnz);
+    std::vector<int32_t> la(nnz), lb(nnz);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t a = tri[3 * f], b = tri[3 * f + 1], c = tri[3 * f + 2];
+        if (a == b || b == c || a == c)
+            return set_err(ctx, VLS_E_MESH_NOT_MANIFOLD, "triangle %lld repeats a vertex", (long long)f);
+        la[fill[a]] = b; lb[fill[a]++] = c;
+        la[fill[b]] = c; lb[fill[b]++] = a;
+        la[fill[c]] = a; lb[fill[c]++] = b;
+    }
+    h.rp.resize(nv + 1);
+    for (int64_t v = 0; v <= nv; ++v) h.rp[v] = (int32_t)cnt[v];
+    h.adj.resize(nnz); h.cyc.resize(nnz); h.src.resize(nnz);
+    h.rev.resize(nnz); h.succ.resize(nnz); h.nin.resize(nnz);
+    int32_t dmax = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t b = cnt[v], d = cnt[v + 1] - b;
+        if (d < 3) return set_err(ctx, VLS_E_MESH_NOT_MANIFOLD, "vertex %lld has degree %lld", (long long)v, (long long)d);
+        if (d > 64) return set_err(ctx, VLS_E_TOO_LARGE, "vertex %lld has degree %lld (limit 64)", (long long)v, (long long)d);
+        dmax = std::max<int32_t>(dmax, (int32_t)d);
+        // each link vertex must start exactly one link edge
+        for (int64_t i = 0; i < d; ++i)
+            for (int64_t j = i + 1; j < d; ++j)
+                if (la[b + i] == la[b + j]) {
+                    // the same directed edge v->la twice: two triangles with equal orientation,
+                    // or a non-manifold fan
+                    return set_err(ctx, VLS_E_MESH_NOT_ORIENTABLE,
+                                   "directed edge %lld->%d occurs twice", (long long)v, la[b + i]);
+                }
+        int32_t start = la[b];
+        for (int64_t i = 1; i < d; ++i) start = std::min(start, la[b + i]);
+        int32_t cur = start;
+        for (int64_t i = 0; i < d; ++i) {
+            h.cyc[b + i] = cur;
+            h.src[b + i] = (int32_t)v;
+            int64_t hit = -1;
+            for (int64_t j = 0; j < d; ++j)
+                if (la[b + j] == cur) { hit = j; break; }
+            if (hit < 0)
+                return set_err(ctx, VLS_E_MESH_HAS_BOUNDARY, "link of vertex %lld is open at %d", (long long)v, cur);
+            cur = lb[b + hit];
+        }
+        if (cur != start)
+            return set_err(ctx, VLS_E_MESH_NOT_MANIFOLD, "link of vertex %lld is not a single cycle", (long long)v);
+        for (int64_t i = 0; i < d; ++i) {
+            h.adj[b + i] = h.cyc[b + i];
+            h.succ[b + i] = (int32_t)(i + 1 == d ? b : b + i + 1);
+        }
+        std::sort(h.adj.begin() + b, h.adj.begin() + b + d);
+        for (int64_t i = 1; i < d; ++i)
+            if (h.adj[b + i] == h.adj[b + i - 1])
+                return set_err(ctx, VLS_E_MESH_NOT_MANIFOLD, "link of vertex %lld repeats vertex %d", (long long)v, h.adj[b + i]);
+    }
+    h.dmax = dmax;
+    // opposite half-edges, and the (y->x) successor
+    auto find = [&](int32_t u, int32_t x) -> int64_t {
+        for (int64_t j = cnt[u]; j < cnt[u + 1]; ++j)
+            if (h.cyc[j] == x) return j;
+        return -1;
+    };
+    for (int64_t v = 0; v < nv; ++v)
+        for (int64_t e = cnt[v]; e < cnt[v + 1]; ++e) {
+            const int32_t x = h.cyc[e];
+            const int64_t r = find(x, (int32_t)v);
+            if (r < 0) return set_err(ctx, VLS_E_MESH_HAS_BOUNDARY, "edge %lld-%d has one side only", (long long)v, x);
+            h.rev[e] = (int32_t)r;
+            const int32_t y = h.cyc[h.succ[e]];
+            const int64_t q = find(y, x);
+            if (q < 0) return set_err(ctx, VLS_E_MESH_NOT_MANIFOLD, "triangle (%lld,%d,%d) not closed", (long long)v, x, y);
+            h.nin[e] = (int32_t)q;
+        }
+    // connected
+    std::vector<int32_t> queue;
+    queue.reserve(nv);
+    std::vector<char> seen(nv, 0);
+    queue.push_back(0);
+    seen[0] = 1;
+    for (size_t qi = 0; qi < queue.size(); ++qi) {
+        const int32_t v = queue[qi];
+        for (int64_t e = cnt[v]; e < cnt[v + 1]; ++e)
+            if (!seen[h.cyc[e]]) { seen[h.cyc[e]] = 1; queue.push_back(h.cyc[e]); }
+    }
+    if ((int64_t)queue.size() != nv)
+        return set_err(ctx, VLS_E_MESH_NOT_CONNECTED, "mesh has %lld of %lld vertices in the first component",
+                       (long long)queue.size(), (long long)nv);
+    return VLS_OK;
+}
+
+template <typename T>
+vls_status upload(vls_mesh *m, const std::vector<T> &h, const T **out) {
+    void *p = nullptr;
+    const size_t bytes = h.size() * sizeof(T);
+    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) return set_err(m->ctx, VLS_E_OUT_OF_MEMORY, "hipMalloc %zu bytes", bytes);
+    m->allocs.push_back(p);
+    if (bytes && hipMemcpyAsync(p, h.data(), bytes, hipMemcpyHostToDevice, m->ctx->stream) != hipSuccess)
+        return set_err(m->ctx, VLS_E_DEVICE, "upload failed");
+    *out = (const T *)p;
+    return VLS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// per-mesh device run state (allocated at the first run, reused)
+// ---------------------------------------------------------------------------
+struct RunBuffers {
+    std::vector<void *> allocs;
+    DState s{};
+    int64_t ord_cap = 0;
+    int32_t n_ckpt_cap = 0;
+    ~RunBuffers() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+template <typename T>
+static hipError_t dalloc(RunBuffers *rb, T **p, size_t n) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T));
+    if (e == hipSuccess) rb->allocs.push_back(q);
+    *p = (T *)q;
+    return e;
+}
+
+static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
+    auto rb = std::make_unique<RunBuffers>();
+    DState &s = rb->s;
+    const size_t nv = (size_t)m->nv, nnz = (size_t)m->nnz;
+    size_t npow = 1;
+    while (npow < nv) npow <<= 1;
+    const int64_t g = std::max<int64_t>(0, m->euler_genus);
+    s.tag_cap = (int32_t)std::min<int64_t>((int64_t)nv + 4096, INT32_MAX);
+    s.front_cap = s.tag_cap;
+    s.ev_cap = (int32_t)std::min<int64_t>((int64_t)nv, (int64_t)1 << 22);
+    s.ev_ids_cap = 4 * (int64_t)s.ev_cap + 64;
+    s.lp_cap = (int32_t)(2 * g + 64);
+    s.lp_he_cap = 4 * (int64_t)nnz + (1 << 20);
+    hipError_t e = hipSuccess;
+#define A(ptr, n) if (e == hipSuccess) e = dalloc(rb.get(), &(ptr), (n))
+    A(s.rho0, nv); A(s.rho1, nv); A(s.key, nv); A(s.parent, nv); A(s.depth, nv);
+    A(s.lid, nnz); A(s.stamp, nv); A(s.cstamp, nv);
+    A(s.act[0], nv); A(s.act[1], nv); A(s.cand[0], nv); A(s.cand[1], nv);
+    A(s.pend[0], nv); A(s.pend[1], nv); A(s.L, nv); A(s.Lrnd, nv); A(s.Lcls, nv);
+    A(s.ord, npow);
+    A(s.tag_parent, (size_t)s.tag_cap); A(s.tag_fid, (size_t)s.tag_cap);
+    A(s.ev, (size_t)s.ev_cap * 16); A(s.ev_rep, (size_t)s.ev_cap * 16); A(s.ev_ids, (size_t)s.ev_ids_cap);
+    A(s.front_birth, (size_t)s.front_cap); A(s.front_death, (size_t)s.front_cap);
+    A(s.lp, (size_t)s.lp_cap * 8); A(s.lp_he, (size_t)s.lp_he_cap * 2); A(s.lp_pts, (size_t)s.lp_he_cap * 3);
+    A(s.tn, (size_t)s.lp_cap * 4);
+    A(s.ctl, 1);
+#undef A
+    if (e != hipSuccess) return set_err(m->ctx, VLS_E_OUT_OF_MEMORY, "device allocation failed: %s", hipGetErrorString(e));
+    rb->ord_cap = (int64_t)npow;
+    *out = rb.release();
+    return VLS_OK;
+}
+
+extern "C" {
+
+vls_status vls_mesh_create(vls_context *ctx, int64_t nv, const double *xyz, int64_t nf, const int32_t *tri,
+                           vls_mesh **out) {
+    if (!ctx || !out || !xyz || !tri || nv < 4 || nf < 4) return set_err(ctx, VLS_E_INVALID_ARG, "bad mesh arguments");
+    *out = nullptr;
+    if (nv >= INT32_MAX) return set_err(ctx, VLS_E_TOO_LARGE, "nv = %lld", (long long)nv);
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    HostAdj h;
+    vls_status st = build_adjacency(ctx, nv, nf, tri, h);
+    if (st) return st;
+    auto m = std::make_unique<vls_mesh>();
+    m->ctx = ctx;
+    m->nv = nv;
+    m->nf = nf;
+    m->nnz = (int64_t)h.cyc.size();
+    m->ne = m->nnz / 2;
+    m->dmax = h.dmax;
+    const int64_t chi = nv - m->ne + nf;
+    m->euler_genus = (int32_t)((2 - chi) / 2);
+    m->xyz.assign(xyz, xyz + 3 * nv);
+    DMesh &d = m->d;
+    d.nv = (int32_t)nv;
+    d.dmax = h.dmax;
+    d.nnz = m->nnz;
+    if ((st = upload(m.get(), h.rp, &d.rp)) || (st = upload(m.get(), h.adj, &d.adj)) ||
+        (st = upload(m.get(), h.cyc, &d.cyc)) || (st = upload(m.get(), h.src, &d.src)) ||
+        (st = upload(m.get(), h.rev, &d.rev)) || (st = upload(m.get(), h.succ, &d.succ)) ||
+        (st = upload(m.get(), h.nin, &d.nin)) || (st = upload(m.get(), m->xyz, &d.xyz))) {
+        for (void *p : m->allocs) (void)hipFree(p);
+        return st;
+    }
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        for (void *p : m->allocs) (void)hipFree(p);
+        return set_err(ctx, VLS_E_DEVICE, "mesh upload failed");
+    }
+    *out = m.release();
+    return VLS_OK;
+}
+
+vls_status vls_mesh_info(const vls_mesh *m, int64_t *nv, int64_t *ne, int64_t *nf, int32_t *dmax, int32_t *eg) {
+    if (!m) return VLS_E_INVALID_ARG;
+    if (nv) *nv = m->nv;
+    if (ne) *ne = m->ne;
+    if (nf) *nf = m->nf;
+    if (dmax) *dmax = m->dmax;
+    if (eg) *eg = m->euler_genus;
+    return VLS_OK;
+}
+
+vls_status vls_mesh_destroy(vls_mesh *m) {
+    if (!m) return VLS_E_INVALID_ARG;
+    (void)hipSetDevice(m->ctx->device);
+    delete m->rb;
+    for (void *p : m->allocs) (void)hipFree(p);
+    delete m;
+    return VLS_OK;
+}
+
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vls_result **out) {
+    if (!ctx || !mc || !p || !out) return set_err(ctx, VLS_E_INVALID_ARG, "null argument");
+    if (p->struct_size != sizeof(vls_params)) return set_err(ctx, VLS_E_INVALID_ARG, "vls_params.struct_size mismatch");
+    *out = nullptr;
+    vls_mesh *m = const_cast<vls_mesh *>(mc);
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    const int64_t nv = m->nv;
+    int64_t seed = p->seed_vertex;
+    if (seed < 0) seed = (int64_t)(splitmix64(p->rng_seed) % (uint64_t)nv);
+    if (seed >= nv) return set_err(ctx, VLS_E_INVALID_ARG, "seed vertex %lld >= nv", (long long)seed);
+    if (p->seed_radius < 0 || p->seed_radius > 1000) return set_err(ctx, VLS_E_INVALID_ARG, "seed_radius");
+    if (p->max_steps < 1 || p->max_steps >= INT32_MAX) return set_err(ctx, VLS_E_INVALID_ARG, "max_steps");
+    if (p->stall_steps < 1) return set_err(ctx, VLS_E_INVALID_ARG, "stall_steps");
+    const int block = p->block ? p->block : 256;
+    if (block != 256) return set_err(ctx, VLS_E_INVALID_ARG, "block must be 256");
+    const bool rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
+    if (!m->rb) {
+        vls_status st = make_run_buffers(m, &m->rb);
+        if (st) return st;
+    }
+    RunBuffers *rb = m->rb;
+    DState s = rb->s;
+    hipStream_t stream = ctx->stream;
+    // checkpoint buffers (per run)
+    std::vector<void *> tmp_allocs;
+    auto cleanup = [&]() { for (void *q : tmp_allocs) (void)hipFree(q); };
+    s.n_ckpt = 0;
+    s.ckpt = nullptr;
+    s.ckpt_steps = nullptr;
+    if (rec_field) {
+        void *a = nullptr, *b = nullptr;
+        if (hipMalloc(&a, (size_t)p->n_ckpt * nv * sizeof(double)) != hipSuccess ||
+            hipMalloc(&b, (size_t)p->n_ckpt * sizeof(int64_t)) != hipSuccess) {
+            if (a) (void)hipFree(a);
+            return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
+        }
+        tmp_allocs.push_back(a);
+        tmp_allocs.push_back(b);
+        s.ckpt = (double *)a;
+        s.ckpt_steps = (const int64_t *)b;
+        s.n_ckpt = p->n_ckpt;
+        HIPCHK(ctx, hipMemcpyAsync(b, p->ckpt_steps, (size_t)p->n_ckpt * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, hipMemsetAsync(a, 0xff, (size_t)p->n_ckpt * nv * sizeof(double), stream));
+    }
+    DParams dp{};
+    const double dt = p->dt_mode == 1 ? 0.25 / (double)m->dmax : 50.0 / (double)m->dmax;
+    dp.tau = p->tau;
+    dp.a = p->a;
+    dp.w = p->w;
+    dp.e = p->e;
+    dp.c = dt * (p->mu / 2.0);
+    dp.seed = seed;
+    dp.r0 = p->seed_radius;
+    dp.stall_steps = p->stall_steps;
+    dp.max_steps = p->max_steps;
+    // launch shape
+    const size_t lds = step_lds_bytes(block, m->dmax);
+    const int maxg = max_coresident_blocks(block, lds);
+    int grid = p->grid > 0 ? p->grid : 128;
+    if (maxg <= 0) { cleanup(); return set_err(ctx, VLS_E_DEVICE, "occupancy query failed"); }
+    if (grid > maxg) grid = maxg;
+    hipEvent_t e0, e1, e2, e3;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventCreate(&e2));
+    HIPCHK(ctx, hipEventCreate(&e3));
+    auto evdestroy = [&]() { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2); (void)hipEventDestroy(e3); };
+    HIPCHK(ctx, hipEventRecord(e0, stream));
+    HIPCHK(ctx, hipMemsetAsync(s.ctl, 0, sizeof(Ctl), stream));
+    HIPCHK(ctx, launch_init(m->d, s, m->nnz, stream));
+    HIPCHK(ctx, launch_seed(m->d, s, dp, stream));
+    HIPCHK(ctx, hipEventRecord(e1, stream));
+    hipError_t le = launch_steps(m->d, s, dp, grid, block, stream);
+    if (le != hipSuccess) { cleanup(); evdestroy(); return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le)); }
+    HIPCHK(ctx, hipEventRecord(e2, stream));
+    Ctl c{};
+    HIPCHK(ctx, hipMemcpyAsync(&c, s.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    // post-passes
+    const int nev = c.n_events, ntn = c.n_tunnels;
+    auto r = std::make_unique<vls_result>();
+    r->nv = nv;
+    std::vector<int64_t> cnt(std::max(nev, ntn) + 1, 0), off;
+    void *dcnt = nullptr, *doff = nullptr, *dbuf = nullptr, *dpos = nullptr, *dtn = nullptr;
+    auto dfree = [&]() { for (void *q : {dcnt, doff, dbuf, dpos, dtn}) if (q) (void)hipFree(q); };
+    if (nev > 0) {
+        HIPCHK(ctx, hipMalloc(&dcnt, (nev + 1) * sizeof(int64_t)));
+        HIPCHK(ctx, hipMalloc(&doff, (nev + 1) * sizeof(int64_t)));
+        HIPCHK(ctx, launch_reeb_count(m->d, s, nev, (int64_t *)dcnt, stream));
+        HIPCHK(ctx, hipMemcpyAsync(cnt.data(), dcnt, nev * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        off.assign(nev + 1, 0);
+        for (int i = 0; i < nev; ++i) {
+            int64_t np = 1;
+            while (np < cnt[i]) np <<= 1;
+            off[i + 1] = off[i] + np;
+        }
+        HIPCHK(ctx, hipMemcpyAsync(doff, off.data(), (nev + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, hipMalloc(&dbuf, off[nev] * sizeof(int32_t) + 16));
+        HIPCHK(ctx, hipMalloc(&dpos, nev * 3 * sizeof(double)));
+        HIPCHK(ctx, launch_reeb_fill(m->d, s, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dbuf, stream));
+        HIPCHK(ctx, launch_reeb_mean(m->d, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dbuf, (double *)dpos, stream));
+    }
+    void *dtcnt = nullptr, *dtoff = nullptr, *dtlen = nullptr;
+    std::vector<int64_t> tcnt(ntn + 1, 0);
+    if (ntn > 0) {
+        HIPCHK(ctx, hipMalloc(&dtcnt, (ntn + 1) * sizeof(int64_t)));
+        HIPCHK(ctx, hipMalloc(&dtoff, (ntn + 1) * sizeof(int64_t)));
+        HIPCHK(ctx, launch_tunnel_count(s, ntn, (int64_t *)dtcnt, stream));
+        HIPCHK(ctx, hipMemcpyAsync(tcnt.data(), dtcnt, ntn * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        r->tn_off.assign(ntn + 1, 0);
+        for (int i = 0; i < ntn; ++i) r->tn_off[i + 1] = r->tn_off[i] + tcnt[i];
+        HIPCHK(ctx, hipMemcpyAsync(dtoff, r->tn_off.data(), (ntn + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, hipMalloc(&dtn, r->tn_off[ntn] * sizeof(int32_t) + 16));
+        HIPCHK(ctx, hipMalloc(&dtlen, ntn * sizeof(double)));
+        HIPCHK(ctx, launch_tunnel_fill(m->d, s, ntn, (int64_t *)dtoff, (int32_t *)dtn, (double *)dtlen, stream));
+    }
+    HIPCHK(ctx, hipEventRecord(e3, stream));
+    // results to host
+    r->ev.resize((size_t)nev * 16);
+    r->ev_ids.resize((size_t)c.ev_ids_used);
+    r->node_pos.resize((size_t)nev * 3);
+    r->front_birth.resize(c.next_front);
+    r->front_death.resize(c.next_front);
+    r->lp.resize((size_t)c.n_loops * 8);
+    r->lp_he.resize((size_t)c.lp_he_used * 2);
+    r->lp_pts.resize((size_t)c.lp_he_used * 3);
+    r->tn.resize((size_t)ntn * 4);
+    r->tn_v.resize(ntn ? (size_t)r->tn_off[ntn] : 0);
+    std::vector<uint64_t> key(nv);
+    r->parent.resize(nv);
+    r->rho_final.resize(nv);
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream) : hipSuccess;
+    };
+    HIPCHK(ctx, cp(r->ev.data(), s.ev, r->ev.size() * 8));
+    HIPCHK(ctx, cp(r->ev_ids.data(), s.ev_ids, r->ev_ids.size() * 8));
+    if (nev) HIPCHK(ctx, cp(r->node_pos.data(), dpos, r->node_pos.size() * 8));
+    HIPCHK(ctx, cp(r->front_birth.data(), s.front_birth, r->front_birth.size() * 4));
+    HIPCHK(ctx, cp(r->front_death.data(), s.front_death, r->front_death.size() * 4));
+    HIPCHK(ctx, cp(r->lp.data(), s.lp, r->lp.size() * 8));
+    HIPCHK(ctx, cp(r->lp_he.data(), s.lp_he, r->lp_he.size() * 4));
+    HIPCHK(ctx, cp(r->lp_pts.data(), s.lp_pts, r->lp_pts.size() * 8));
+    HIPCHK(ctx, cp(r->tn.data(), s.tn, r->tn.size() * 4));
+    r->tn_len.resize(ntn);
+    if (ntn) HIPCHK(ctx, cp(r->tn_v.data(), dtn, r->tn_v.size() * 4));
+    if (ntn) HIPCHK(ctx, cp(r->tn_len.data(), dtlen, ntn * 8));
+    HIPCHK(ctx, cp(key.data(), s.key, nv * 8));
+    HIPCHK(ctx, cp(r->parent.data(), s.parent, nv * 4));
+    const int64_t fin = c.steps;
+    HIPCHK(ctx, cp(r->rho_final.data(), (fin & 1) ? s.rho1 : s.rho0, nv * 8));
+    if (rec_field) {
+        r->ckpt_steps.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
+        r->ckpt.resize((size_t)p->n_ckpt * nv);
+        HIPCHK(ctx, cp(r->ckpt.data(), s.ckpt, r->ckpt.size() * 8));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    float ms_k = 0.f, ms_t = 0.f;
+    (void)hipEventElapsedTime(&ms_k, e1, e2);
+    (void)hipEventElapsedTime(&ms_t, e0, e3);
+    evdestroy();
+    dfree();
+    if (dtcnt) (void)hipFree(dtcnt);
+    if (dtoff) (void)hipFree(dtoff);
+    if (dtlen) (void)hipFree(dtlen);
+    cleanup();
+    r->step.resize(nv);
+    r->round.resize(nv);
+    for (int64_t v = 0; v < nv; ++v) {
+        if (key[v] == KEY_OUT) { r->step[v] = INT32_MAX; r->round[v] = 0; }
+        else { r->step[v] = (int32_t)(key[v] >> 32); r->round[v] = (int32_t)(key[v] & 0xffffffffu); }
+    }
+    if (rec_field) {
+        r->ckpt_ok.assign(p->n_ckpt, 0);
+        for (int q = 0; q < p->n_ckpt; ++q) {
+            const int64_t st = p->ckpt_steps[q];
+            r->ckpt_ok[q] = st >= 1 && st <= fin;
+        }
+    }
+    r->seed_xyz.assign(m->xyz.begin() + 3 * seed, m->xyz.begin() + 3 * seed + 3);
+    r->mesh_xyz = m->xyz;
+    vls_summary &S = r->sum;
+    S.n_handles = (int32_t)c.gsum_h;
+    S.n_tunnels = ntn;
+    S.euler_genus = m->euler_genus;
+    S.swept_genus = (int32_t)((2 - c.chi - c.b) / 2);
+    S.reeb_nodes = nev + 1;
+    S.reeb_edges = c.next_front;
+    int32_t ndeg = 0;
+    for (int i = 0; i < nev; ++i) ndeg += r->ev[16 * (size_t)i + 2] == VLS_NODE_DEGENERATE;
+    S.n_degenerate = ndeg;
+    S.n_events = nev;
+    S.steps = c.steps;
+    S.active_vertex_updates = c.active_updates;
+    S.active_degree_sum = c.active_deg;
+    S.n_inside = c.n_inside;
+    S.seed_vertex = seed;
+    S.run_status = c.status;
+    S.grid = grid;
+    S.block = block;
+    S.kernel_ms = ms_k;
+    S.total_ms = ms_t;
+    vls_status rs = c.status;
+    if (rs == VLS_E_INVARIANT || rs == VLS_E_CAPACITY)
+        set_err(ctx, rs, "device reported %s (detail %d) at step %lld", vls_status_string(rs), c.err_code, (long long)c.steps);
+    else if (rs == VLS_E_STALLED)
+        set_err(ctx, rs, "front stalled at step %lld (%lld of %lld vertices inside)", (long long)c.steps,
+                (long long)c.n_inside, (long long)nv);
+    else if (rs == VLS_E_SEED_INVALID)
+        set_err(ctx, rs, "seed region around vertex %lld is not a disk-like region", (long long)seed);
+    *out = r.release();
+    return rs;
+}
+
+vls_status vls_result_summary(const vls_result *r, vls_summary *s) {
+    if (!r || !s) return VLS_E_INVALID_ARG;
+    *s = r->sum;
+    return VLS_OK;
+}
+
+vls_status vls_result_events(const vls_result *r, int64_t cap, int64_t *rec, int64_t *n_out) {
+    if (!r || !n_out) return VLS_E_INVALID_ARG;
+    const int64_t n = (int64_t)r->ev.size() / 16;
+    *n_out = n;
+    if (cap == 0) return VLS_OK;
+    if (cap < n || !rec) return VLS_E_BUFFER_TOO_SMALL;
+    std::memcpy(rec, r->ev.data(), r->ev.size() * 8);
+    return VLS_OK;
+}
+
+vls_status vls_result_event_fronts(const vls_result *r, int64_t cap, int64_t *ids, int64_t *n_out) {
+    if (!r || !n_out) return VLS_E_INVALID_ARG;
+    const int64_t n = (int64_t)r->ev_ids.size();
+    *n_out = n;
+    if (cap == 0) return VLS_OK;
+    if (cap < n || !ids) return VLS_E_BUFFER_TOO_SMALL;
+    std::memcpy(ids, r->ev_ids.data(), n * 8);
+    return VLS_OK;
+}
+
+static bool loop_index(const vls_result *r, int32_t kind, int32_t i, int64_t *li) {
+    const int64_t nl = (int64_t)r->lp.size() / 8;
+    if (kind == 2) {
+        if (i < 0 || i >= nl) return false;
+        *li = i;
+        return true;
+    }
+    int64_t c = 0;
+    for (int64_t q = 0; q < nl; ++q)
+        if (r->lp[8 * q + 2]) {
+            if (c == i) { *li = q; return true; }
+            c++;
+        }
+    return false;
+}
+
+vls_status vls_result_loop(const vls_result *r, int32_t kind, int32_t i, int64_t cap, int32_t *edges_uv,
+                           double *pts, double *length, int64_t *n_out) {
+    if (!r || !n_out) return VLS_E_INVALID_ARG;
+    if (kind == 0 || kind == 2) {
+        int64_t li;
+        if (!loop_index(r, kind, i, &li)) return VLS_E_INVALID_ARG;
+        const int64_t off = r->lp[8 * li + 3], n = r->lp[8 * li + 4];
+        *n_out = n;
+        if (length) { double L; int64_t bits = r->lp[8 * li + 6]; std::memcpy(&L, &bits, 8); *length = L; }
+        if (cap == 0) return VLS_OK;
+        if (cap < n) return VLS_E_BUFFER_TOO_SMALL;
+        if (edges_uv) std::memcpy(edges_uv, r->lp_he.data() + 2 * off, n * 2 * sizeof(int32_t));
+        if (pts) std::memcpy(pts, r->lp_pts.data() + 3 * off, n * 3 * sizeof(double));
+        return VLS_OK;
+    }
+    if (kind == 1) {
+        const int64_t nt = (int64_t)r->tn.size() / 4;
+        if (i < 0 || i >= nt) return VLS_E_INVALID_ARG;
+        const int64_t off = r->tn_off[i], n = r->tn_off[i + 1] - off;
+        *n_out = n;
+        if (length) *length = r->tn_len[i];
+        if (cap == 0) return VLS_OK;
+        if (cap < n) return VLS_E_BUFFER_TOO_SMALL;
+        for (int64_t q = 0; q < n; ++q) {
+            const int32_t a = r->tn_v[off + q], b = r->tn_v[off + (q + 1) % n];
+            if (edges_uv) { edges_uv[2 * q] = a; edges_uv[2 * q + 1] = b; }
+            if (pts) std::memcpy(pts + 3 * q, r->mesh_xyz.data() + 3 * (int64_t)a, 3 * sizeof(double));
+        }
+        return VLS_OK;
+    }
+    return VLS_E_INVALID_ARG;
+}
+
+vls_status vls_result_loop_info(const vls_result *r, int32_t kind, int32_t i, int64_t *event, int64_t *front_id,
+                                int32_t *kept) {
+    if (!r || (kind != 0 && kind != 2)) return VLS_E_INVALID_ARG;
+    int64_t li;
+    if (!loop_index(r, kind, i, &li)) return VLS_E_INVALID_ARG;
+    if (event) *event = r->lp[8 * li];
+    if (front_id) *front_id = r->lp[8 * li + 1];
+    if (kept) *kept = (int32_t)r->lp[8 * li + 2];
+    return VLS_OK;
+}
+
+vls_status vls_result_reeb(const vls_result *r, int64_t cap_n, vls_reeb_node *nodes, int64_t cap_e,
+                           vls_reeb_edge *edges, int64_t *n_nodes, int64_t *n_edges) {
+    if (!r || !n_nodes || !n_edges) return VLS_E_INVALID_ARG;
+    const int64_t nev = (int64_t)r->ev.size() / 16;
+    const int64_t nn = nev + 1, ne = (int64_t)r->front_birth.size();
+    *n_nodes = nn;
+    *n_edges = ne;
+    if (cap_n == 0 && cap_e == 0) return VLS_OK;
+    if (cap_n < nn || cap_e < ne || !nodes || !edges) return VLS_E_BUFFER_TOO_SMALL;
+    int32_t b0 = 0;
+    for (int64_t f = 0; f < ne; ++f) b0 += r->front_birth[f] == 0;
+    vls_reeb_node &s0 = nodes[0];
+    std::memset(&s0, 0, sizeof s0);
+    s0.type = VLS_NODE_SEED;
+    s0.vertex = (int32_t)r->sum.seed_vertex;
+    s0.in_deg = 0;
+    s0.out_deg = b0;
+    s0.step = 0;
+    std::memcpy(s0.xyz, r->seed_xyz.data(), 3 * sizeof(double));
+    for (int64_t i = 0; i < nev; ++i) {
+        const int64_t *e = r->ev.data() + 16 * i;
+        vls_reeb_node &n = nodes[i + 1];
+        std::memset(&n, 0, sizeof n);
+        n.type = (int32_t)e[2];
+        n.vertex = (int32_t)e[1];
+        n.in_deg = (int32_t)e[4];
+        n.out_deg = (int32_t)e[5];
+        n.extra_cycles = (int32_t)e[7];
+        n.step = e[0];
+        std::memcpy(n.xyz, r->node_pos.data() + 3 * i, 3 * sizeof(double));
+    }
+    for (int64_t f = 0; f < ne; ++f) {
+        edges[f].src = r->front_birth[f];
+        edges[f].dst = r->front_death[f];
+        edges[f].front_id = (int32_t)f;
+    }
+    return VLS_OK;
+}
+
+vls_status vls_result_field(const vls_result *r, int64_t step, double *rho) {
+    if (!r || !rho) return VLS_E_INVALID_ARG;
+    if (step < 0) {
+        std::memcpy(rho, r->rho_final.data(), r->nv * sizeof(double));
+        return VLS_OK;
+    }
+    for (size_t q = 0; q < r->ckpt_steps.size(); ++q)
+        if (r->ckpt_steps[q] == step && r->ckpt_ok[q]) {
+            std::memcpy(rho, r->ckpt.data() + q * r->nv, r->nv * sizeof(double));
+            return VLS_OK;
+        }
+    return VLS_E_INVALID_ARG;
+}
+
+vls_status vls_result_vertices(const vls_result *r, int32_t *step, int32_t *round, int32_t *parent) {
+    if (!r) return VLS_E_INVALID_ARG;
+    if (step) std::memcpy(step, r->step.data(), r->nv * sizeof(int32_t));
+    if (round) std::memcpy(round, r->round.data(), r->nv * sizeof(int32_t));
+    if (parent) std::memcpy(parent, r->parent.data(), r->nv * sizeof(int32_t));
+    return VLS_OK;
+}
+
+vls_status vls_result_destroy(vls_result *r) {
+    if (!r) return VLS_E_INVALID_ARG;
+    delete r;
+    return VLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// vls_internal.h -- device-side data layout shared by the host part of the
+// library (vls_api.cpp) and its HIP kernels (vls_kernels.hip).  Not part of
+// the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vls {
+
+// ---------------------------------------------------------------------------
+// Mesh in HBM.  Half-edges are stored per owner vertex in counter-clockwise
+// link order (triangles (u, cyc[e], cyc[succ[e]]) are the mesh triangles
+// around u); the ascending neighbour list adj[] is kept separately because
+// the field sum runs over ascending neighbour ids.
+// ---------------------------------------------------------------------------
+struct DMesh {
+    int32_t nv;
+    int32_t dmax;
+    int64_t nnz;
+    const int32_t *rp;    // [nv+1] row offsets (both layouts share them)
+    const int32_t *adj;   // [nnz]  neighbours, ascending id
+    const int32_t *cyc;   // [nnz]  neighbours, counter-clockwise from the smallest id
+    const int32_t *src;   // [nnz]  owner vertex of half-edge e
+    const int32_t *rev;   // [nnz]  index of the opposite half-edge
+    const int32_t *succ;  // [nnz]  next half-edge of the same owner (ccw, wrapping)
+    const int32_t *nin;   // [nnz]  e=(u->x), y=cyc[succ[e]]: index of half-edge (y->x)
+    const double *xyz;    // [nv][3]
+};
+
+constexpr uint64_t KEY_OUT = ~0ull;   // rank key of a vertex not yet inside
+
+// control block (device memory), zeroed by the host before a run
+struct Ctl {
+    unsigned long long bar;  // grid barrier arrivals (monotonic)
+    int32_t stop[2];         // per-iteration exit decision, slot j&1
+    int32_t done;
+    int32_t status;
+    int32_t err_code;        // detail for VLS_E_INVARIANT / VLS_E_CAPACITY
+    int32_t cnt_act[4];      // update-list counts, slot t&3 for step t
+    int32_t cnt_cand[4];     // crosser-candidate counts, slot t&3 for step t
+    int32_t cnt_pend[2];     // pending crossers, slot t&1
+    int32_t n_events;
+    int32_t next_front;
+    int32_t n_tags;
+    int32_t n_loops;
+    int32_t n_tunnels;
+    int32_t pad0;
+    int64_t steps;
+    int64_t n_inside;
+    int64_t last_insert;
+    int64_t active_updates;
+    int64_t active_deg;
+    int64_t lp_he_used;
+    int64_t ev_ids_used;
+    int64_t chi;
+    int64_t b;
+    int64_t gsum_h;
+    int64_t gsum_x;
+    int64_t event_steps;     // steps that needed the sequential event path
+};
+
+// run state in HBM
+struct DState {
+    double *rho0, *rho1;     // field double buffer: step t lives in rho[t&1]
+    uint64_t *key;           // [nv] (step << 32) | round, KEY_OUT if outside
+    int32_t *parent;         // [nv]
+    int32_t *depth;          // [nv]
+    int32_t *lid;            // [nnz] front tag of a crossed half-edge (inside -> outside)
+    int32_t *stamp;          // [nv] update-list claims (step number)
+    int32_t *cstamp;         // [nv] candidate de-duplication (step number)
+    int32_t *act[2];         // [nv] update lists (step parity)
+    int32_t *cand[2];        // [nv] crosser candidates (step parity)
+    int32_t *pend[2];        // [nv] crossers not yet connected
+    int32_t *L;              // [nv] topology-phase list
+    int32_t *Lrnd;           // [nv] closure round per entry (-1: not connected)
+    int32_t *Lcls;           // [nv] lower arcs per entry (-1: full link)
+    uint64_t *ord;           // [nv] rank-sort scratch
+    int32_t *tag_parent;     // [tag_cap] union-find over front tags
+    int32_t *tag_fid;        // [tag_cap] front id of a root tag
+    int32_t tag_cap;
+    int32_t ev_cap;
+    int64_t *ev;             // [ev_cap][16] event records
+    int32_t *ev_rep;         // [ev_cap][16] one lower-run position per involved front
+    int64_t *ev_ids;         // [ev_ids_cap] involved / new front ids
+    int64_t ev_ids_cap;
+    int32_t *front_birth;    // [front_cap]
+    int32_t *front_death;    // [front_cap]
+    int32_t front_cap;
+    int32_t lp_cap;
+    int64_t *lp;             // [lp_cap][8]: event, front id, kept, off, count, a-vertex, len bits, pad
+    int32_t *lp_he;          // [lp_he_cap][2]
+    double *lp_pts;          // [lp_he_cap][3]
+    int64_t lp_he_cap;
+    int32_t *tn;             // [lp_cap][4]: loop index, v, a_j, a_0
+    double *ckpt;            // [n_ckpt][nv]
+    const int64_t *ckpt_steps;  // (device) [n_ckpt]
+    int32_t n_ckpt;
+    int32_t pad1;
+    Ctl *ctl;
+};
+
+struct DParams {
+    double tau, a, w, e, c;  // c = dt * mu / 2
+    int64_t seed;
+    int32_t r0;
+    int32_t stall_steps;
+    int64_t max_steps;
+};
+
+// host launchers (vls_kernels.hip)
+hipError_t launch_init(const DMesh &m, const DState &s, int64_t nnz, hipStream_t st);
+hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
+hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int grid, int block,
+                        hipStream_t st);
+int max_coresident_blocks(int block, size_t lds_bytes);
+size_t step_lds_bytes(int block, int dmax);
+hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt,
+                             hipStream_t st);
+hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int n_events, const int64_t *off,
+                            const int64_t *cnt, int32_t *buf, hipStream_t st);
+hipError_t launch_reeb_mean(const DMesh &m, int n_events, const int64_t *off, const int64_t *cnt,
+                            int32_t *buf, double *pos, hipStream_t st);
+hipError_t launch_tunnel_count(const DState &s, int n_tunnels, int64_t *cnt, hipStream_t st);
+hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int n_tunnels, const int64_t *off, int32_t *out,
+                              double *len, hipStream_t st);
+
+}  // namespace vls

@@ -1,0 +1,1198 @@
+// vls_kernels.hip -- HIP kernels (gfx950) for the initial pass of the
+// variational loop-shrinking method.
+//
+// One persistent cooperative kernel advances the diffusion front step by
+// step with a single grid barrier per step:
+//   * workgroups 1..G-1 run the field phase of step t+1 over the update list
+//     (explicit Euler step of the two-phase diffuse-interface equation with
+//     the clip that the column normalisation reduces to; Section
+//     "Mathematical representation and data structure"), grow the next
+//     update list and collect threshold-crossing candidates;
+//   * workgroup 0 runs the topology phase of step t: closure rounds that
+//     grow the inside set through adjacency, lower-link classification of
+//     each inserted vertex, the front-tag update of regular insertions, and
+//     for saddle / vanish insertions the event resolution (branching and
+//     collision, Section "Initial Pass"; front labelling over crossed edges,
+//     Section "Performance Considerations").
+// The field never depends on the fronts (one dense field plus integer front
+// bookkeeping), so step t's topology and step t+1's field run concurrently.
+//
+// Post-passes compute Reeb node positions (mean of the involved band,
+// Section "Reeb Graph Extraction") and tunnel candidates (streamline traced
+// back against the diffusion, Introduction).
+//
+// Floating point: FP64, evaluated exactly as written (built with
+// -ffp-contract=off), neighbour sums in ascending neighbour id.
+#include <climits>
+
+#include "vls_internal.h"
+
+namespace vls {
+
+#define NT 256               // threads per workgroup (4 wave64)
+#define WAVE 64
+#define SORTCAP 2048         // N_t entries sorted in LDS
+#define MAXDEG 64            // vertex degree bound of the event path (one lane per link position)
+
+enum { NODE_SEED = 0, NODE_SPLIT = 1, NODE_MERGE = 2, NODE_VANISH = 3, NODE_DEGENERATE = 4 };
+enum { ST_OK = 0, ST_SEED_INVALID = -6, ST_STALLED = -7, ST_CAPACITY = -11, ST_INVARIANT = -13 };
+
+__device__ __forceinline__ bool rank_lt(uint64_t ka, int32_t a, uint64_t kb, int32_t b) {
+    return ka < kb || (ka == kb && a < b);
+}
+
+__device__ __forceinline__ int ld_relaxed(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier over all co-resident workgroups: monotonic arrival counter.
+__device__ __forceinline__ void grid_sync(Ctl *ctl, unsigned long long G, unsigned long long &epoch) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        epoch += 1;
+        const unsigned long long target = epoch * G;
+        __threadfence();
+        atomicAdd(&ctl->bar, 1ull);
+        while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+            __builtin_amdgcn_s_sleep(1);
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void fail(const DState &s, int code, int detail) {
+    if (atomicCAS(&s.ctl->status, 0, code) == 0) s.ctl->err_code = detail;
+    __hip_atomic_store(&s.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// successor of crossed half-edge e=(u->x) along its loop, in the state where
+// the inside set is {y : rank(y) < rank(v)} (plus v itself when post): the
+// triangle (u, x, y) holding directed edge u->x has one more crossed edge,
+// (y,x) if y is inside, else (u,y).
+__device__ __forceinline__ int32_t he_next(const DMesh &m, const uint64_t *__restrict__ key,
+                                           int32_t e, uint64_t kv, int32_t v, bool post) {
+    const int32_t j = m.succ[e];
+    const int32_t y = m.cyc[j];
+    const uint64_t ky = key[y];
+    const bool in = rank_lt(ky, y, kv, v) || (post && y == v);
+    return in ? m.nin[e] : j;
+}
+
+// ---------------------------------------------------------------------------
+// initialisation of a run
+// ---------------------------------------------------------------------------
+__global__ void k_init(DState s, int32_t nv, int64_t nnz) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride) {
+        s.lid[i] = -1;
+        if (i < nv) {
+            s.rho0[i] = 0.0;
+            s.rho1[i] = 0.0;
+            s.key[i] = KEY_OUT;
+            s.parent[i] = -1;
+            s.depth[i] = 0;
+            s.stamp[i] = 0;
+            s.cstamp[i] = -1;
+        }
+    }
+}
+
+hipError_t launch_init(const DMesh &m, const DState &s, int64_t nnz, hipStream_t st) {
+    int blocks = (int)((nnz + NT - 1) / NT);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(NT), 0, st, s, m.nv, nnz);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// seed: hop ball B(s, r0) inside, field 1 on B; the update list of step 1 is
+// every vertex within r0+2 hops; initial loops numbered by their smallest
+// crossed half-edge key (inside*nv + outside)
+// ---------------------------------------------------------------------------
+struct SeedSh {
+    int n;           // vertices listed so far
+    int layer_beg, layer_end;
+    int add;
+    int nball;
+    unsigned long long ne, nf;
+    int nloops;
+    int bad;
+};
+
+__global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
+    __shared__ SeedSh sh;
+    __shared__ long long loopkey[64];
+    __shared__ int loopstart[64];
+    const int tid = threadIdx.x;
+    int32_t *list = s.L;       // BFS order, hop in Lrnd
+    if (tid == 0) {
+        sh.n = 1; sh.layer_beg = 0; sh.layer_end = 1; sh.nball = 0; sh.ne = 0; sh.nf = 0;
+        sh.nloops = 0; sh.bad = 0;
+        list[0] = (int32_t)p.seed;
+        s.Lrnd[0] = 0;
+        s.cstamp[p.seed] = -2;
+    }
+    __syncthreads();
+    for (int h = 1; h <= p.r0 + 2; ++h) {
+        const int beg = sh.layer_beg, end = sh.layer_end;
+        for (int i = beg + tid; i < end; i += NT) {
+            const int32_t v = list[i];
+            for (int32_t j = m.rp[v]; j < m.rp[v + 1]; ++j) {
+                const int32_t u = m.adj[j];
+                if (atomicCAS(&s.cstamp[u], -1, -2) == -1) {
+                    const int slot = atomicAdd(&sh.n, 1);
+                    list[slot] = u;
+                    s.Lrnd[slot] = h;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) { sh.layer_beg = end; sh.layer_end = sh.n; }
+        __syncthreads();
+    }
+    const int ntot = sh.n;
+    // ball membership, field, update list of step 1 (stamp 1)
+    int myball = 0;
+    for (int i = tid; i < ntot; i += NT) {
+        const int32_t v = list[i];
+        const int h = s.Lrnd[i];
+        if (h <= p.r0) {
+            s.key[v] = (uint64_t)h;      // step 0, round = hop
+            s.rho0[v] = 1.0;
+            s.rho1[v] = 1.0;
+            myball++;
+        }
+        s.act[1][i] = v;
+        s.stamp[v] = 1;
+    }
+    atomicAdd(&sh.nball, myball);
+    __syncthreads();
+    // parent = minimum-rank lower neighbour; depth = hop (the parent is one hop closer)
+    long long my_ne = 0, my_nf = 0;
+    for (int i = tid; i < ntot; i += NT) {
+        const int32_t v = list[i];
+        const int h = s.Lrnd[i];
+        if (h > p.r0) continue;
+        const uint64_t kv = s.key[v];
+        int32_t par = -1;
+        uint64_t kp = KEY_OUT;
+        for (int32_t j = m.rp[v]; j < m.rp[v + 1]; ++j) {
+            const int32_t u = m.cyc[j];
+            const uint64_t ku = s.key[u];
+            const int32_t y = m.cyc[m.succ[j]];
+            const uint64_t ky = s.key[y];
+            if (ku != KEY_OUT && rank_lt(ku, u, kv, v) && (par < 0 || rank_lt(ku, u, kp, par))) { par = u; kp = ku; }
+            if (ku != KEY_OUT && u > v) my_ne++;
+            if (ku != KEY_OUT && ky != KEY_OUT && v < u && v < y) my_nf++;
+        }
+        s.parent[v] = par;
+        s.depth[v] = h;
+    }
+    atomicAdd(&sh.ne, (unsigned long long)my_ne);
+    atomicAdd(&sh.nf, (unsigned long long)my_nf);
+    __syncthreads();
+    // initial loops: walked by thread 0 (the ball boundary is short)
+    if (tid == 0) {
+        const int64_t nvv = m.nv;
+        int nl = 0;
+        for (int i = 0; i < ntot && !sh.bad; ++i) {
+            const int32_t v = list[i];
+            if (s.Lrnd[i] > p.r0) continue;
+            for (int32_t j = m.rp[v]; j < m.rp[v + 1]; ++j) {
+                if (s.key[m.cyc[j]] != KEY_OUT || s.lid[j] >= 0) continue;
+                if (nl == 64) { sh.bad = 2; break; }
+                int32_t e = j;
+                long long best = LLONG_MAX;
+                int64_t guard = 0;
+                do {
+                    s.lid[e] = nl;
+                    const long long k = (long long)m.src[e] * nvv + m.cyc[e];
+                    if (k < best) best = k;
+                    // inside = step-0 key (not KEY_OUT); v = -1 never matches
+                    const int32_t jj = m.succ[e];
+                    const int32_t y = m.cyc[jj];
+                    e = s.key[y] != KEY_OUT ? m.nin[e] : jj;
+                    if (++guard > m.nnz) { sh.bad = 3; break; }
+                } while (e != j);
+                loopkey[nl] = best;
+                loopstart[nl] = j;
+                nl++;
+            }
+        }
+        // order loops by their smallest key; rank[i] = front id of walk i
+        int rank[64];
+        for (int i = 0; i < nl; ++i) {
+            int r = 0;
+            for (int q = 0; q < nl; ++q) if (loopkey[q] < loopkey[i]) r++;
+            rank[i] = r;
+        }
+        for (int i = 0; i < nl && !sh.bad; ++i) {
+            int32_t e = loopstart[i];
+            do {
+                s.lid[e] = rank[i];
+                const int32_t jj = m.succ[e];
+                e = s.key[m.cyc[jj]] != KEY_OUT ? m.nin[e] : jj;
+            } while (e != loopstart[i]);
+            s.tag_parent[i] = i;
+            s.tag_fid[i] = i;
+            s.front_birth[i] = 0;
+            s.front_death[i] = -1;
+        }
+        sh.nloops = nl;
+        Ctl *c = s.ctl;
+        const long long chi = (long long)sh.nball - (long long)sh.ne + (long long)sh.nf;
+        c->chi = chi;
+        c->b = nl;
+        c->n_inside = sh.nball;
+        c->next_front = nl;
+        c->n_tags = nl;
+        c->cnt_act[1] = ntot;
+        c->last_insert = 0;
+        if (sh.bad == 2) { c->status = ST_CAPACITY; c->err_code = 1; c->done = 1; }
+        else if (sh.bad) { c->status = ST_INVARIANT; c->err_code = 2; c->done = 1; }
+        else if (nl < 1 || 2 - chi - nl != 0) { c->status = ST_SEED_INVALID; c->done = 1; }
+        else if (sh.nball == nvv) { c->done = 1; }
+    }
+}
+
+hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStream_t st) {
+    hipLaunchKernelGGL(k_seed, dim3(1), dim3(NT), 0, st, m, s, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// field phase of step t: rho_t from rho_{t-1} over the update list C_t
+// ---------------------------------------------------------------------------
+__device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+                            int worker, int nworkers, int32_t *lds_claims, int *lds_cnt,
+                            int *lds_base) {
+    Ctl *ctl = s.ctl;
+    const int n = ld_relaxed(&ctl->cnt_act[t & 3]);
+    const int32_t *__restrict__ list = s.act[t & 1];
+    int32_t *__restrict__ out = s.act[(t + 1) & 1];
+    int *outcnt = &ctl->cnt_act[(t + 1) & 3];
+    const double *__restrict__ rin = ((t - 1) & 1) ? s.rho1 : s.rho0;
+    double *__restrict__ rout = (t & 1) ? s.rho1 : s.rho0;
+    int32_t *__restrict__ cl = s.cand[t & 1];
+    int *clc = &ctl->cnt_cand[t & 3];
+    const int32_t next = (int32_t)(t + 1);
+    const int per = (n + nworkers - 1) / nworkers;
+    const int beg = worker * per;
+    const int end = min(n, beg + per);
+    const int lane = __lane_id();
+    long long upd = 0, degsum = 0;
+    for (int base = beg; base < end; base += NT) {
+        if (threadIdx.x == 0) *lds_cnt = 0;
+        __syncthreads();
+        const int i = base + threadIdx.x;
+        bool cand = false;
+        int32_t v = -1;
+        if (i < end) {
+            v = list[i];
+            const int32_t b = m.rp[v], e = m.rp[v + 1];
+            const double r = rin[v];
+            double x0 = rin[m.adj[b]];
+            double sum = x0;
+            bool quiet = (r == 0.0 || r == 1.0) && x0 == r;
+            for (int32_t j = b + 1; j < e; ++j) {
+                const double xn = rin[m.adj[j]];
+                sum = sum + xn;
+                quiet = quiet && xn == r;
+            }
+            const double lap = sum - (double)(e - b) * r;
+            const double d = (p.a * lap + p.w * (2.0 * r - 1.0)) + p.e * sqrt(r * (1.0 - r));
+            double x = r + p.c * d;
+            if (x < 0.0) x = 0.0;
+            if (x > 1.0) x = 1.0;
+            rout[v] = x;
+            upd += 1;
+            degsum += e - b;
+            if (!quiet) {
+                // v is not a fixed point at step t-1: v and its ring may change
+                // at step t+1
+                if (s.stamp[v] != next && atomicExch(&s.stamp[v], next) != next)
+                    lds_claims[atomicAdd(lds_cnt, 1)] = v;
+                for (int32_t j = b; j < e; ++j) {
+                    const int32_t u = m.adj[j];
+                    if (s.stamp[u] != next && atomicExch(&s.stamp[u], next) != next)
+                        lds_claims[atomicAdd(lds_cnt, 1)] = u;
+                }
+            }
+            cand = x > p.tau && s.key[v] == KEY_OUT;
+        }
+        const unsigned long long mask = __ballot(cand);
+        if (mask) {
+            int cb = 0;
+            const int leader = __ffsll((long long)mask) - 1;
+            if (lane == leader) cb = atomicAdd(clc, __popcll(mask));
+            cb = __shfl(cb, leader);
+            if (cand) cl[cb + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int c = *lds_cnt;
+            *lds_base = c ? atomicAdd(outcnt, c) : 0;
+        }
+        __syncthreads();
+        const int c = *lds_cnt, b0 = *lds_base;
+        for (int j = threadIdx.x; j < c; j += NT) out[b0 + j] = lds_claims[j];
+        __syncthreads();
+    }
+    // wave reduction of the counters, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        upd += __shfl_down(upd, off);
+        degsum += __shfl_down(degsum, off);
+    }
+    if (lane == 0 && upd) {
+        atomicAdd((unsigned long long *)&ctl->active_updates, (unsigned long long)upd);
+        atomicAdd((unsigned long long *)&ctl->active_deg, (unsigned long long)degsum);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// topology phase of step t (one workgroup)
+// ---------------------------------------------------------------------------
+struct KSh {
+    int nL, nN, nnew, event, maxround, npend, flag;
+    int nev_step;
+    // event-path tables (wave 0)
+    int runid[MAXDEG];
+    int ostart[MAXDEG / 2 + 1], oend[MAXDEG / 2 + 1];
+    int sig[MAXDEG / 2 + 1];
+    int fin[MAXDEG / 2 + 1];
+    int steps_w[MAXDEG / 2 + 1];
+    int cyc_of[MAXDEG / 2 + 1];
+    int newtag[MAXDEG / 2 + 1];
+    int newid[MAXDEG / 2 + 1];
+    int root_run[MAXDEG / 2 + 1];      // root per lower run
+    int lrstart[MAXDEG / 2 + 1];       // start position per lower run
+    int sroot[MAXDEG / 2 + 1];         // distinct roots (ascending front id)
+    int sfid[MAXDEG / 2 + 1];
+    int srep[MAXDEG / 2 + 1];
+    int sa[MAXDEG / 2 + 1];
+    long long lplen[MAXDEG / 2 + 1];
+    long long lpoff[MAXDEG / 2 + 1];
+    long long lpmin[MAXDEG / 2 + 1];
+    double lplength[MAXDEG / 2 + 1];
+};
+
+// root of a front tag; -1 when the tag is not a valid one (a broken
+// invariant, reported by the caller)
+__device__ __forceinline__ int32_t tag_find(int32_t *tp, int32_t ntags, int32_t x) {
+    if (x < 0 || x >= ntags) return -1;
+    int32_t r = x;
+    for (int32_t g = 0; tp[r] != r; ++g) {
+        if (g > ntags) return -1;
+        r = tp[r];
+    }
+    while (tp[x] != r) { const int32_t n = tp[x]; tp[x] = r; x = n; }
+    return r;
+}
+
+// block-wide bitonic sort of n keys (ascending); a holds a power-of-two
+// padded array of size np (padding = UINT64_MAX)
+__device__ void block_bitonic(uint64_t *a, int np) {
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += NT) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t x = a[i], y = a[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) { a[i] = y; a[ixj] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// regular insertion of v (one lower arc): its new crossed half-edges carry
+// the tag of the arc, read from the half-edge (parent -> v)
+__device__ __forceinline__ void regular_insert(const DMesh &m, const DState &s, int32_t v) {
+    const int32_t par = s.parent[v];
+    const int32_t b = m.rp[v], e = m.rp[v + 1];
+    const uint64_t kv = s.key[v];
+    int32_t tag = -1;
+    for (int32_t j = b; j < e; ++j)
+        if (m.cyc[j] == par) tag = s.lid[m.rev[j]];
+    s.depth[v] = s.depth[par] + 1;
+    for (int32_t j = b; j < e; ++j) {
+        const int32_t u = m.cyc[j];
+        if (!rank_lt(s.key[u], u, kv, v)) s.lid[j] = tag;
+    }
+}
+
+// crossing point of edge (u inside, x outside) at the threshold
+__device__ __forceinline__ void crossing_point(const DMesh &m, const double *rho, int32_t u,
+                                               int32_t x, double tau, double *pt) {
+    const double ru = rho[u], rx = rho[x];
+    const double den = ru - rx;
+    double t;
+    if (den <= 0.0) {
+        t = 0.5;
+    } else {
+        t = (ru - tau) / den;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+    }
+    const double *pu = m.xyz + 3 * (int64_t)u, *px = m.xyz + 3 * (int64_t)x;
+    pt[0] = pu[0] + t * (px[0] - pu[0]);
+    pt[1] = pu[1] + t * (px[1] - pu[1]);
+    pt[2] = pu[2] + t * (px[2] - pu[2]);
+}
+
+// Saddle or vanish insertion of v at step t, resolved by wave 0 (all 64
+// lanes call it with the same v).
+__device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+                              int32_t v, KSh *sh, const double *rho) {
+    Ctl *ctl = s.ctl;
+    const int lane = __lane_id();
+    const int32_t b = m.rp[v];
+    const int d = m.rp[v + 1] - b;
+    const uint64_t kv = s.key[v];
+    const unsigned long long full_mask = d == 64 ? ~0ull : ((1ull << d) - 1ull);
+    int32_t u = -1;
+    uint64_t ku = KEY_OUT;
+    bool low = false;
+    if (lane < d) {
+        u = m.cyc[b + lane];
+        ku = s.key[u];
+        low = rank_lt(ku, u, kv, v);
+    }
+    const unsigned long long lm = __ballot(low) & full_mask;
+    const bool full = lm == full_mask;
+    // prev[j] = low[j-1], nxt[j] = low[j+1] (cyclic within d)
+    const unsigned long long prevm = ((lm << 1) | (lm >> (d - 1))) & full_mask;
+    const unsigned long long nextm = ((lm >> 1) | (lm << (d - 1))) & full_mask;
+    const unsigned long long lstart = lm & ~prevm;           // first positions of lower runs
+    const unsigned long long ostartm = ~lm & full_mask & prevm;
+    const unsigned long long oendm = ~lm & full_mask & nextm;
+    const int k = full ? 0 : __popcll(lstart);
+    // parent / depth
+    const int32_t par = s.parent[v];
+    if (lane == 0) s.depth[v] = s.depth[par] + 1;
+    // roots of the lower runs (vanish: the whole link is one run, position 0)
+    const int nruns = full ? 1 : k;
+    if (lane == 0) {
+        unsigned long long mm = full ? 1ull : lstart;
+        for (int r = 0; r < nruns; ++r) {
+            const int pos = __ffsll((long long)mm) - 1;
+            mm &= mm - 1;
+            sh->lrstart[r] = pos;
+            sh->root_run[r] = tag_find(s.tag_parent, ctl->n_tags, s.lid[m.rev[b + pos]]);
+            if (sh->root_run[r] < 0) fail(s, ST_INVARIANT, 13);
+        }
+        // distinct roots, ascending front id
+        int ns = 0;
+        for (int r = 0; r < nruns; ++r) {
+            const int rt = sh->root_run[r];
+            int q = 0;
+            while (q < ns && sh->sroot[q] != rt) q++;
+            if (q == ns) { sh->sroot[ns] = rt; sh->sfid[ns] = s.tag_fid[rt]; sh->srep[ns] = sh->lrstart[r]; ns++; }
+        }
+        for (int i = 1; i < ns; ++i)
+            for (int j = i; j > 0 && sh->sfid[j] < sh->sfid[j - 1]; --j) {
+                int t1 = sh->sfid[j]; sh->sfid[j] = sh->sfid[j - 1]; sh->sfid[j - 1] = t1;
+                t1 = sh->sroot[j]; sh->sroot[j] = sh->sroot[j - 1]; sh->sroot[j - 1] = t1;
+                t1 = sh->srep[j]; sh->srep[j] = sh->srep[j - 1]; sh->srep[j - 1] = t1;
+            }
+        sh->flag = ns;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __threadfence_block();
+    if (__shfl(ld_relaxed(&ctl->status), 0) != 0) return;
+    const int sN = __shfl(sh->flag, 0);
+    // minimum-rank lower neighbour per involved front (tunnel end points)
+    {
+        int myroot = -1;
+        if (low) myroot = tag_find(s.tag_parent, ctl->n_tags, s.lid[m.rev[b + lane]]);
+        for (int q = 0; q < sN; ++q) {
+            const int rt = sh->sroot[q];
+            const bool mine = low && myroot == rt;
+            // reduction for the minimum rank among lanes with mine
+            uint64_t bk = mine ? ku : KEY_OUT;
+            int32_t bu = mine ? u : 0x7fffffff;
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint64_t ok = __shfl_xor(bk, off);
+                const int32_t ou = __shfl_xor(bu, off);
+                if (rank_lt(ok, ou, bk, bu)) { bk = ok; bu = ou; }
+            }
+            if (lane == 0) sh->sa[q] = bu;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __threadfence_block();
+    // ---- merge: the involved loops before v joins (handle loops) ----------
+    int keep_loop0 = 0;
+    if (!full && sN >= 2) {
+        if (sN > MAXDEG / 2) { if (lane == 0) fail(s, ST_CAPACITY, 3); return; }
+        long long n = 0, best = LLONG_MAX, bestidx = 0;
+        int32_t e0 = -1;
+        if (lane < sN) {
+            e0 = m.rev[b + sh->srep[lane]];
+            int32_t e = e0;
+            do {
+                const long long key = (long long)m.src[e] * m.nv + m.cyc[e];
+                if (key < best) { best = key; bestidx = n; }
+                n++;
+                e = he_next(m, s.key, e, kv, v, false);
+            } while (e != e0 && n <= m.nnz);
+            if (n > m.nnz) fail(s, ST_INVARIANT, 4);
+            sh->lplen[lane] = n;
+            sh->lpmin[lane] = bestidx;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+        if (__shfl(ld_relaxed(&ctl->status), 0) != 0) return;
+        if (lane == 0) {
+            long long tot = 0;
+            for (int q = 0; q < sN; ++q) tot += sh->lplen[q];
+            const long long base = ctl->lp_he_used;
+            const int nl0 = ctl->n_loops;
+            if (base + tot > s.lp_he_cap || nl0 + sN > s.lp_cap) {
+                fail(s, ST_CAPACITY, 5);
+                sh->flag = -1;
+            } else {
+                long long o = base;
+                for (int q = 0; q < sN; ++q) { sh->lpoff[q] = o; o += sh->lplen[q]; }
+                ctl->lp_he_used = o;
+                ctl->n_loops = nl0 + sN;
+                sh->flag = nl0;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+        const int nl0 = __shfl(sh->flag, 0);
+        if (nl0 < 0) return;
+        keep_loop0 = nl0;
+        if (lane < sN) {
+            const long long off = sh->lpoff[lane];
+            int32_t e = e0;
+            long long i = 0;
+            do {
+                const long long pos = off + (i - bestidx + n) % n;
+                const int32_t uu = m.src[e], xx = m.cyc[e];
+                s.lp_he[2 * pos] = uu;
+                s.lp_he[2 * pos + 1] = xx;
+                crossing_point(m, rho, uu, xx, p.tau, s.lp_pts + 3 * pos);
+                i++;
+                e = he_next(m, s.key, e, kv, v, false);
+            } while (e != e0);
+            double L = 0.0;
+            for (long long q = 0; q < n; ++q) {
+                const double *pa = s.lp_pts + 3 * (off + q);
+                const double *pb = s.lp_pts + 3 * (off + (q + 1) % n);
+                const double dx = pb[0] - pa[0], dy = pb[1] - pa[1], dz = pb[2] - pa[2];
+                L = L + sqrt((dx * dx + dy * dy) + dz * dz);
+            }
+            sh->lplength[lane] = L;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+    }
+    // ---- the loops after v joins: walkers from the end of each new arc ----
+    int mN = 0;
+    if (!full) {
+        if (k > MAXDEG / 2) { if (lane == 0) fail(s, ST_CAPACITY, 6); return; }
+        // run id of every outside position: index of the end position that
+        // closes its arc (ends in ascending order)
+        if (lane < d && !low) {
+            const unsigned long long ge = oendm >> lane;
+            int endpos;
+            if (ge) endpos = lane + __ffsll((long long)ge) - 1;
+            else endpos = __ffsll((long long)oendm) - 1;
+            sh->runid[lane] = __popcll(oendm & ((endpos == 0) ? 0ull : ((1ull << endpos) - 1ull)));
+        }
+        if (lane < k) {
+            // lane-th end / start positions (ascending)
+            unsigned long long mm = oendm;
+            for (int q = 0; q < lane; ++q) mm &= mm - 1;
+            sh->oend[lane] = __ffsll((long long)mm) - 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+        if (lane < d && !low && (ostartm >> lane & 1ull)) sh->ostart[sh->runid[lane]] = lane;
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+        int32_t e = lane < k ? b + sh->oend[lane] : -1;
+        bool done = lane >= k;
+        int steps = 0, tgt = -1;
+        for (;;) {
+            const unsigned long long act = __ballot(!done) & ((k == 64) ? ~0ull : ((1ull << k) - 1ull));
+            if (__popcll(act) <= 1) break;
+            if (!done) {
+                e = he_next(m, s.key, e, kv, v, true);
+                steps++;
+                if (m.src[e] == v) { done = true; tgt = sh->runid[e - b]; }
+                if (steps > m.nnz) { fail(s, ST_INVARIANT, 7); done = true; tgt = 0; }
+            }
+        }
+        if (lane < k) { sh->fin[lane] = done ? 1 : 0; sh->sig[lane] = tgt; sh->steps_w[lane] = steps; }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+        if (__shfl(ld_relaxed(&ctl->status), 0) != 0) return;
+        if (lane == 0) {
+            // the unfinished walker (if any) closes onto the one arc nobody reached
+            unsigned long long hit = 0;
+            int unf = -1;
+            for (int o = 0; o < k; ++o) { if (sh->fin[o]) hit |= 1ull << sh->sig[o]; else unf = o; }
+            if (unf >= 0) {
+                const unsigned long long rem = ~hit & ((k == 64) ? ~0ull : ((1ull << k) - 1ull));
+                sh->sig[unf] = __ffsll((long long)rem) - 1;
+            }
+            // cycles of the arc permutation = the loops after the insertion
+            for (int o = 0; o < k; ++o) sh->cyc_of[o] = -1;
+            int nc = 0;
+            int minpos[MAXDEG / 2 + 1];
+            long long wlen[MAXDEG / 2 + 1];
+            for (int o = 0; o < k; ++o) {
+                if (sh->cyc_of[o] >= 0) continue;
+                int q = o, mp = 1 << 30;
+                long long wl = 0;
+                int guard = 0;
+                while (sh->cyc_of[q] < 0 && guard++ <= k) {
+                    sh->cyc_of[q] = nc;
+                    const int st = sh->ostart[q], en = sh->oend[q];
+                    const int mpos = st <= en ? st : 0;
+                    if (mpos < mp) mp = mpos;
+                    wl += sh->steps_w[q];
+                    q = sh->sig[q];
+                }
+                minpos[nc] = mp;
+                wlen[nc] = wl;
+                nc++;
+            }
+            // the loop holding the unfinished walker keeps the old tags
+            int big = 0;
+            if (unf >= 0) big = sh->cyc_of[unf];
+            else for (int c = 1; c < nc; ++c) if (wlen[c] > wlen[big]) big = c;
+            // new front ids in counter-clockwise order of the first new half-edge
+            int order[MAXDEG / 2 + 1];
+            for (int c = 0; c < nc; ++c) {
+                int r = 0;
+                for (int q = 0; q < nc; ++q) if (minpos[q] < minpos[c]) r++;
+                order[c] = r;
+            }
+            const int fid0 = ctl->next_front;
+            if (fid0 + nc > s.front_cap || ctl->n_tags + nc > s.tag_cap) {
+                fail(s, ST_CAPACITY, 8);
+                sh->flag = -1;
+            } else {
+                ctl->next_front = fid0 + nc;
+                const int R0 = sh->sroot[0];
+                for (int q = 1; q < sN; ++q) s.tag_parent[sh->sroot[q]] = R0;
+                for (int c = 0; c < nc; ++c) {
+                    sh->newid[c] = fid0 + order[c];
+                    if (c == big) {
+                        sh->newtag[c] = R0;
+                        s.tag_fid[R0] = fid0 + order[c];
+                    } else {
+                        const int tg = ctl->n_tags++;
+                        s.tag_parent[tg] = tg;
+                        s.tag_fid[tg] = fid0 + order[c];
+                        sh->newtag[c] = tg;
+                    }
+                }
+                sh->flag = nc;
+                sh->maxround = big;   // reuse: index of the big loop
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+        mN = __shfl(sh->flag, 0);
+        if (mN < 0) return;
+        const int big = __shfl(sh->maxround, 0);
+        // tags of the new arcs, and relabel of every loop but the big one
+        if (lane < d && !low) s.lid[b + lane] = sh->newtag[sh->cyc_of[sh->runid[lane]]];
+        if (lane < k && sh->cyc_of[lane] != big) {
+            const int32_t tg = sh->newtag[sh->cyc_of[lane]];
+            int32_t ee = b + sh->oend[lane];
+            for (int64_t guard = 0; guard <= m.nnz; ++guard) {
+                ee = he_next(m, s.key, ee, kv, v, true);
+                if (m.src[ee] == v) break;
+                s.lid[ee] = tg;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+    }
+    // ---- bookkeeping: h, x, node, records ----------------------------------
+    if (lane == 0) {
+        long long h = 0, xx = 0;
+        bool ok = true;
+        if (full) {
+            ok = (sN == 1);
+        } else {
+            const long long num = (long long)k - 1 - ((long long)mN - sN);
+            if (num < 0 || (num & 1)) ok = false;
+            h = num / 2;
+            xx = h - (sN - 1);
+            if (xx < 0) ok = false;
+        }
+        const int ev = ctl->n_events;
+        const long long idoff = ctl->ev_ids_used;
+        if (!ok) {
+            fail(s, ST_INVARIANT, 9);
+        } else if (ev >= s.ev_cap || idoff + sN + mN > s.ev_ids_cap || sN > 16) {
+            fail(s, ST_CAPACITY, 10);
+        } else {
+            const int type = full ? NODE_VANISH : (xx > 0 ? NODE_DEGENERATE : (sN >= 2 ? NODE_MERGE : NODE_SPLIT));
+            const int node = ev + 1;
+            int64_t *rec = s.ev + 16 * (int64_t)ev;
+            rec[0] = t; rec[1] = v; rec[2] = type; rec[3] = full ? 0 : k; rec[4] = sN; rec[5] = mN;
+            rec[6] = h; rec[7] = xx; rec[8] = node; rec[9] = (int64_t)(kv & 0xffffffffull);
+            rec[10] = full ? 1 : 0; rec[11] = idoff; rec[12] = 0; rec[13] = 0; rec[14] = 0; rec[15] = 0;
+            for (int q = 0; q < sN; ++q) {
+                s.ev_ids[idoff + q] = sh->sfid[q];
+                s.ev_rep[16 * (int64_t)ev + q] = sh->srep[q];
+                s.front_death[sh->sfid[q]] = node;
+            }
+            if (!full) {
+                for (int c = 0; c < mN; ++c) {
+                    // out ids listed in ascending (counter-clockwise) order
+                    s.ev_ids[idoff + sN + (sh->newid[c] - ctl->next_front + mN)] = sh->newid[c];
+                    s.front_birth[sh->newid[c]] = node;
+                    s.front_death[sh->newid[c]] = -1;
+                }
+            }
+            ctl->ev_ids_used = idoff + sN + mN;
+            ctl->n_events = ev + 1;
+            ctl->chi += full ? 1 : 1 - k;
+            ctl->b += (long long)mN - sN;
+            ctl->gsum_x += xx;
+            // handle loops: every involved loop but the longest (ties: larger id)
+            if (!full && sN >= 2) {
+                int drop = 0;
+                for (int q = 1; q < sN; ++q) if (sh->lplength[q] >= sh->lplength[drop]) drop = q;
+                for (int q = 0; q < sN; ++q) {
+                    int64_t *lr = s.lp + 8 * (int64_t)(keep_loop0 + q);
+                    lr[0] = ev; lr[1] = sh->sfid[q]; lr[2] = q != drop; lr[3] = sh->lpoff[q];
+                    lr[4] = sh->lplen[q]; lr[5] = sh->sa[q];
+                    lr[6] = __double_as_longlong(sh->lplength[q]); lr[7] = 0;
+                    if (q != drop) {
+                        const int tnn = ctl->n_tunnels++;
+                        int32_t *tr = s.tn + 4 * (int64_t)tnn;
+                        tr[0] = keep_loop0 + q; tr[1] = v; tr[2] = sh->sa[q]; tr[3] = sh->sa[drop];
+                        ctl->gsum_h += 1;
+                    }
+                }
+            }
+            const long long twog = 2 - ctl->chi - ctl->b;
+            if (twog != 2 * (ctl->gsum_h + ctl->gsum_x)) fail(s, ST_INVARIANT, 11);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __threadfence_block();
+}
+
+__device__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+                           KSh *sh, uint64_t *lsort) {
+    Ctl *ctl = s.ctl;
+    const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
+    const int tid = threadIdx.x;
+    if (tid == 0) { sh->nL = 0; sh->nN = 0; sh->nnew = 0; sh->event = 0; sh->npend = 0; }
+    __syncthreads();
+    // 1. candidates: this step's crossers plus the pending ones, de-duplicated
+    const int nc = ld_relaxed(&ctl->cnt_cand[t & 3]);
+    const int np = ctl->cnt_pend[(t - 1) & 1];
+    const int32_t *cl = s.cand[t & 1];
+    const int32_t *pl = s.pend[(t - 1) & 1];
+    for (int i = tid; i < nc + np; i += NT) {
+        const int32_t x = i < nc ? cl[i] : pl[i - nc];
+        if (s.key[x] == KEY_OUT && rho[x] > p.tau) {
+            if (atomicExch(&s.cstamp[x], (int32_t)t) != (int32_t)t) {
+                const int slot = atomicAdd(&sh->nL, 1);
+                s.L[slot] = x;
+                s.Lrnd[slot] = -1;
+            }
+        }
+    }
+    __syncthreads();
+    const int nL = sh->nL;
+    const uint64_t tk = (uint64_t)t << 32;
+    int round = 0;
+    if (nL > 0) {
+        // 2. closure rounds: round 0 touches the inside set of step t-1,
+        //    round j touches round j-1
+        for (;;) {
+            for (int i = tid; i < nL; i += NT) {
+                int flag = 0;
+                if (s.Lrnd[i] == -1) {
+                    const int32_t x = s.L[i];
+                    for (int32_t j = m.rp[x]; j < m.rp[x + 1]; ++j) {
+                        const uint64_t kk = s.key[m.adj[j]];
+                        if (round == 0 ? (kk < tk) : (kk == (tk | (uint64_t)(round - 1)))) { flag = 1; break; }
+                    }
+                }
+                s.Lcls[i] = flag;
+            }
+            __syncthreads();
+            int mine = 0;
+            for (int i = tid; i < nL; i += NT)
+                if (s.Lcls[i]) { s.Lrnd[i] = round; s.key[s.L[i]] = tk | (uint64_t)round; mine++; }
+            if (mine) atomicAdd(&sh->nnew, mine);
+            __syncthreads();
+            const int nnew = sh->nnew;
+            __syncthreads();
+            if (tid == 0) { sh->nN += nnew; sh->nnew = 0; }
+            __syncthreads();
+            if (nnew == 0) break;
+            if (sh->nN == nL) { round++; break; }
+            round++;
+        }
+        // rounds used: 0 .. round-1
+        const int nrounds = round;
+        // 3. lower-link classification of every inserted vertex
+        for (int i = tid; i < nL; i += NT) {
+            if (s.Lrnd[i] < 0) continue;
+            const int32_t v = s.L[i];
+            const uint64_t kv = s.key[v];
+            const int32_t b = m.rp[v];
+            const int d = m.rp[v + 1] - b;
+            int32_t ulast = m.cyc[b + d - 1];
+            bool prev = rank_lt(s.key[ulast], ulast, kv, v);
+            int nlow = 0, runs = 0;
+            int32_t par = -1;
+            uint64_t kp = KEY_OUT;
+            for (int j = 0; j < d; ++j) {
+                const int32_t u = m.cyc[b + j];
+                const uint64_t ku = s.key[u];
+                const bool low = rank_lt(ku, u, kv, v);
+                if (low) {
+                    nlow++;
+                    if (!prev) runs++;
+                    if (par < 0 || rank_lt(ku, u, kp, par)) { par = u; kp = ku; }
+                }
+                prev = low;
+            }
+            const int cls = nlow == d ? -1 : runs;
+            s.Lcls[i] = cls;
+            s.parent[v] = par;
+            if (cls != 1) atomicOr(&sh->event, 1);
+            if (nlow == 0 || d > MAXDEG) atomicOr(&sh->event, 2);
+        }
+        __syncthreads();
+        if (sh->event & 2) {
+            if (tid == 0) fail(s, ST_INVARIANT, 12);
+        } else if (!sh->event) {
+            // 4a. all insertions regular: tags follow the parent edge, by round
+            for (int r = 0; r < nrounds; ++r) {
+                for (int i = tid; i < nL; i += NT)
+                    if (s.Lrnd[i] == r) regular_insert(m, s, s.L[i]);
+                __syncthreads();
+            }
+        } else {
+            // 4b. events: rank order (round, id); regular runs between events in
+            //     parallel by round, each event by wave 0
+            const int nN = sh->nN;
+            int npow = 1;
+            while (npow < nN) npow <<= 1;
+            uint64_t *arr = npow <= SORTCAP ? lsort : s.ord;
+            for (int i = tid; i < npow; i += NT) arr[i] = ~0ull;
+            __syncthreads();
+            if (tid == 0) sh->nnew = 0;
+            __syncthreads();
+            for (int i = tid; i < nL; i += NT) {
+                if (s.Lrnd[i] < 0) continue;
+                const int slot = atomicAdd(&sh->nnew, 1);
+                arr[slot] = ((uint64_t)s.Lrnd[i] << 33) | ((uint64_t)s.L[i] << 1) | (uint64_t)(s.Lcls[i] != 1);
+            }
+            __syncthreads();
+            block_bitonic(arr, npow);
+            int pos = 0;
+            while (pos < nN) {
+                // regular segment [pos, q)
+                int q = pos;
+                while (q < nN && !(arr[q] & 1ull)) q++;
+                int a0 = pos;
+                while (a0 < q) {
+                    const int r = (int)(arr[a0] >> 33);
+                    int a1 = a0;
+                    while (a1 < q && (int)(arr[a1] >> 33) == r) a1++;
+                    for (int i = a0 + tid; i < a1; i += NT)
+                        regular_insert(m, s, (int32_t)((arr[i] >> 1) & 0xffffffffull));
+                    __syncthreads();
+                    a0 = a1;
+                }
+                if (q < nN) {
+                    if (tid < WAVE)
+                        resolve_event(m, s, p, t, (int32_t)((arr[q] >> 1) & 0xffffffffull), sh, rho);
+                    __syncthreads();
+                    if (ld_relaxed(&ctl->status) != 0) break;
+                }
+                pos = q + 1;
+            }
+            if (tid == 0) ctl->event_steps += 1;
+        }
+    }
+    // 5. crossers not connected this step wait for the next
+    for (int i = tid; i < nL; i += NT)
+        if (s.Lrnd[i] < 0) s.pend[t & 1][atomicAdd(&sh->npend, 1)] = s.L[i];
+    __syncthreads();
+    if (tid == 0) {
+        ctl->cnt_pend[t & 1] = sh->npend;
+        const int nN = sh->nN;
+        ctl->n_inside += nN;
+        if (nN) ctl->last_insert = t;
+        ctl->steps = t;
+        if (ctl->status != 0) {
+            ctl->done = 1;
+        } else if (ctl->n_inside == m.nv) {
+            ctl->done = 1;
+        } else if (t - ctl->last_insert >= p.stall_steps || t >= p.max_steps) {
+            ctl->status = ST_STALLED;
+            ctl->done = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the persistent step kernel
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const unsigned G = gridDim.x;
+    unsigned long long epoch = 0;
+    Ctl *ctl = s.ctl;
+    KSh *ksh = (KSh *)lds;
+    uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
+    int *fcnt = (int *)lds;
+    int32_t *claims = (int32_t *)(lds + 16);
+    if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    for (int64_t j = 0;; ++j) {
+        if (blockIdx.x == 0) {
+            if (threadIdx.x == 0) {
+                ctl->cnt_act[(j + 3) & 3] = 0;
+                ctl->cnt_cand[(j + 2) & 3] = 0;
+            }
+            if (j >= 1) phase_topo(m, s, p, j, ksh, lsort);
+            __syncthreads();
+            // publish this iteration's decision in its own slot: the slot is
+            // rewritten two iterations later, after every workgroup read it
+            if (threadIdx.x == 0)
+                ctl->stop[j & 1] = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (G == 1) {
+                __syncthreads();
+                phase_field(m, s, p, j + 1, 0, 1, claims, fcnt, fcnt + 1);
+            }
+        } else {
+            phase_field(m, s, p, j + 1, blockIdx.x - 1, G - 1, claims, fcnt, fcnt + 1);
+        }
+        // field snapshots of step j (its buffer is not written in this iteration)
+        for (int q = 0; q < s.n_ckpt; ++q) {
+            if (s.ckpt_steps[q] != j || j == 0) continue;
+            const double *src = (j & 1) ? s.rho1 : s.rho0;
+            double *dst = s.ckpt + (int64_t)q * m.nv;
+            const int nb = G > 1 ? G - 1 : 1;
+            const int bi = G > 1 ? (int)blockIdx.x - 1 : 0;
+            if (bi < 0) continue;
+            for (int64_t i = (int64_t)bi * NT + threadIdx.x; i < m.nv; i += (int64_t)nb * NT) dst[i] = src[i];
+        }
+        grid_sync(ctl, G, epoch);
+        if (__hip_atomic_load(&ctl->stop[j & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    }
+}
+
+size_t step_lds_bytes(int block, int dmax) {
+    const size_t kb = ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t);
+    const size_t fb = 16 + (size_t)block * (dmax + 1) * sizeof(int32_t);
+    return kb > fb ? kb : fb;
+}
+
+int max_coresident_blocks(int block, size_t lds_bytes) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_steps, block, lds_bytes) != hipSuccess)
+        return 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return per_cu * cus;
+}
+
+hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int grid, int block,
+                        hipStream_t st) {
+    const size_t lds = step_lds_bytes(block, m.dmax);
+    DMesh mm = m;
+    DState ss = s;
+    DParams pp = p;
+    void *args[] = {&mm, &ss, &pp};
+    return hipLaunchCooperativeKernel((const void *)k_steps, dim3(grid), dim3(block), args,
+                                      (unsigned)lds, st);
+}
+
+// ---------------------------------------------------------------------------
+// post-pass: Reeb node positions = mean of the distinct vertices of the
+// front triangles of the involved loops just before the event vertex joins,
+// summed in ascending vertex id
+// ---------------------------------------------------------------------------
+__device__ int64_t walk_event_loops(const DMesh &m, const DState &s, int ev, int32_t *out) {
+    const int64_t *rec = s.ev + 16 * (int64_t)ev;
+    const int32_t v = (int32_t)rec[1];
+    const int sN = (int)rec[4];
+    const uint64_t kv = s.key[v];
+    const int32_t b = m.rp[v];
+    int64_t n = 0;
+    for (int q = 0; q < sN; ++q) {
+        const int32_t e0 = m.rev[b + s.ev_rep[16 * (int64_t)ev + q]];
+        int32_t e = e0;
+        int64_t guard = 0;
+        do {
+            if (out) {
+                out[3 * n] = m.src[e];
+                out[3 * n + 1] = m.cyc[e];
+                out[3 * n + 2] = m.cyc[m.succ[e]];
+            }
+            n++;
+            e = he_next(m, s.key, e, kv, v, false);
+        } while (e != e0 && ++guard <= m.nnz);
+    }
+    return n;
+}
+
+__global__ void k_reeb_count(DMesh m, DState s, int n_events, int64_t *cnt) {
+    for (int ev = blockIdx.x * blockDim.x + threadIdx.x; ev < n_events; ev += gridDim.x * blockDim.x)
+        cnt[ev] = 3 * walk_event_loops(m, s, ev, nullptr);
+}
+
+// segment ev of buf spans [off[ev], off[ev+1]) (a power of two), its first
+// cnt[ev] entries are vertex ids, the rest is padding above every id
+__global__ void k_reeb_fill(DMesh m, DState s, int n_events, const int64_t *off, const int64_t *cnt,
+                            int32_t *buf) {
+    for (int ev = blockIdx.x * blockDim.x + threadIdx.x; ev < n_events; ev += gridDim.x * blockDim.x) {
+        walk_event_loops(m, s, ev, buf + off[ev]);
+        for (int64_t i = off[ev] + cnt[ev]; i < off[ev + 1]; ++i) buf[i] = 0x7fffffff;
+    }
+}
+
+template <typename K>
+__device__ void block_bitonic_t(K *a, int64_t np) {
+    for (int64_t k = 2; k <= np; k <<= 1) {
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            for (int64_t i = threadIdx.x; i < np; i += NT) {
+                const int64_t ixj = i ^ j;
+                if (ixj > i) {
+                    const K x = a[i], y = a[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) { a[i] = y; a[ixj] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+#define MEANCAP 16384
+__global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const int64_t *off,
+                                                   const int64_t *cnt, int32_t *buf, double *pos) {
+    __shared__ uint32_t a[MEANCAP];
+    for (int ev = blockIdx.x; ev < n_events; ev += gridDim.x) {
+        const int64_t o = off[ev], np = off[ev + 1] - off[ev], n = cnt[ev];
+        uint32_t *arr;
+        if (np <= MEANCAP) {
+            for (int64_t i = threadIdx.x; i < np; i += NT) a[i] = (uint32_t)buf[o + i];
+            __syncthreads();
+            arr = a;
+        } else {
+            arr = (uint32_t *)(buf + o);
+        }
+        block_bitonic_t<uint32_t>(arr, np);
+        if (threadIdx.x == 0) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            long long c = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (i > 0 && arr[i] == arr[i - 1]) continue;
+                const double *x = m.xyz + 3 * (int64_t)arr[i];
+                sx = sx + x[0];
+                sy = sy + x[1];
+                sz = sz + x[2];
+                c++;
+            }
+            pos[3 * ev] = sx / (double)c;
+            pos[3 * ev + 1] = sy / (double)c;
+            pos[3 * ev + 2] = sz / (double)c;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt,
+                             hipStream_t st) {
+    if (n_events <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reeb_count, dim3((n_events + 63) / 64), dim3(64), 0, st, m, s, n_events, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int n_events, const int64_t *off,
+                            const int64_t *cnt, int32_t *buf, hipStream_t st) {
+    if (n_events <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reeb_fill, dim3((n_events + 63) / 64), dim3(64), 0, st, m, s, n_events, off,
+                       cnt, buf);
+    return hipGetLastError();
+}
+hipError_t launch_reeb_mean(const DMesh &m, int n_events, const int64_t *off, const int64_t *cnt,
+                            int32_t *buf, double *pos, hipStream_t st) {
+    if (n_events <= 0) return hipSuccess;
+    int blocks = n_events < 1024 ? n_events : 1024;
+    hipLaunchKernelGGL(k_reeb_mean, dim3(blocks), dim3(NT), 0, st, m, n_events, off, cnt, buf, pos);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// post-pass: tunnel candidates v, a_j, ..., common ancestor, ..., a_0
+// ---------------------------------------------------------------------------
+__device__ int64_t tunnel_path(const DState &s, int i, int32_t *out) {
+    const int32_t *tr = s.tn + 4 * (int64_t)i;
+    const int32_t v = tr[1];
+    int32_t p1 = tr[2], p2 = tr[3];
+    int64_t n = 0;
+    if (out) out[n] = v;
+    n++;
+    // climb to equal depth, then together; the a_0 side is written reversed
+    int64_t up = 0, down = 0;
+    {
+        int32_t q1 = p1, q2 = p2;
+        while (s.depth[q1] > s.depth[q2]) { q1 = s.parent[q1]; up++; }
+        while (s.depth[q2] > s.depth[q1]) { q2 = s.parent[q2]; down++; }
+        while (q1 != q2) { q1 = s.parent[q1]; q2 = s.parent[q2]; up++; down++; }
+    }
+    if (out) {
+        int32_t q = p1;
+        for (int64_t i2 = 0; i2 <= up; ++i2) { out[n + i2] = q; q = s.parent[q]; }
+        q = p2;
+        for (int64_t i2 = 0; i2 < down; ++i2) { out[n + up + down - i2] = q; q = s.parent[q]; }
+    }
+    return n + up + 1 + down;
+}
+
+__global__ void k_tunnel_count(DState s, int nt, int64_t *cnt) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x)
+        cnt[i] = tunnel_path(s, i, nullptr);
+}
+__global__ void k_tunnel_fill(DMesh m, DState s, int nt, const int64_t *off, int32_t *out, double *len) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+        const int64_t n = tunnel_path(s, i, out + off[i]);
+        const int32_t *c = out + off[i];
+        double L = 0.0;
+        for (int64_t q = 0; q < n; ++q) {
+            const double *pa = m.xyz + 3 * (int64_t)c[q];
+            const double *pb = m.xyz + 3 * (int64_t)c[(q + 1) % n];
+            const double dx = pb[0] - pa[0], dy = pb[1] - pa[1], dz = pb[2] - pa[2];
+            L = L + sqrt((dx * dx + dy * dy) + dz * dz);
+        }
+        len[i] = L;
+    }
+}
+hipError_t launch_tunnel_count(const DState &s, int n_tunnels, int64_t *cnt, hipStream_t st) {
+    if (n_tunnels <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tunnel_count, dim3((n_tunnels + 63) / 64), dim3(64), 0, st, s, n_tunnels, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int n_tunnels, const int64_t *off, int32_t *out,
+                              double *len, hipStream_t st) {
+    if (n_tunnels <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tunnel_fill, dim3((n_tunnels + 63) / 64), dim3(64), 0, st, m, s, n_tunnels, off, out, len);
+    return hipGetLastError();
+}
+
+}  // namespace vls

@@ -1,0 +1,95 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on
+the same seeded inputs, element by element.
+
+Bars (stated in tests/_parity.py): integer, index and topology outputs
+bit-exact; the FP64 field within 1e-12 and, since both sides evaluate the
+same expressions in the same order without contraction, bit-identical, as
+are crossing points, loop lengths and Reeb node positions.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from _parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2105_13168_amd as vls
+    c = vls.Context(0)
+    yield c
+    c.close()
+
+
+def _run_both(ctx, oracle_mod, m, ck=(), **kw):
+    import paper_2105_13168_amd as vls
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    try:
+        g = M.run(seed_vertex=m.seed, ckpt_steps=ck, raise_on_error=False, **kw)
+    finally:
+        M.close()
+    o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed, ckpt_steps=ck, **kw)
+    return g, o
+
+
+SMALL = [
+    ("torus64x32_s0", lambda: mg.torus_grid(rng_seed=0), [1, 2, 4, 8, 16, 32, 64, 128, 250, 256, 450, 502]),
+    ("torus64x32_s1", lambda: mg.torus_grid(rng_seed=1), [1, 100, 300]),
+    ("torus64x32_s2", lambda: mg.torus_grid(rng_seed=2), [1, 500]),
+    ("sphere16", lambda: mg.sdf_surface(mg.sdf_sphere(), (-1, -1, -1), (1, 1, 1), 16, 1e-4, 0), [1, 50]),
+    ("box20", lambda: mg.sdf_surface(mg.sdf_box((1, .5, .3)), (-1, -.5, -.3), (1, .5, .3), 20, 1e-4, 3), [7]),
+    ("double_torus32", lambda: mg.multi_torus(2, 32), [1, 500, 1000]),
+    ("pretzel48", lambda: mg.pretzel(48), [1, 1000, 2000, 3000]),
+    ("thin_strip400x6", lambda: mg.torus_grid(400, 6, R=10.0, r=0.2, jitter=1e-3, rng_seed=0), [1, 1000]),
+]
+
+
+@pytest.mark.parametrize("name,make,ck", SMALL, ids=[c[0] for c in SMALL])
+def test_parity_small(ctx, oracle_mod, name, make, ck):
+    m = make()
+    g, o = _run_both(ctx, oracle_mod, m, ck)
+    assert g.summary["run_status"] == 0
+    bad = compare(g, o, m.nv)
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("grid", [1, 2, 3, 17, 64])
+def test_parity_independent_of_launch_shape(ctx, oracle_mod, grid):
+    m = mg.multi_torus(2, 28, rng_seed=3)
+    g, o = _run_both(ctx, oracle_mod, m, [1, 300, 900], grid=grid)
+    assert g.summary["grid"] == grid
+    bad = compare(g, o, m.nv)
+    assert not bad, bad
+
+
+def test_parity_dt_literal_and_radius(ctx, oracle_mod):
+    # literal dt = 0.25/dmax on a tiny torus; and a radius-1 / radius-3 seed
+    m = mg.torus_grid(16, 8, R=1.0, r=0.4, jitter=1e-3, rng_seed=5)
+    for kw in (dict(dt_mode=1), dict(seed_radius=1), dict(seed_radius=3)):
+        g, o = _run_both(ctx, oracle_mod, m, [1, 10], **kw)
+        bad = compare(g, o, m.nv)
+        assert not bad, (kw, bad)
+
+
+def test_error_paths(ctx, oracle_mod):
+    import paper_2105_13168_amd as vls
+    # seed region containing a handle
+    m = mg.torus_grid(5, 4, R=1.0, r=0.3, jitter=0.0)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    g = M.run(seed_vertex=0, raise_on_error=False)
+    assert g.status == -6 and g.summary["run_status"] == -6
+    M.close()
+    # stall by step limit: partial results equal the oracle's
+    m = mg.torus_grid()
+    g, o = _run_both(ctx, oracle_mod, m, [5], max_steps=300)
+    assert g.summary["run_status"] == -7 and o.status == -7
+    assert not compare(g, o, m.nv)
+    # invalid meshes are rejected at setup
+    with pytest.raises(vls.VLSError):
+        vls.Mesh(ctx, m.xyz, m.tri[1:])
+    t = m.tri.copy()
+    t[3] = t[3, ::-1]
+    with pytest.raises(vls.VLSError):
+        vls.Mesh(ctx, m.xyz, t)
