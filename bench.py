@@ -1,0 +1,168 @@
+"""Benchmark of the initial pass of the variational loop-shrinking method on
+one MI355X.
+
+A "step" here is one complete initial pass over the workload: seed region,
+every diffusion step until the front has swept the whole surface (field,
+threshold + closure, lower-link classification, front tags, split / merge /
+vanish events with handle loops), then the Reeb-position and tunnel
+post-passes.  The workload is the genus-3 pretzel (three tori R=1, r=0.35 at
+x = -1.6, 0, 1.6; level-0 surface on a 256^3 sample grid fitted per axis;
+N(0,1e-4) jitter; seed vertex from rng seed 0), with its mesh uploaded to
+HBM before the timed region.  Bulk results stay on the device (deferred),
+so the timed region holds no result download.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+
+Prints one JSON line.
+"""
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import meshgen as mg
+    if name == "pretzel256":
+        m = mg.pretzel(256, rng_seed=0)
+        desc = "genus-3 pretzel, level-0 surface of three tori SDFs on a 256^3 grid (marching tetrahedra)"
+    elif name == "torus64x32":
+        m = mg.torus_grid(rng_seed=0)
+        desc = "64x32 torus grid, R=1, r=0.4"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return m, desc
+
+
+def alg_bytes(updates, degsum):
+    # per updated vertex: read rho(v) 8 + write rho(v) 8 + two row offsets 8
+    # + update-list entry in/out 8, plus 4 bytes per neighbour id
+    return 32 * updates + 4 * degsum
+
+
+def cpu_baseline(m, max_steps):
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed, max_steps=max_steps)
+    dt = time.perf_counter() - t0
+    steps = r.steps
+    return {"value": m.nv * steps / dt, "unit": "vertex-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} diffusion steps of the same pass (single thread, {dt:.1f} s)",
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pretzel256")
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--cpu-steps", type=int, default=10000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(meshes shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    t0 = time.time()
+    m, desc = make_workload(args.workload)
+    log(f"workload {args.workload}: V={m.nv} F={m.nf} seed={m.seed} ({time.time() - t0:.1f}s)")
+    import torch
+    import paper_2105_13168_amd as vls
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    ctx = vls.Context(0, stream=stream.cuda_stream)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+
+    def one_pass():
+        p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_DEFER_RESULTS, grid=args.grid)
+        h = C.c_void_p()
+        st = vls.vls_run(ctx.h, M.h, C.byref(p), C.byref(h))
+        if st != 0:
+            raise vls.VLSError(st, ctx.last_error())
+        s = vls.vls_summary()
+        vls.vls_result_summary(h, C.byref(s))
+        return h, {f: getattr(s, f) for f, _ in vls.vls_summary._fields_}
+
+    for _ in range(args.warmup):
+        h, _s = one_pass()
+        vls.vls_result_destroy(h)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    sums = []
+    handles = []
+    ev0.record(stream)
+    for k in range(args.steps):
+        h, s = one_pass()
+        sums.append(s)
+        handles.append(h)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    # validate the last pass outside the timed region
+    last = sums[-1]
+    for h in handles[:-1]:
+        vls.vls_result_destroy(h)
+    vls.vls_result_fetch(handles[-1])
+    vls.vls_result_destroy(handles[-1])
+    assert last["run_status"] == 0
+    assert last["n_handles"] == M.euler_genus and last["n_tunnels"] == M.euler_genus
+    steps = last["steps"]
+    kernel_ms = sum(s["kernel_ms"] for s in sums) / len(sums)
+    device_ms = sum(s["total_ms"] for s in sums) / len(sums)
+    upd = last["active_vertex_updates"]
+    deg = last["active_degree_sum"]
+    ab = alg_bytes(upd, deg)
+    achieved = ab / (kernel_ms * 1e-3) / 1e9
+    value = m.nv * steps / (ms * 1e-3)
+    out = {
+        "metric": "vertex-diffusion-steps/sec",
+        "value": value,
+        "unit": "vertex-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": desc, "nv": m.nv, "nf": m.nf, "seed_vertex": m.seed, "genus": M.euler_genus,
+            "diffusion_steps": steps, "events": last["n_events"], "handles": last["n_handles"],
+            "active_vertex_updates": upd, "grid": last["grid"], "block": last["block"],
+            "device_ms_per_pass": device_ms, "step_kernel_ms": kernel_ms,
+            "active_updates_per_s": upd / (ms * 1e-3),
+            "phase_ms": {"topology": last["topo_ms"], "topology_wait": last["wait0_ms"],
+                         "field": last["field_ms"], "field_wait": last["wait1_ms"]},
+            "event_steps": last["event_steps"],
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_steps", "algorithmic_bytes": ab},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_steps)
+    M.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,6 +62,8 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
 
 /* flags */
 #define VLS_RECORD_FIELD 1u   /* keep FP64 snapshots of the field at ckpt_steps */
+#define VLS_DEFER_RESULTS 2u  /* vls_run returns once the device work is done; bulk results
+                                 are copied to the host by vls_result_fetch or on first access */
 
 /*
  * Parameters.  Defaults (vls_params_default) are the paper's coefficients
@@ -148,6 +150,10 @@ typedef struct {
     int32_t grid, block;       /* launch shape used                                           */
     double kernel_ms;          /* device time of the persistent step kernel (HIP events)     */
     double total_ms;           /* device time of the whole pass, seed to post-passes          */
+    /* device clock (s_memrealtime) split of the step kernel: workgroup 0
+       topology work and its barrier wait, workgroup 1 field work and wait */
+    double topo_ms, wait0_ms, field_ms, wait1_ms;
+    int64_t event_steps;       /* steps resolved through the sequential event path           */
 } vls_summary;
 vls_status vls_result_summary(const struct vls_result *r, vls_summary *s);
 
@@ -197,6 +203,14 @@ vls_status vls_result_field(const struct vls_result *r, int64_t step, double *rh
    parent (streamline predecessor, -1 for the seed).  Any pointer may be NULL. */
 vls_status vls_result_vertices(const struct vls_result *r, int32_t *step, int32_t *round,
                                int32_t *parent);
+/* Copies the bulk results of a VLS_DEFER_RESULTS run to the host (no-op
+   otherwise).  Called implicitly by every accessor, by the next vls_run on
+   the same mesh and by vls_mesh_destroy, since a mesh keeps one run's
+   device state at a time.  A deferred result must be fetched or destroyed
+   before its context is destroyed. */
+vls_status vls_result_fetch(struct vls_result *r);
+/* Frees a result; a deferred result that was never fetched is discarded
+   without copying it. */
 vls_status vls_result_destroy(struct vls_result *r);
 
 #ifdef __cplusplus

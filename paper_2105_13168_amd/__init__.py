@@ -6,8 +6,8 @@ Only argument marshalling lives here: every step of the method runs in the
 HIP kernels behind the C ABI of ``include/vls.h``.  The functions keep the C
 names (``vls_context_create``, ``vls_mesh_create``, ``vls_run``, ...); the
 small ``Context`` / ``Mesh`` / ``Result`` classes wrap them for tests and the
-benchmark.  The library must have been built (``python -m
-paper_2105_13168_amd.build``); importing fails loudly otherwise.
+benchmark.  The library must have been built (``python
+paper_2105_13168_amd/build.py``); importing fails loudly otherwise.
 """
 from __future__ import annotations
 
@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libvls.so")
 VLS_OK = 0
 VLS_E_BUFFER_TOO_SMALL = -10
 VLS_RECORD_FIELD = 1
+VLS_DEFER_RESULTS = 2
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 
@@ -42,7 +43,8 @@ class vls_summary(C.Structure):
                 ("active_vertex_updates", C.c_int64), ("active_degree_sum", C.c_int64),
                 ("n_inside", C.c_int64), ("seed_vertex", C.c_int64), ("run_status", C.c_int32),
                 ("grid", C.c_int32), ("block", C.c_int32), ("kernel_ms", C.c_double),
-                ("total_ms", C.c_double)]
+                ("total_ms", C.c_double), ("topo_ms", C.c_double), ("wait0_ms", C.c_double),
+                ("field_ms", C.c_double), ("wait1_ms", C.c_double), ("event_steps", C.c_int64)]
 
 
 class vls_reeb_node(C.Structure):
@@ -56,7 +58,7 @@ class vls_reeb_edge(C.Structure):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2105_13168_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2105_13168_amd/build.py`")
 _lib = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 _PP = C.POINTER(C.c_void_p)
@@ -80,6 +82,7 @@ _sig = {
     "vls_result_reeb": (C.c_int32, [_P, C.c_int64, _P, C.c_int64, _P, _I64P, _I64P]),
     "vls_result_field": (C.c_int32, [_P, C.c_int64, _P]),
     "vls_result_vertices": (C.c_int32, [_P, _P, _P, _P]),
+    "vls_result_fetch": (C.c_int32, [_P]),
     "vls_result_destroy": (C.c_int32, [_P]),
 }
 for _n, (_rt, _at) in _sig.items():

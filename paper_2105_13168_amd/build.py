@@ -1,6 +1,8 @@
 """Builds the HIP library libvls.so in-tree for gfx950.
 
-    python -m paper_2105_13168_amd.build
+    python paper_2105_13168_amd/build.py
+
+(run it as a script: importing the package loads the library it builds)
 """
 import os
 import subprocess

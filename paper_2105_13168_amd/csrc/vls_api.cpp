@@ -44,9 +44,22 @@ struct vls_mesh {
     DMesh d{};
     std::vector<void *> allocs;
     RunBuffers *rb = nullptr;
+    vls_result *pending = nullptr;       // run whose results still sit in rb
+};
+
+struct Pending {
+    bool active = false;
+    vls_context *ctx = nullptr;
+    vls_mesh *mesh = nullptr;
+    DState s{};
+    Ctl c{};
+    void *dpos = nullptr, *dtn = nullptr, *dtlen = nullptr;
+    std::vector<void *> tmp_allocs;
+    bool rec_field = false;
 };
 
 struct vls_result {
+    Pending pend;
     vls_summary sum{};
     int64_t nv = 0;
     std::vector<int64_t> ev;             // [n][16]
@@ -346,6 +359,80 @@ static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
     return VLS_OK;
 }
 
+// Copies a run's bulk results from the device; frees the per-run device
+// buffers.  Runs once per result (at the end of vls_run, or on first access
+// for VLS_DEFER_RESULTS, or before the mesh's buffers are reused).
+static vls_status fetch_results(vls_result *r) {
+    Pending &pd = r->pend;
+    if (!pd.active) return VLS_OK;
+    pd.active = false;
+    vls_context *ctx = pd.ctx;
+    if (pd.mesh && pd.mesh->pending == r) pd.mesh->pending = nullptr;
+    const DState &s = pd.s;
+    const Ctl &c = pd.c;
+    hipStream_t stream = ctx->stream;
+    const int64_t nv = r->nv;
+    const int nev = c.n_events, ntn = c.n_tunnels;
+    (void)hipSetDevice(ctx->device);
+    r->ev.resize((size_t)nev * 16);
+    r->ev_ids.resize((size_t)c.ev_ids_used);
+    r->node_pos.resize((size_t)nev * 3);
+    r->front_birth.resize(c.next_front);
+    r->front_death.resize(c.next_front);
+    r->lp.resize((size_t)c.n_loops * 8);
+    r->lp_he.resize((size_t)c.lp_he_used * 2);
+    r->lp_pts.resize((size_t)c.lp_he_used * 3);
+    r->tn.resize((size_t)ntn * 4);
+    r->tn_v.resize(ntn ? (size_t)r->tn_off[ntn] : 0);
+    r->tn_len.resize(ntn);
+    std::vector<uint64_t> key(nv);
+    r->parent.resize(nv);
+    r->rho_final.resize(nv);
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream) : hipSuccess;
+    };
+    HIPCHK(ctx, cp(r->ev.data(), s.ev, r->ev.size() * 8));
+    HIPCHK(ctx, cp(r->ev_ids.data(), s.ev_ids, r->ev_ids.size() * 8));
+    if (nev) HIPCHK(ctx, cp(r->node_pos.data(), pd.dpos, r->node_pos.size() * 8));
+    HIPCHK(ctx, cp(r->front_birth.data(), s.front_birth, r->front_birth.size() * 4));
+    HIPCHK(ctx, cp(r->front_death.data(), s.front_death, r->front_death.size() * 4));
+    HIPCHK(ctx, cp(r->lp.data(), s.lp, r->lp.size() * 8));
+    HIPCHK(ctx, cp(r->lp_he.data(), s.lp_he, r->lp_he.size() * 4));
+    HIPCHK(ctx, cp(r->lp_pts.data(), s.lp_pts, r->lp_pts.size() * 8));
+    HIPCHK(ctx, cp(r->tn.data(), s.tn, r->tn.size() * 4));
+    if (ntn) HIPCHK(ctx, cp(r->tn_v.data(), pd.dtn, r->tn_v.size() * 4));
+    if (ntn) HIPCHK(ctx, cp(r->tn_len.data(), pd.dtlen, ntn * 8));
+    HIPCHK(ctx, cp(key.data(), s.key, nv * 8));
+    HIPCHK(ctx, cp(r->parent.data(), s.parent, nv * 4));
+    const int64_t fin = c.steps;
+    HIPCHK(ctx, cp(r->rho_final.data(), (fin & 1) ? s.rho1 : s.rho0, nv * 8));
+    const int nck = (int)r->ckpt_steps.size();
+    if (pd.rec_field) {
+        r->ckpt.resize((size_t)nck * nv);
+        HIPCHK(ctx, cp(r->ckpt.data(), s.ckpt, r->ckpt.size() * 8));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    for (void *q : {pd.dpos, pd.dtn, pd.dtlen}) if (q) (void)hipFree(q);
+    for (void *q : pd.tmp_allocs) (void)hipFree(q);
+    pd.tmp_allocs.clear();
+    r->step.resize(nv);
+    r->round.resize(nv);
+    for (int64_t v = 0; v < nv; ++v) {
+        if (key[v] == KEY_OUT) { r->step[v] = INT32_MAX; r->round[v] = 0; }
+        else { r->step[v] = (int32_t)(key[v] >> 32); r->round[v] = (int32_t)(key[v] & 0xffffffffu); }
+    }
+    if (pd.rec_field) {
+        r->ckpt_ok.assign(nck, 0);
+        for (int q = 0; q < nck; ++q) {
+            const int64_t st = r->ckpt_steps[q];
+            r->ckpt_ok[q] = st >= 1 && st <= fin;
+        }
+    }
+    return VLS_OK;
+}
+
+static vls_status ensure(const vls_result *r) { return fetch_results(const_cast<vls_result *>(r)); }
+
 extern "C" {
 
 vls_status vls_mesh_create(vls_context *ctx, int64_t nv, const double *xyz, int64_t nf, const int32_t *tri,
@@ -398,6 +485,7 @@ vls_status vls_mesh_info(const vls_mesh *m, int64_t *nv, int64_t *ne, int64_t *n
 
 vls_status vls_mesh_destroy(vls_mesh *m) {
     if (!m) return VLS_E_INVALID_ARG;
+    if (m->pending) (void)fetch_results(m->pending);
     (void)hipSetDevice(m->ctx->device);
     delete m->rb;
     for (void *p : m->allocs) (void)hipFree(p);
@@ -418,6 +506,10 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     *out = nullptr;
     vls_mesh *m = const_cast<vls_mesh *>(mc);
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    if (m->pending) {
+        vls_status fs = fetch_results(m->pending);
+        if (fs) return fs;
+    }
     const int64_t nv = m->nv;
     int64_t seed = p->seed_vertex;
     if (seed < 0) seed = (int64_t)(splitmix64(p->rng_seed) % (uint64_t)nv);
@@ -437,7 +529,7 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     hipStream_t stream = ctx->stream;
     // checkpoint buffers (per run)
     std::vector<void *> tmp_allocs;
-    auto cleanup = [&]() { for (void *q : tmp_allocs) (void)hipFree(q); };
+    auto cleanup = [&]() { for (void *q : tmp_allocs) (void)hipFree(q); tmp_allocs.clear(); };
     s.n_ckpt = 0;
     s.ckpt = nullptr;
     s.ckpt_steps = nullptr;
@@ -496,7 +588,6 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     r->nv = nv;
     std::vector<int64_t> cnt(std::max(nev, ntn) + 1, 0), off;
     void *dcnt = nullptr, *doff = nullptr, *dbuf = nullptr, *dpos = nullptr, *dtn = nullptr;
-    auto dfree = [&]() { for (void *q : {dcnt, doff, dbuf, dpos, dtn}) if (q) (void)hipFree(q); };
     if (nev > 0) {
         HIPCHK(ctx, hipMalloc(&dcnt, (nev + 1) * sizeof(int64_t)));
         HIPCHK(ctx, hipMalloc(&doff, (nev + 1) * sizeof(int64_t)));
@@ -531,67 +622,30 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
         HIPCHK(ctx, launch_tunnel_fill(m->d, s, ntn, (int64_t *)dtoff, (int32_t *)dtn, (double *)dtlen, stream));
     }
     HIPCHK(ctx, hipEventRecord(e3, stream));
-    // results to host
-    r->ev.resize((size_t)nev * 16);
-    r->ev_ids.resize((size_t)c.ev_ids_used);
-    r->node_pos.resize((size_t)nev * 3);
-    r->front_birth.resize(c.next_front);
-    r->front_death.resize(c.next_front);
-    r->lp.resize((size_t)c.n_loops * 8);
-    r->lp_he.resize((size_t)c.lp_he_used * 2);
-    r->lp_pts.resize((size_t)c.lp_he_used * 3);
-    r->tn.resize((size_t)ntn * 4);
-    r->tn_v.resize(ntn ? (size_t)r->tn_off[ntn] : 0);
-    std::vector<uint64_t> key(nv);
-    r->parent.resize(nv);
-    r->rho_final.resize(nv);
-    auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
-        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream) : hipSuccess;
-    };
-    HIPCHK(ctx, cp(r->ev.data(), s.ev, r->ev.size() * 8));
-    HIPCHK(ctx, cp(r->ev_ids.data(), s.ev_ids, r->ev_ids.size() * 8));
-    if (nev) HIPCHK(ctx, cp(r->node_pos.data(), dpos, r->node_pos.size() * 8));
-    HIPCHK(ctx, cp(r->front_birth.data(), s.front_birth, r->front_birth.size() * 4));
-    HIPCHK(ctx, cp(r->front_death.data(), s.front_death, r->front_death.size() * 4));
-    HIPCHK(ctx, cp(r->lp.data(), s.lp, r->lp.size() * 8));
-    HIPCHK(ctx, cp(r->lp_he.data(), s.lp_he, r->lp_he.size() * 4));
-    HIPCHK(ctx, cp(r->lp_pts.data(), s.lp_pts, r->lp_pts.size() * 8));
-    HIPCHK(ctx, cp(r->tn.data(), s.tn, r->tn.size() * 4));
-    r->tn_len.resize(ntn);
-    if (ntn) HIPCHK(ctx, cp(r->tn_v.data(), dtn, r->tn_v.size() * 4));
-    if (ntn) HIPCHK(ctx, cp(r->tn_len.data(), dtlen, ntn * 8));
-    HIPCHK(ctx, cp(key.data(), s.key, nv * 8));
-    HIPCHK(ctx, cp(r->parent.data(), s.parent, nv * 4));
-    const int64_t fin = c.steps;
-    HIPCHK(ctx, cp(r->rho_final.data(), (fin & 1) ? s.rho1 : s.rho0, nv * 8));
-    if (rec_field) {
-        r->ckpt_steps.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
-        r->ckpt.resize((size_t)p->n_ckpt * nv);
-        HIPCHK(ctx, cp(r->ckpt.data(), s.ckpt, r->ckpt.size() * 8));
-    }
     HIPCHK(ctx, hipStreamSynchronize(stream));
     float ms_k = 0.f, ms_t = 0.f;
     (void)hipEventElapsedTime(&ms_k, e1, e2);
     (void)hipEventElapsedTime(&ms_t, e0, e3);
     evdestroy();
-    dfree();
+    if (dcnt) (void)hipFree(dcnt);
+    if (doff) (void)hipFree(doff);
+    if (dbuf) (void)hipFree(dbuf);
     if (dtcnt) (void)hipFree(dtcnt);
     if (dtoff) (void)hipFree(dtoff);
-    if (dtlen) (void)hipFree(dtlen);
-    cleanup();
-    r->step.resize(nv);
-    r->round.resize(nv);
-    for (int64_t v = 0; v < nv; ++v) {
-        if (key[v] == KEY_OUT) { r->step[v] = INT32_MAX; r->round[v] = 0; }
-        else { r->step[v] = (int32_t)(key[v] >> 32); r->round[v] = (int32_t)(key[v] & 0xffffffffu); }
-    }
-    if (rec_field) {
-        r->ckpt_ok.assign(p->n_ckpt, 0);
-        for (int q = 0; q < p->n_ckpt; ++q) {
-            const int64_t st = p->ckpt_steps[q];
-            r->ckpt_ok[q] = st >= 1 && st <= fin;
-        }
-    }
+    // bulk results stay on the device until fetched
+    Pending &pd = r->pend;
+    pd.active = true;
+    pd.ctx = ctx;
+    pd.mesh = m;
+    pd.s = s;
+    pd.c = c;
+    pd.dpos = dpos;
+    pd.dtn = dtn;
+    pd.dtlen = dtlen;
+    pd.tmp_allocs = tmp_allocs;
+    pd.rec_field = rec_field;
+    if (rec_field) r->ckpt_steps.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
+    m->pending = r.get();
     r->seed_xyz.assign(m->xyz.begin() + 3 * seed, m->xyz.begin() + 3 * seed + 3);
     r->mesh_xyz = m->xyz;
     vls_summary &S = r->sum;
@@ -601,9 +655,7 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     S.swept_genus = (int32_t)((2 - c.chi - c.b) / 2);
     S.reeb_nodes = nev + 1;
     S.reeb_edges = c.next_front;
-    int32_t ndeg = 0;
-    for (int i = 0; i < nev; ++i) ndeg += r->ev[16 * (size_t)i + 2] == VLS_NODE_DEGENERATE;
-    S.n_degenerate = ndeg;
+    S.n_degenerate = c.n_degenerate;
     S.n_events = nev;
     S.steps = c.steps;
     S.active_vertex_updates = c.active_updates;
@@ -615,6 +667,11 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     S.block = block;
     S.kernel_ms = ms_k;
     S.total_ms = ms_t;
+    S.topo_ms = (double)c.clk_topo * 1e-5;
+    S.wait0_ms = (double)c.clk_wait0 * 1e-5;
+    S.field_ms = (double)c.clk_field * 1e-5;
+    S.wait1_ms = (double)c.clk_wait1 * 1e-5;
+    S.event_steps = c.event_steps;
     vls_status rs = c.status;
     if (rs == VLS_E_INVARIANT || rs == VLS_E_CAPACITY)
         set_err(ctx, rs, "device reported %s (detail %d) at step %lld", vls_status_string(rs), c.err_code, (long long)c.steps);
@@ -623,6 +680,10 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
                 (long long)c.n_inside, (long long)nv);
     else if (rs == VLS_E_SEED_INVALID)
         set_err(ctx, rs, "seed region around vertex %lld is not a disk-like region", (long long)seed);
+    if (!(p->flags & VLS_DEFER_RESULTS)) {
+        vls_status fs = fetch_results(r.get());
+        if (fs) return fs;
+    }
     *out = r.release();
     return rs;
 }
@@ -635,6 +696,7 @@ vls_status vls_result_summary(const vls_result *r, vls_summary *s) {
 
 vls_status vls_result_events(const vls_result *r, int64_t cap, int64_t *rec, int64_t *n_out) {
     if (!r || !n_out) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
     const int64_t n = (int64_t)r->ev.size() / 16;
     *n_out = n;
     if (cap == 0) return VLS_OK;
@@ -645,6 +707,7 @@ vls_status vls_result_events(const vls_result *r, int64_t cap, int64_t *rec, int
 
 vls_status vls_result_event_fronts(const vls_result *r, int64_t cap, int64_t *ids, int64_t *n_out) {
     if (!r || !n_out) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
     const int64_t n = (int64_t)r->ev_ids.size();
     *n_out = n;
     if (cap == 0) return VLS_OK;
@@ -672,6 +735,7 @@ static bool loop_index(const vls_result *r, int32_t kind, int32_t i, int64_t *li
 vls_status vls_result_loop(const vls_result *r, int32_t kind, int32_t i, int64_t cap, int32_t *edges_uv,
                            double *pts, double *length, int64_t *n_out) {
     if (!r || !n_out) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
     if (kind == 0 || kind == 2) {
         int64_t li;
         if (!loop_index(r, kind, i, &li)) return VLS_E_INVALID_ARG;
@@ -705,6 +769,7 @@ vls_status vls_result_loop(const vls_result *r, int32_t kind, int32_t i, int64_t
 vls_status vls_result_loop_info(const vls_result *r, int32_t kind, int32_t i, int64_t *event, int64_t *front_id,
                                 int32_t *kept) {
     if (!r || (kind != 0 && kind != 2)) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
     int64_t li;
     if (!loop_index(r, kind, i, &li)) return VLS_E_INVALID_ARG;
     if (event) *event = r->lp[8 * li];
@@ -716,6 +781,7 @@ vls_status vls_result_loop_info(const vls_result *r, int32_t kind, int32_t i, in
 vls_status vls_result_reeb(const vls_result *r, int64_t cap_n, vls_reeb_node *nodes, int64_t cap_e,
                            vls_reeb_edge *edges, int64_t *n_nodes, int64_t *n_edges) {
     if (!r || !n_nodes || !n_edges) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
     const int64_t nev = (int64_t)r->ev.size() / 16;
     const int64_t nn = nev + 1, ne = (int64_t)r->front_birth.size();
     *n_nodes = nn;
@@ -754,6 +820,7 @@ vls_status vls_result_reeb(const vls_result *r, int64_t cap_n, vls_reeb_node *no
 
 vls_status vls_result_field(const vls_result *r, int64_t step, double *rho) {
     if (!r || !rho) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
     if (step < 0) {
         std::memcpy(rho, r->rho_final.data(), r->nv * sizeof(double));
         return VLS_OK;
@@ -768,14 +835,29 @@ vls_status vls_result_field(const vls_result *r, int64_t step, double *rho) {
 
 vls_status vls_result_vertices(const vls_result *r, int32_t *step, int32_t *round, int32_t *parent) {
     if (!r) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
     if (step) std::memcpy(step, r->step.data(), r->nv * sizeof(int32_t));
     if (round) std::memcpy(round, r->round.data(), r->nv * sizeof(int32_t));
     if (parent) std::memcpy(parent, r->parent.data(), r->nv * sizeof(int32_t));
     return VLS_OK;
 }
 
+vls_status vls_result_fetch(vls_result *r) {
+    if (!r) return VLS_E_INVALID_ARG;
+    return fetch_results(r);
+}
+
 vls_status vls_result_destroy(vls_result *r) {
     if (!r) return VLS_E_INVALID_ARG;
+    Pending &pd = r->pend;
+    if (pd.active) {
+        // never fetched: drop the device copies without reading them
+        pd.active = false;
+        if (pd.mesh && pd.mesh->pending == r) pd.mesh->pending = nullptr;
+        (void)hipSetDevice(pd.ctx->device);
+        for (void *q : {pd.dpos, pd.dtn, pd.dtlen}) if (q) (void)hipFree(q);
+        for (void *q : pd.tmp_allocs) (void)hipFree(q);
+    }
     delete r;
     return VLS_OK;
 }

@@ -44,7 +44,7 @@ struct Ctl {
     int32_t n_tags;
     int32_t n_loops;
     int32_t n_tunnels;
-    int32_t pad0;
+    int32_t n_degenerate;
     int64_t steps;
     int64_t n_inside;
     int64_t last_insert;
@@ -57,6 +57,9 @@ struct Ctl {
     int64_t gsum_h;
     int64_t gsum_x;
     int64_t event_steps;     // steps that needed the sequential event path
+    // phase clocks (s_memrealtime ticks, 100 MHz): workgroup 0 topology,
+    // workgroup 0 barrier wait, workgroup 1 field, workgroup 1 barrier wait
+    unsigned long long clk_topo, clk_wait0, clk_field, clk_wait1;
 };
 
 // run state in HBM

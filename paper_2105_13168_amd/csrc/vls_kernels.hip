@@ -758,6 +758,7 @@ __device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p,
             }
             ctl->ev_ids_used = idoff + sN + mN;
             ctl->n_events = ev + 1;
+            if (type == NODE_DEGENERATE) ctl->n_degenerate += 1;
             ctl->chi += full ? 1 : 1 - k;
             ctl->b += (long long)mN - sN;
             ctl->gsum_x += xx;
@@ -960,7 +961,9 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
     int *fcnt = (int *)lds;
     int32_t *claims = (int32_t *)(lds + 16);
     if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    unsigned long long c_work = 0, c_wait = 0;
     for (int64_t j = 0;; ++j) {
+        const unsigned long long c0 = __builtin_amdgcn_s_memrealtime();
         if (blockIdx.x == 0) {
             if (threadIdx.x == 0) {
                 ctl->cnt_act[(j + 3) & 3] = 0;
@@ -989,8 +992,16 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
             if (bi < 0) continue;
             for (int64_t i = (int64_t)bi * NT + threadIdx.x; i < m.nv; i += (int64_t)nb * NT) dst[i] = src[i];
         }
+        const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
         grid_sync(ctl, G, epoch);
+        const unsigned long long c2 = __builtin_amdgcn_s_memrealtime();
+        c_work += c1 - c0;
+        c_wait += c2 - c1;
         if (__hip_atomic_load(&ctl->stop[j & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    }
+    if (threadIdx.x == 0 && blockIdx.x <= 1) {
+        if (blockIdx.x == 0) { ctl->clk_topo = c_work; ctl->clk_wait0 = c_wait; }
+        else { ctl->clk_field = c_work; ctl->clk_wait1 = c_wait; }
     }
 }
 
