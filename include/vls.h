@@ -64,6 +64,9 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
 #define VLS_RECORD_FIELD 1u   /* keep FP64 snapshots of the field at ckpt_steps */
 #define VLS_DEFER_RESULTS 2u  /* vls_run returns once the device work is done; bulk results
                                  are copied to the host by vls_result_fetch or on first access */
+#define VLS_TOPO_GLOBAL_PATH 4u  /* always run the topology phase from global memory (the path
+                                    otherwise taken only by steps with more than 1024 crossers);
+                                    results are identical, the flag exists for testing */
 
 /*
  * Parameters.  Defaults (vls_params_default) are the paper's coefficients

@@ -23,6 +23,7 @@ VLS_OK = 0
 VLS_E_BUFFER_TOO_SMALL = -10
 VLS_RECORD_FIELD = 1
 VLS_DEFER_RESULTS = 2
+VLS_TOPO_GLOBAL_PATH = 4
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 

@@ -559,6 +559,7 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     dp.r0 = p->seed_radius;
     dp.stall_steps = p->stall_steps;
     dp.max_steps = p->max_steps;
+    dp.topo_global = (p->flags & VLS_TOPO_GLOBAL_PATH) ? 1 : 0;
     // launch shape
     const size_t lds = step_lds_bytes(block, m->dmax);
     const int maxg = max_coresident_blocks(block, lds);

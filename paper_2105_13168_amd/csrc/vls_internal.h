@@ -108,6 +108,8 @@ struct DParams {
     int32_t r0;
     int32_t stall_steps;
     int64_t max_steps;
+    int32_t topo_global;     // 1: always use the global-memory topology path
+    int32_t pad;
 };
 
 // host launchers (vls_kernels.hip)

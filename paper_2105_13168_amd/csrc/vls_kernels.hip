@@ -263,6 +263,15 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 // ---------------------------------------------------------------------------
 // field phase of step t: rho_t from rho_{t-1} over the update list C_t
 // ---------------------------------------------------------------------------
+#define GB 16   // neighbours gathered per batch (registers)
+
+// claim u for the next update list (de-duplicated by the step stamp)
+__device__ __forceinline__ void claim_one(const DState &s, int32_t u, int32_t next, int32_t *lds_claims,
+                                          int *lds_cnt) {
+    if (s.stamp[u] != next && atomicExch(&s.stamp[u], next) != next)
+        lds_claims[atomicAdd(lds_cnt, 1)] = u;
+}
+
 __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                             int worker, int nworkers, int32_t *lds_claims, int *lds_cnt,
                             int *lds_base) {
@@ -290,34 +299,63 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
         if (i < end) {
             v = list[i];
             const int32_t b = m.rp[v], e = m.rp[v + 1];
+            const int d = e - b;
             const double r = rin[v];
-            double x0 = rin[m.adj[b]];
-            double sum = x0;
-            bool quiet = (r == 0.0 || r == 1.0) && x0 == r;
-            for (int32_t j = b + 1; j < e; ++j) {
-                const double xn = rin[m.adj[j]];
-                sum = sum + xn;
-                quiet = quiet && xn == r;
+            double sum;
+            bool quiet = (r == 0.0 || r == 1.0);
+            if (d <= GB) {
+                // one batch: all neighbour ids, then all neighbour values
+                int32_t nb[GB];
+                double xs[GB];
+#pragma unroll
+                for (int j = 0; j < GB; ++j) nb[j] = j < d ? m.adj[b + j] : v;
+#pragma unroll
+                for (int j = 0; j < GB; ++j) xs[j] = rin[nb[j]];
+                sum = xs[0];
+                quiet = quiet && xs[0] == r;
+#pragma unroll
+                for (int j = 1; j < GB; ++j)
+                    if (j < d) {
+                        sum = sum + xs[j];
+                        quiet = quiet && xs[j] == r;
+                    }
+                if (!quiet) {
+                    // v and its ring may change at step t+1: stamps first, then
+                    // the claiming exchanges, each as one batch
+                    int32_t st[GB + 1];
+                    st[0] = s.stamp[v];
+#pragma unroll
+                    for (int j = 0; j < GB; ++j) st[j + 1] = j < d ? s.stamp[nb[j]] : next;
+                    int32_t ol[GB + 1];
+                    ol[0] = st[0] != next ? atomicExch(&s.stamp[v], next) : next;
+#pragma unroll
+                    for (int j = 0; j < GB; ++j) ol[j + 1] = st[j + 1] != next ? atomicExch(&s.stamp[nb[j]], next) : next;
+                    if (ol[0] != next) lds_claims[atomicAdd(lds_cnt, 1)] = v;
+#pragma unroll
+                    for (int j = 0; j < GB; ++j)
+                        if (ol[j + 1] != next) lds_claims[atomicAdd(lds_cnt, 1)] = nb[j];
+                }
+            } else {
+                sum = rin[m.adj[b]];
+                quiet = quiet && sum == r;
+                for (int32_t j = b + 1; j < e; ++j) {
+                    const double xn = rin[m.adj[j]];
+                    sum = sum + xn;
+                    quiet = quiet && xn == r;
+                }
+                if (!quiet) {
+                    claim_one(s, v, next, lds_claims, lds_cnt);
+                    for (int32_t j = b; j < e; ++j) claim_one(s, m.adj[j], next, lds_claims, lds_cnt);
+                }
             }
-            const double lap = sum - (double)(e - b) * r;
-            const double d = (p.a * lap + p.w * (2.0 * r - 1.0)) + p.e * sqrt(r * (1.0 - r));
-            double x = r + p.c * d;
+            const double lap = sum - (double)d * r;
+            const double dd = (p.a * lap + p.w * (2.0 * r - 1.0)) + p.e * sqrt(r * (1.0 - r));
+            double x = r + p.c * dd;
             if (x < 0.0) x = 0.0;
             if (x > 1.0) x = 1.0;
             rout[v] = x;
             upd += 1;
-            degsum += e - b;
-            if (!quiet) {
-                // v is not a fixed point at step t-1: v and its ring may change
-                // at step t+1
-                if (s.stamp[v] != next && atomicExch(&s.stamp[v], next) != next)
-                    lds_claims[atomicAdd(lds_cnt, 1)] = v;
-                for (int32_t j = b; j < e; ++j) {
-                    const int32_t u = m.adj[j];
-                    if (s.stamp[u] != next && atomicExch(&s.stamp[u], next) != next)
-                        lds_claims[atomicAdd(lds_cnt, 1)] = u;
-                }
-            }
+            degsum += d;
             cand = x > p.tau && s.key[v] == KEY_OUT;
         }
         const unsigned long long mask = __ballot(cand);
@@ -787,8 +825,8 @@ __device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p,
     __threadfence_block();
 }
 
-__device__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, int64_t t,
-                           KSh *sh, uint64_t *lsort) {
+__device__ void phase_topo_global(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+                                  KSh *sh, uint64_t *lsort) {
     Ctl *ctl = s.ctl;
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
     const int tid = threadIdx.x;
@@ -949,6 +987,284 @@ __device__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, in
 }
 
 // ---------------------------------------------------------------------------
+// topology phase, small steps: the step's candidates, their closure rounds,
+// classes and parents live in LDS; an LDS hash maps a vertex to its entry so
+// that same-step neighbours are recognised without re-reading global keys
+// ---------------------------------------------------------------------------
+#define LCAP 1024
+#define HCAP 2048
+#define HBITS 11
+
+struct KL {
+    int32_t Lv[LCAP];       // candidate vertex
+    int32_t Lr[LCAP];       // closure round (-1: not connected)
+    int32_t Lc[LCAP];       // lower arcs (-1: full link)
+    int32_t Lp[LCAP];       // parent vertex
+    int32_t Lq[LCAP];       // link position of the parent
+    uint64_t Lm[LCAP];      // lower-neighbour mask (link positions < 64)
+    int32_t hk[HCAP];       // hash: vertex id (-1 empty)
+    int32_t hv[HCAP];       // hash: entry index
+};
+
+__device__ __forceinline__ uint32_t hslot(int32_t x) { return ((uint32_t)x * 2654435761u) >> (32 - HBITS); }
+
+__device__ __forceinline__ int hfind(const KL *kl, int32_t x) {
+    uint32_t h = hslot(x);
+    for (int g = 0; g < HCAP; ++g) {
+        const int32_t k = kl->hk[h];
+        if (k == x) return kl->hv[h];
+        if (k < 0) return -1;
+        h = (h + 1) & (HCAP - 1);
+    }
+    return -1;
+}
+
+// gathers link positions [c0, c0+GB) of vertex x (counter-clockwise order)
+// and the keys of those neighbours, as one batch each
+__device__ __forceinline__ void gather_link(const DMesh &m, const uint64_t *key, int32_t b, int d, int c0,
+                                            int32_t *nb, uint64_t *kn) {
+#pragma unroll
+    for (int j = 0; j < GB; ++j) nb[j] = c0 + j < d ? m.cyc[b + c0 + j] : -1;
+#pragma unroll
+    for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? key[nb[j]] : KEY_OUT;
+}
+
+__device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+                               KSh *sh, KL *kl, uint64_t *lsort, int nc, int np) {
+    Ctl *ctl = s.ctl;
+    const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
+    const int tid = threadIdx.x;
+    const uint64_t tk = (uint64_t)t << 32;
+    for (int i = tid; i < HCAP; i += NT) kl->hk[i] = -1;
+    if (tid == 0) { sh->nL = 0; sh->nN = 0; sh->nnew = 0; sh->event = 0; sh->npend = 0; }
+    __syncthreads();
+    // 1. candidates, de-duplicated through the hash
+    const int32_t *cl = s.cand[t & 1];
+    const int32_t *pl = s.pend[(t - 1) & 1];
+    for (int i = tid; i < nc + np; i += NT) {
+        const int32_t x = i < nc ? cl[i] : pl[i - nc];
+        // crossers of step t were checked against rho_t by the field phase;
+        // pending ones are re-checked here
+        if (s.key[x] != KEY_OUT || (i >= nc && !(rho[x] > p.tau))) continue;
+        uint32_t h = hslot(x);
+        for (int g = 0; g < HCAP; ++g) {
+            const int32_t old = atomicCAS(&kl->hk[h], -1, x);
+            if (old == -1) {
+                const int slot = atomicAdd(&sh->nL, 1);
+                kl->Lv[slot] = x;
+                kl->Lr[slot] = -1;
+                kl->hv[h] = slot;
+                break;
+            }
+            if (old == x) break;
+            h = (h + 1) & (HCAP - 1);
+        }
+    }
+    __syncthreads();
+    const int nL = sh->nL;
+    if (nL == 0) return;
+    // 2. closure round 0: touches the inside set of step t-1
+    int n0 = 0;
+    for (int i = tid; i < nL; i += NT) {
+        const int32_t x = kl->Lv[i];
+        const int32_t b = m.rp[x];
+        const int d = m.rp[x + 1] - b;
+        bool hit = false;
+        for (int c0 = 0; c0 < d; c0 += GB) {
+            int32_t nb[GB];
+            uint64_t kn[GB];
+            gather_link(m, s.key, b, d, c0, nb, kn);
+#pragma unroll
+            for (int j = 0; j < GB; ++j) hit = hit || kn[j] < tk;
+        }
+        kl->Lr[i] = hit ? 0 : -1;
+        n0 += hit;
+    }
+    if (n0) atomicAdd(&sh->nN, n0);
+    __syncthreads();
+    int nrounds = sh->nN ? 1 : 0;
+    // later rounds (rare): touch the previous round, found through the hash
+    if (sh->nN && sh->nN < nL) {
+        for (int round = 1;; ++round) {
+            for (int i = tid; i < nL; i += NT) {
+                int flag = 0;
+                if (kl->Lr[i] == -1) {
+                    const int32_t x = kl->Lv[i];
+                    for (int32_t j = m.rp[x]; j < m.rp[x + 1] && !flag; ++j) {
+                        const int q = hfind(kl, m.cyc[j]);
+                        if (q >= 0 && kl->Lr[q] == round - 1) flag = 1;
+                    }
+                }
+                kl->Lc[i] = flag;
+            }
+            __syncthreads();
+            int mine = 0;
+            for (int i = tid; i < nL; i += NT)
+                if (kl->Lc[i]) { kl->Lr[i] = round; mine++; }
+            if (tid == 0) sh->nnew = 0;
+            __syncthreads();
+            if (mine) atomicAdd(&sh->nnew, mine);
+            __syncthreads();
+            const int nnew = sh->nnew;
+            if (nnew == 0) break;
+            nrounds = round + 1;
+            __syncthreads();
+            if (tid == 0) sh->nN += nnew;
+            __syncthreads();
+            if (sh->nN == nL) break;
+        }
+    }
+    __syncthreads();
+    // 3. lower-link classification: a neighbour is lower if it was inside
+    //    before step t, or joined in this step with a smaller (round, id)
+    for (int i = tid; i < nL; i += NT) {
+        const int rv = kl->Lr[i];
+        if (rv < 0) continue;
+        const int32_t x = kl->Lv[i];
+        const int32_t b = m.rp[x];
+        const int d = m.rp[x + 1] - b;
+        int nlow = 0, runs = 0, ppos = -1;
+        int32_t par = -1;
+        uint64_t kp = KEY_OUT;
+        bool first = false, prev = false;
+        uint64_t mask = 0;
+        for (int c0 = 0; c0 < d; c0 += GB) {
+            int32_t nb[GB];
+            uint64_t kn[GB];
+            gather_link(m, s.key, b, d, c0, nb, kn);
+#pragma unroll
+            for (int j = 0; j < GB; ++j) {
+                if (c0 + j >= d) continue;
+                const int32_t u = nb[j];
+                uint64_t ku = kn[j];
+                bool low;
+                if (ku < tk) {
+                    low = true;
+                } else {
+                    const int q = hfind(kl, u);
+                    const int ru = q >= 0 ? kl->Lr[q] : -1;
+                    low = ru >= 0 && (ru < rv || (ru == rv && u < x));
+                    ku = tk | (uint64_t)(ru < 0 ? 0 : ru);
+                }
+                if (low) {
+                    nlow++;
+                    if (c0 + j < 64) mask |= 1ull << (c0 + j);
+                    if (c0 + j > 0 && !prev) runs++;
+                    if (par < 0 || rank_lt(ku, u, kp, par)) { par = u; kp = ku; ppos = c0 + j; }
+                }
+                if (c0 + j == 0) first = low;
+                prev = low;
+            }
+        }
+        // a run starts at position 0 unless it continues from the last
+        // position (cyclic link)
+        if (first && !prev) runs++;
+        const int cls = nlow == d ? -1 : runs;
+        kl->Lc[i] = cls;
+        kl->Lp[i] = par;
+        kl->Lq[i] = ppos;
+        kl->Lm[i] = mask;
+        s.key[x] = tk | (uint64_t)rv;
+        s.parent[x] = par;
+        if (cls != 1) atomicOr(&sh->event, 1);
+        if (nlow == 0 || d > MAXDEG) atomicOr(&sh->event, 2);
+    }
+    __syncthreads();
+    if (sh->event & 2) {
+        if (tid == 0) fail(s, ST_INVARIANT, 12);
+    } else if (!sh->event) {
+        // 4a. all insertions regular: the new crossed half-edges take the
+        //     tag of the half-edge (parent -> v), round by round
+        for (int r = 0; r < nrounds; ++r) {
+            for (int i = tid; i < nL; i += NT) {
+                if (kl->Lr[i] != r) continue;
+                const int32_t v = kl->Lv[i];
+                const int32_t b = m.rp[v];
+                const int d = m.rp[v + 1] - b;
+                const int32_t par = kl->Lp[i];
+                const int32_t tag = s.lid[m.rev[b + kl->Lq[i]]];
+                s.depth[v] = s.depth[par] + 1;
+                const uint64_t mask = kl->Lm[i];
+                for (int j = 0; j < d; ++j)
+                    if (!(mask >> j & 1ull)) s.lid[b + j] = tag;
+            }
+            __syncthreads();
+        }
+    } else {
+        // 4b. events: rank order, regular runs in parallel, events by wave 0
+        const int nN = sh->nN;
+        int npow = 1;
+        while (npow < nN) npow <<= 1;
+        uint64_t *arr = npow <= SORTCAP ? lsort : s.ord;
+        for (int i = tid; i < npow; i += NT) arr[i] = ~0ull;
+        __syncthreads();
+        if (tid == 0) sh->nnew = 0;
+        __syncthreads();
+        for (int i = tid; i < nL; i += NT) {
+            if (kl->Lr[i] < 0) continue;
+            const int slot = atomicAdd(&sh->nnew, 1);
+            arr[slot] = ((uint64_t)kl->Lr[i] << 33) | ((uint64_t)kl->Lv[i] << 1) | (uint64_t)(kl->Lc[i] != 1);
+        }
+        __syncthreads();
+        block_bitonic(arr, npow);
+        int pos = 0;
+        while (pos < nN) {
+            int q = pos;
+            while (q < nN && !(arr[q] & 1ull)) q++;
+            int a0 = pos;
+            while (a0 < q) {
+                const int r = (int)(arr[a0] >> 33);
+                int a1 = a0;
+                while (a1 < q && (int)(arr[a1] >> 33) == r) a1++;
+                for (int i = a0 + tid; i < a1; i += NT)
+                    regular_insert(m, s, (int32_t)((arr[i] >> 1) & 0xffffffffull));
+                __syncthreads();
+                a0 = a1;
+            }
+            if (q < nN) {
+                if (tid < WAVE)
+                    resolve_event(m, s, p, t, (int32_t)((arr[q] >> 1) & 0xffffffffull), sh, rho);
+                __syncthreads();
+                if (ld_relaxed(&ctl->status) != 0) break;
+            }
+            pos = q + 1;
+        }
+        if (tid == 0) ctl->event_steps += 1;
+    }
+    // 5. crossers not connected this step wait for the next
+    for (int i = tid; i < nL; i += NT)
+        if (kl->Lr[i] < 0) s.pend[t & 1][atomicAdd(&sh->npend, 1)] = kl->Lv[i];
+    __syncthreads();
+}
+
+__device__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+                           KSh *sh, KL *kl, uint64_t *lsort) {
+    Ctl *ctl = s.ctl;
+    const int nc = ld_relaxed(&ctl->cnt_cand[t & 3]);
+    const int np = ctl->cnt_pend[(t - 1) & 1];
+    if (p.topo_global || nc + np > LCAP) {
+        phase_topo_global(m, s, p, t, sh, lsort);
+        return;
+    }
+    phase_topo_lds(m, s, p, t, sh, kl, lsort, nc, np);
+    if (threadIdx.x == 0) {
+        ctl->cnt_pend[t & 1] = sh->npend;
+        const int nN = sh->nN;
+        ctl->n_inside += nN;
+        if (nN) ctl->last_insert = t;
+        ctl->steps = t;
+        if (ctl->status != 0) {
+            ctl->done = 1;
+        } else if (ctl->n_inside == m.nv) {
+            ctl->done = 1;
+        } else if (t - ctl->last_insert >= p.stall_steps || t >= p.max_steps) {
+            ctl->status = ST_STALLED;
+            ctl->done = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // the persistent step kernel
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
@@ -958,6 +1274,7 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
     Ctl *ctl = s.ctl;
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
+    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
     int *fcnt = (int *)lds;
     int32_t *claims = (int32_t *)(lds + 16);
     if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
@@ -969,7 +1286,7 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->cnt_act[(j + 3) & 3] = 0;
                 ctl->cnt_cand[(j + 2) & 3] = 0;
             }
-            if (j >= 1) phase_topo(m, s, p, j, ksh, lsort);
+            if (j >= 1) phase_topo(m, s, p, j, ksh, kl, lsort);
             __syncthreads();
             // publish this iteration's decision in its own slot: the slot is
             // rewritten two iterations later, after every workgroup read it
@@ -1006,7 +1323,7 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
 }
 
 size_t step_lds_bytes(int block, int dmax) {
-    const size_t kb = ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t);
+    const size_t kb = ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t) + sizeof(KL);
     const size_t fb = 16 + (size_t)block * (dmax + 1) * sizeof(int32_t);
     return kb > fb ? kb : fb;
 }

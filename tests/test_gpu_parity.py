@@ -30,7 +30,8 @@ def _run_both(ctx, oracle_mod, m, ck=(), **kw):
         g = M.run(seed_vertex=m.seed, ckpt_steps=ck, raise_on_error=False, **kw)
     finally:
         M.close()
-    o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed, ckpt_steps=ck, **kw)
+    okw = {k: v for k, v in kw.items() if k not in ("grid", "flags")}
+    o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed, ckpt_steps=ck, **okw)
     return g, o
 
 
@@ -60,6 +61,17 @@ def test_parity_independent_of_launch_shape(ctx, oracle_mod, grid):
     m = mg.multi_torus(2, 28, rng_seed=3)
     g, o = _run_both(ctx, oracle_mod, m, [1, 300, 900], grid=grid)
     assert g.summary["grid"] == grid
+    bad = compare(g, o, m.nv)
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("name,make,ck", SMALL[:1] + SMALL[5:7], ids=["torus", "double_torus", "pretzel48"])
+def test_parity_global_topology_path(ctx, oracle_mod, name, make, ck):
+    """The global-memory topology path (taken by steps with more than 1024
+    crossers) forced on every step gives the same results."""
+    import paper_2105_13168_amd as vls
+    m = make()
+    g, o = _run_both(ctx, oracle_mod, m, ck, flags=vls.VLS_TOPO_GLOBAL_PATH)
     bad = compare(g, o, m.nv)
     assert not bad, bad
 
