@@ -51,6 +51,42 @@ def alg_bytes(updates, degsum):
     return 32 * updates + 4 * degsum
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("vls_kernels.hip", "vls_internal.h"):
+        with open(os.path.join(ROOT, "paper_2105_13168_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_ms):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    runs (FETCH_SIZE, WRITE_SIZE scaled by a copy of known size), as GB/s over
+    the live kernel time; None when the counters were taken on other kernel
+    sources."""
+    path = os.path.join(ROOT, "profiles", "k_steps_pretzel256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t["hbm_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9
+
+
+def copy_calibration(nbytes=1 << 30):
+    """One plain device-to-device copy of nbytes (a kernel of known traffic
+    for scaling the HBM counters)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {nbytes} bytes read and written")
+
+
 def cpu_baseline(m, max_steps):
     import oracle
     oracle.build(force=False)
@@ -72,6 +108,7 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -154,9 +191,12 @@ def main():
             "event_steps": last["event_steps"],
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_steps", "algorithmic_bytes": ab},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms),
+                     "kernel": "k_steps", "algorithmic_bytes": ab,
+                     "kernel_source_hash": kernel_source_hash()},
     }
+    if args.copy_calibration:
+        copy_calibration()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_steps)
     M.close()

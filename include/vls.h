@@ -67,6 +67,9 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
 #define VLS_TOPO_GLOBAL_PATH 4u  /* always run the topology phase from global memory (the path
                                     otherwise taken only by steps with more than 1024 crossers);
                                     results are identical, the flag exists for testing */
+#define VLS_FULL_FENCES 8u       /* share data between workgroups with plain accesses and full
+                                    agent-scope fences at every step barrier instead of coherent
+                                    atomic accesses; identical results, for testing */
 
 /*
  * Parameters.  Defaults (vls_params_default) are the paper's coefficients
@@ -206,6 +209,18 @@ vls_status vls_result_field(const struct vls_result *r, int64_t step, double *rh
    parent (streamline predecessor, -1 for the seed).  Any pointer may be NULL. */
 vls_status vls_result_vertices(const struct vls_result *r, int32_t *step, int32_t *round,
                                int32_t *parent);
+/*
+ * Batched initial passes (many meshes, one launch): each mesh is advanced by
+ * one workgroup of a persistent pool, the largest meshes first; a mesh's
+ * results are identical to a vls_run of that mesh alone.  meshes[n] must be
+ * distinct (a mesh holds one run's device state); per_mesh[n] parameters
+ * (grid of per_mesh[0] = pool size, 0 = as many as fit); out[n] receives one
+ * result per mesh (kernel_ms of each = the whole batch kernel).  Returns the
+ * first non-OK run status, VLS_OK if all succeeded.
+ */
+vls_status vls_batch_run(struct vls_context *ctx, int32_t n, const struct vls_mesh *const *meshes,
+                         const vls_params *per_mesh, struct vls_result **out);
+
 /* Copies the bulk results of a VLS_DEFER_RESULTS run to the host (no-op
    otherwise).  Called implicitly by every accessor, by the next vls_run on
    the same mesh and by vls_mesh_destroy, since a mesh keeps one run's

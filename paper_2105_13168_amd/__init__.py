@@ -24,6 +24,7 @@ VLS_E_BUFFER_TOO_SMALL = -10
 VLS_RECORD_FIELD = 1
 VLS_DEFER_RESULTS = 2
 VLS_TOPO_GLOBAL_PATH = 4
+VLS_FULL_FENCES = 8
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 
@@ -74,6 +75,7 @@ _sig = {
     "vls_mesh_info": (C.c_int32, [_P, _I64P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vls_mesh_destroy": (C.c_int32, [_P]),
     "vls_run": (C.c_int32, [_P, _P, C.POINTER(vls_params), _PP]),
+    "vls_batch_run": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "vls_result_summary": (C.c_int32, [_P, C.POINTER(vls_summary)]),
     "vls_result_events": (C.c_int32, [_P, C.c_int64, _P, _I64P]),
     "vls_result_event_fronts": (C.c_int32, [_P, C.c_int64, _P, _I64P]),
@@ -255,6 +257,31 @@ class Result:
 
     def handle_loops(self):
         return [l for l in self.loops if l["kept"]]
+
+
+def batch_run(ctx: Context, meshes, seeds, raise_on_error: bool = True, **kw):
+    """Many meshes in one launch (one workgroup per mesh); returns one
+    Result per mesh, in input order."""
+    n = len(meshes)
+    hm = (C.c_void_p * n)(*[m.h.value for m in meshes])
+    ps = (vls_params * n)()
+    for i in range(n):
+        ps[i] = default_params(seed_vertex=int(seeds[i]), **kw)
+    outs = (C.c_void_p * n)()
+    st = vls_batch_run(ctx.h, n, hm, ps, outs)
+    if st != VLS_OK and (raise_on_error and st != -7 or not outs[0]):
+        for i in range(n):
+            if outs[i]:
+                vls_result_destroy(C.c_void_p(outs[i]))
+        raise VLSError(st, ctx.last_error())
+    res = []
+    empty = np.zeros(0, dtype=np.int64)
+    for i in range(n):
+        r = Result(C.c_void_p(outs[i]), meshes[i], empty)
+        r.status = r.summary["run_status"]
+        r.error = ""
+        res.append(r)
+    return res
 
 
 def run(xyz, tri, seed_vertex=0, device=0, stream=None, **kw) -> Result:

@@ -500,12 +500,27 @@ static uint64_t splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vls_result **out) {
-    if (!ctx || !mc || !p || !out) return set_err(ctx, VLS_E_INVALID_ARG, "null argument");
+}  // extern "C"
+
+// One run in flight: everything prepared on the host before the launch of
+// the step kernel, and what finishing it needs afterwards.
+struct RunPrep {
+    vls_mesh *m = nullptr;
+    DState s{};
+    DParams dp{};
+    int64_t seed = 0;
+    bool rec_field = false;
+    std::vector<void *> tmp_allocs;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    ~RunPrep() {
+        for (void *q : tmp_allocs) (void)hipFree(q);
+        for (hipEvent_t e : {e0, e1, e2, e3}) if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// checks, device buffers, parameters; enqueues init + seed on the stream
+static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p, RunPrep &rp) {
     if (p->struct_size != sizeof(vls_params)) return set_err(ctx, VLS_E_INVALID_ARG, "vls_params.struct_size mismatch");
-    *out = nullptr;
-    vls_mesh *m = const_cast<vls_mesh *>(mc);
-    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
     if (m->pending) {
         vls_status fs = fetch_results(m->pending);
         if (fs) return fs;
@@ -517,38 +532,32 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     if (p->seed_radius < 0 || p->seed_radius > 1000) return set_err(ctx, VLS_E_INVALID_ARG, "seed_radius");
     if (p->max_steps < 1 || p->max_steps >= INT32_MAX) return set_err(ctx, VLS_E_INVALID_ARG, "max_steps");
     if (p->stall_steps < 1) return set_err(ctx, VLS_E_INVALID_ARG, "stall_steps");
-    const int block = p->block ? p->block : 256;
-    if (block != 256) return set_err(ctx, VLS_E_INVALID_ARG, "block must be 256");
-    const bool rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
+    if (p->block != 0 && p->block != 256) return set_err(ctx, VLS_E_INVALID_ARG, "block must be 256");
+    rp.m = m;
+    rp.seed = seed;
+    rp.rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
     if (!m->rb) {
         vls_status st = make_run_buffers(m, &m->rb);
         if (st) return st;
     }
-    RunBuffers *rb = m->rb;
-    DState s = rb->s;
+    rp.s = m->rb->s;
+    DState &s = rp.s;
     hipStream_t stream = ctx->stream;
-    // checkpoint buffers (per run)
-    std::vector<void *> tmp_allocs;
-    auto cleanup = [&]() { for (void *q : tmp_allocs) (void)hipFree(q); tmp_allocs.clear(); };
     s.n_ckpt = 0;
     s.ckpt = nullptr;
     s.ckpt_steps = nullptr;
-    if (rec_field) {
+    if (rp.rec_field) {
         void *a = nullptr, *b = nullptr;
-        if (hipMalloc(&a, (size_t)p->n_ckpt * nv * sizeof(double)) != hipSuccess ||
-            hipMalloc(&b, (size_t)p->n_ckpt * sizeof(int64_t)) != hipSuccess) {
-            if (a) (void)hipFree(a);
-            return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
-        }
-        tmp_allocs.push_back(a);
-        tmp_allocs.push_back(b);
+        if (hipMalloc(&a, (size_t)p->n_ckpt * nv * sizeof(double)) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
+        rp.tmp_allocs.push_back(a);
+        if (hipMalloc(&b, (size_t)p->n_ckpt * sizeof(int64_t)) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
+        rp.tmp_allocs.push_back(b);
         s.ckpt = (double *)a;
         s.ckpt_steps = (const int64_t *)b;
         s.n_ckpt = p->n_ckpt;
         HIPCHK(ctx, hipMemcpyAsync(b, p->ckpt_steps, (size_t)p->n_ckpt * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-        HIPCHK(ctx, hipMemsetAsync(a, 0xff, (size_t)p->n_ckpt * nv * sizeof(double), stream));
     }
-    DParams dp{};
+    DParams &dp = rp.dp;
     const double dt = p->dt_mode == 1 ? 0.25 / (double)m->dmax : 50.0 / (double)m->dmax;
     dp.tau = p->tau;
     dp.a = p->a;
@@ -560,35 +569,40 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     dp.stall_steps = p->stall_steps;
     dp.max_steps = p->max_steps;
     dp.topo_global = (p->flags & VLS_TOPO_GLOBAL_PATH) ? 1 : 0;
-    // launch shape
-    const size_t lds = step_lds_bytes(block, m->dmax);
-    const int maxg = max_coresident_blocks(block, lds);
-    int grid = p->grid > 0 ? p->grid : 128;
-    if (maxg <= 0) { cleanup(); return set_err(ctx, VLS_E_DEVICE, "occupancy query failed"); }
-    if (grid > maxg) grid = maxg;
-    hipEvent_t e0, e1, e2, e3;
-    HIPCHK(ctx, hipEventCreate(&e0));
-    HIPCHK(ctx, hipEventCreate(&e1));
-    HIPCHK(ctx, hipEventCreate(&e2));
-    HIPCHK(ctx, hipEventCreate(&e3));
-    auto evdestroy = [&]() { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2); (void)hipEventDestroy(e3); };
-    HIPCHK(ctx, hipEventRecord(e0, stream));
+    dp.full_fences = (p->flags & VLS_FULL_FENCES) ? 1 : 0;
+    HIPCHK(ctx, hipEventCreate(&rp.e0));
+    HIPCHK(ctx, hipEventCreate(&rp.e1));
+    HIPCHK(ctx, hipEventCreate(&rp.e2));
+    HIPCHK(ctx, hipEventCreate(&rp.e3));
+    HIPCHK(ctx, hipEventRecord(rp.e0, stream));
     HIPCHK(ctx, hipMemsetAsync(s.ctl, 0, sizeof(Ctl), stream));
     HIPCHK(ctx, launch_init(m->d, s, m->nnz, stream));
     HIPCHK(ctx, launch_seed(m->d, s, dp, stream));
-    HIPCHK(ctx, hipEventRecord(e1, stream));
-    hipError_t le = launch_steps(m->d, s, dp, grid, block, stream);
-    if (le != hipSuccess) { cleanup(); evdestroy(); return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le)); }
-    HIPCHK(ctx, hipEventRecord(e2, stream));
+    HIPCHK(ctx, hipEventRecord(rp.e1, stream));
+    return VLS_OK;
+}
+
+// after the step kernel: post-passes, summary, result object (bulk results
+// deferred until fetched)
+static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p, int grid, int block,
+                             double kernel_ms_override, std::unique_ptr<vls_result> &rout) {
+    vls_mesh *m = rp.m;
+    const DState &s = rp.s;
+    hipStream_t stream = ctx->stream;
+    const int64_t nv = m->nv;
     Ctl c{};
     HIPCHK(ctx, hipMemcpyAsync(&c, s.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     HIPCHK(ctx, hipStreamSynchronize(stream));
-    // post-passes
     const int nev = c.n_events, ntn = c.n_tunnels;
     auto r = std::make_unique<vls_result>();
     r->nv = nv;
     std::vector<int64_t> cnt(std::max(nev, ntn) + 1, 0), off;
     void *dcnt = nullptr, *doff = nullptr, *dbuf = nullptr, *dpos = nullptr, *dtn = nullptr;
+    void *dtcnt = nullptr, *dtoff = nullptr, *dtlen = nullptr;
+    struct Guard {
+        std::vector<void **> ptrs;
+        ~Guard() { for (void **q : ptrs) if (*q) (void)hipFree(*q); }
+    } guard{{&dcnt, &doff, &dbuf, &dtcnt, &dtoff}};
     if (nev > 0) {
         HIPCHK(ctx, hipMalloc(&dcnt, (nev + 1) * sizeof(int64_t)));
         HIPCHK(ctx, hipMalloc(&doff, (nev + 1) * sizeof(int64_t)));
@@ -607,7 +621,6 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
         HIPCHK(ctx, launch_reeb_fill(m->d, s, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dbuf, stream));
         HIPCHK(ctx, launch_reeb_mean(m->d, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dbuf, (double *)dpos, stream));
     }
-    void *dtcnt = nullptr, *dtoff = nullptr, *dtlen = nullptr;
     std::vector<int64_t> tcnt(ntn + 1, 0);
     if (ntn > 0) {
         HIPCHK(ctx, hipMalloc(&dtcnt, (ntn + 1) * sizeof(int64_t)));
@@ -622,17 +635,11 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
         HIPCHK(ctx, hipMalloc(&dtlen, ntn * sizeof(double)));
         HIPCHK(ctx, launch_tunnel_fill(m->d, s, ntn, (int64_t *)dtoff, (int32_t *)dtn, (double *)dtlen, stream));
     }
-    HIPCHK(ctx, hipEventRecord(e3, stream));
+    HIPCHK(ctx, hipEventRecord(rp.e3, stream));
     HIPCHK(ctx, hipStreamSynchronize(stream));
     float ms_k = 0.f, ms_t = 0.f;
-    (void)hipEventElapsedTime(&ms_k, e1, e2);
-    (void)hipEventElapsedTime(&ms_t, e0, e3);
-    evdestroy();
-    if (dcnt) (void)hipFree(dcnt);
-    if (doff) (void)hipFree(doff);
-    if (dbuf) (void)hipFree(dbuf);
-    if (dtcnt) (void)hipFree(dtcnt);
-    if (dtoff) (void)hipFree(dtoff);
+    (void)hipEventElapsedTime(&ms_k, rp.e1, rp.e2);
+    (void)hipEventElapsedTime(&ms_t, rp.e0, rp.e3);
     // bulk results stay on the device until fetched
     Pending &pd = r->pend;
     pd.active = true;
@@ -643,12 +650,12 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     pd.dpos = dpos;
     pd.dtn = dtn;
     pd.dtlen = dtlen;
-    pd.tmp_allocs = tmp_allocs;
-    pd.rec_field = rec_field;
-    if (rec_field) r->ckpt_steps.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
+    pd.tmp_allocs = rp.tmp_allocs;
+    rp.tmp_allocs.clear();
+    pd.rec_field = rp.rec_field;
+    if (rp.rec_field) r->ckpt_steps.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
     m->pending = r.get();
-    r->seed_xyz.assign(m->xyz.begin() + 3 * seed, m->xyz.begin() + 3 * seed + 3);
-    r->mesh_xyz = m->xyz;
+    r->seed_xyz.assign(m->xyz.begin() + 3 * rp.seed, m->xyz.begin() + 3 * rp.seed + 3);
     vls_summary &S = r->sum;
     S.n_handles = (int32_t)c.gsum_h;
     S.n_tunnels = ntn;
@@ -662,11 +669,11 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     S.active_vertex_updates = c.active_updates;
     S.active_degree_sum = c.active_deg;
     S.n_inside = c.n_inside;
-    S.seed_vertex = seed;
+    S.seed_vertex = rp.seed;
     S.run_status = c.status;
     S.grid = grid;
     S.block = block;
-    S.kernel_ms = ms_k;
+    S.kernel_ms = kernel_ms_override >= 0 ? kernel_ms_override : ms_k;
     S.total_ms = ms_t;
     S.topo_ms = (double)c.clk_topo * 1e-5;
     S.wait0_ms = (double)c.clk_wait0 * 1e-5;
@@ -680,13 +687,115 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
         set_err(ctx, rs, "front stalled at step %lld (%lld of %lld vertices inside)", (long long)c.steps,
                 (long long)c.n_inside, (long long)nv);
     else if (rs == VLS_E_SEED_INVALID)
-        set_err(ctx, rs, "seed region around vertex %lld is not a disk-like region", (long long)seed);
+        set_err(ctx, rs, "seed region around vertex %lld is not a disk-like region", (long long)rp.seed);
     if (!(p->flags & VLS_DEFER_RESULTS)) {
         vls_status fs = fetch_results(r.get());
         if (fs) return fs;
     }
+    rout = std::move(r);
+    return rs;
+}
+
+extern "C" {
+
+vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vls_result **out) {
+    if (!ctx || !mc || !p || !out) return set_err(ctx, VLS_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    vls_mesh *m = const_cast<vls_mesh *>(mc);
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    RunPrep rp;
+    vls_status st = prepare_run(ctx, m, p, rp);
+    if (st) return st;
+    const int block = 256;
+    const size_t lds = step_lds_bytes(block, m->dmax);
+    const int maxg = max_coresident_blocks(block, lds);
+    if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
+    int grid = p->grid > 0 ? p->grid : 128;
+    if (grid > maxg) grid = maxg;
+    hipError_t le = launch_steps(m->d, rp.s, rp.dp, grid, block, ctx->stream);
+    if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le));
+    HIPCHK(ctx, hipEventRecord(rp.e2, ctx->stream));
+    std::unique_ptr<vls_result> r;
+    vls_status rs = finish_run(ctx, rp, p, grid, block, -1.0, r);
+    if (!r) return rs;
     *out = r.release();
     return rs;
+}
+
+vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *meshes, const vls_params *per_mesh,
+                         vls_result **out) {
+    if (!ctx || n <= 0 || !meshes || !per_mesh || !out) return set_err(ctx, VLS_E_INVALID_ARG, "bad batch arguments");
+    for (int32_t i = 0; i < n; ++i) {
+        out[i] = nullptr;
+        if (!meshes[i]) return set_err(ctx, VLS_E_INVALID_ARG, "mesh %d is NULL", i);
+        for (int32_t j = 0; j < i; ++j)
+            if (meshes[j] == meshes[i]) return set_err(ctx, VLS_E_INVALID_ARG, "mesh %d appears twice in the batch", i);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    hipStream_t stream = ctx->stream;
+    std::vector<RunPrep> preps(n);
+    std::vector<DMesh> hm(n);
+    std::vector<DState> hs(n);
+    std::vector<DParams> hp(n);
+    size_t lds = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        vls_mesh *m = const_cast<vls_mesh *>(meshes[i]);
+        vls_status st = prepare_run(ctx, m, &per_mesh[i], preps[i]);
+        if (st) return st;
+        hm[i] = m->d;
+        hs[i] = preps[i].s;
+        hp[i] = preps[i].dp;
+        lds = std::max(lds, step_lds_bytes(256, m->dmax));
+    }
+    // largest meshes first, so that the longest runs start early
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return meshes[a]->nv > meshes[b]->nv; });
+    void *dm = nullptr, *ds = nullptr, *dpp = nullptr, *dord = nullptr, *dnext = nullptr;
+    struct Guard {
+        std::vector<void **> ptrs;
+        ~Guard() { for (void **q : ptrs) if (*q) (void)hipFree(*q); }
+    } guard{{&dm, &ds, &dpp, &dord, &dnext}};
+    HIPCHK(ctx, hipMalloc(&dm, n * sizeof(DMesh)));
+    HIPCHK(ctx, hipMalloc(&ds, n * sizeof(DState)));
+    HIPCHK(ctx, hipMalloc(&dpp, n * sizeof(DParams)));
+    HIPCHK(ctx, hipMalloc(&dord, n * sizeof(int32_t)));
+    HIPCHK(ctx, hipMalloc(&dnext, sizeof(int)));
+    HIPCHK(ctx, hipMemcpyAsync(dm, hm.data(), n * sizeof(DMesh), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(ds, hs.data(), n * sizeof(DState), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(dpp, hp.data(), n * sizeof(DParams), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(dord, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemsetAsync(dnext, 0, sizeof(int), stream));
+    const int maxg = max_coresident_batch(lds);
+    if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
+    int grid = per_mesh[0].grid > 0 ? per_mesh[0].grid : maxg;
+    if (grid > n) grid = n;
+    hipEvent_t b0 = nullptr, b1 = nullptr;
+    HIPCHK(ctx, hipEventCreate(&b0));
+    HIPCHK(ctx, hipEventCreate(&b1));
+    HIPCHK(ctx, hipEventRecord(b0, stream));
+    hipError_t le = launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dpp, (const int32_t *)dord, n,
+                                 (int *)dnext, grid, lds, stream);
+    if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "batch kernel launch: %s", hipGetErrorString(le));
+    HIPCHK(ctx, hipEventRecord(b1, stream));
+    HIPCHK(ctx, hipEventSynchronize(b1));
+    float ms_b = 0.f;
+    (void)hipEventElapsedTime(&ms_b, b0, b1);
+    (void)hipEventDestroy(b0);
+    (void)hipEventDestroy(b1);
+    vls_status first = VLS_OK;
+    for (int32_t i = 0; i < n; ++i) {
+        HIPCHK(ctx, hipEventRecord(preps[i].e2, stream));
+        std::unique_ptr<vls_result> r;
+        vls_status rs = finish_run(ctx, preps[i], &per_mesh[i], grid, 256, ms_b, r);
+        if (!r) {
+            for (int32_t j = 0; j < i; ++j) { (void)vls_result_destroy(out[j]); out[j] = nullptr; }
+            return rs;
+        }
+        if (rs && !first) first = rs;
+        out[i] = r.release();
+    }
+    return first;
 }
 
 vls_status vls_result_summary(const vls_result *r, vls_summary *s) {

@@ -109,7 +109,7 @@ struct DParams {
     int32_t stall_steps;
     int64_t max_steps;
     int32_t topo_global;     // 1: always use the global-memory topology path
-    int32_t pad;
+    int32_t full_fences;     // 1: plain shared accesses + full fences at the barrier
 };
 
 // host launchers (vls_kernels.hip)
@@ -118,6 +118,9 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int grid, int block,
                         hipStream_t st);
 int max_coresident_blocks(int block, size_t lds_bytes);
+hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order, int n,
+                        int *next_mesh, int grid, size_t lds, hipStream_t st);
+int max_coresident_batch(size_t lds_bytes);
 size_t step_lds_bytes(int block, int dmax);
 hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt,
                              hipStream_t st);

@@ -45,17 +45,52 @@ __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Data written by one workgroup and read by another inside the step kernel
+// (field buffers, update / candidate lists, the key hint) go through these
+// accessors.  CM = 1: agent-scope relaxed atomics, coherent across the XCDs'
+// separate L2 caches by themselves, so the grid barrier needs no acquire-side
+// cache invalidation and read-only mesh data stays cached between steps.
+// CM = 0: plain accesses, made coherent by full agent-scope fences at the
+// barrier.
+template <int CM> __device__ __forceinline__ double ldx(const double *p) {
+    if constexpr (CM) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <int CM> __device__ __forceinline__ void stx(double *p, double v) {
+    if constexpr (CM) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <int CM> __device__ __forceinline__ int32_t ldx(const int32_t *p) {
+    if constexpr (CM) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <int CM> __device__ __forceinline__ void stx(int32_t *p, int32_t v) {
+    if constexpr (CM) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <int CM> __device__ __forceinline__ uint64_t ldx(const uint64_t *p) {
+    if constexpr (CM) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+
 // Grid barrier over all co-resident workgroups: monotonic arrival counter.
+// Release side: every wave's stores complete (__syncthreads), then an
+// agent-scope release by the arriving thread.  Acquire side: CM = 0 a full
+// agent-scope fence; CM = 1 only an ordering point (shared data is read
+// with coherent loads).
+template <int CM>
 __device__ __forceinline__ void grid_sync(Ctl *ctl, unsigned long long G, unsigned long long &epoch) {
     __syncthreads();
     if (threadIdx.x == 0) {
         epoch += 1;
         const unsigned long long target = epoch * G;
-        __threadfence();
+        if constexpr (CM) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        else __threadfence();
         atomicAdd(&ctl->bar, 1ull);
         while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
             __builtin_amdgcn_s_sleep(1);
-        __threadfence();
+        if constexpr (CM) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        else __threadfence();
     }
     __syncthreads();
 }
@@ -272,6 +307,7 @@ __device__ __forceinline__ void claim_one(const DState &s, int32_t u, int32_t ne
         lds_claims[atomicAdd(lds_cnt, 1)] = u;
 }
 
+template <int CM>
 __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                             int worker, int nworkers, int32_t *lds_claims, int *lds_cnt,
                             int *lds_base) {
@@ -297,10 +333,10 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
         bool cand = false;
         int32_t v = -1;
         if (i < end) {
-            v = list[i];
+            v = ldx<CM>(list + i);
             const int32_t b = m.rp[v], e = m.rp[v + 1];
             const int d = e - b;
-            const double r = rin[v];
+            const double r = ldx<CM>(rin + v);
             double sum;
             bool quiet = (r == 0.0 || r == 1.0);
             if (d <= GB) {
@@ -310,7 +346,7 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
 #pragma unroll
                 for (int j = 0; j < GB; ++j) nb[j] = j < d ? m.adj[b + j] : v;
 #pragma unroll
-                for (int j = 0; j < GB; ++j) xs[j] = rin[nb[j]];
+                for (int j = 0; j < GB; ++j) xs[j] = ldx<CM>(rin + nb[j]);
                 sum = xs[0];
                 quiet = quiet && xs[0] == r;
 #pragma unroll
@@ -336,10 +372,10 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
                         if (ol[j + 1] != next) lds_claims[atomicAdd(lds_cnt, 1)] = nb[j];
                 }
             } else {
-                sum = rin[m.adj[b]];
+                sum = ldx<CM>(rin + m.adj[b]);
                 quiet = quiet && sum == r;
                 for (int32_t j = b + 1; j < e; ++j) {
-                    const double xn = rin[m.adj[j]];
+                    const double xn = ldx<CM>(rin + m.adj[j]);
                     sum = sum + xn;
                     quiet = quiet && xn == r;
                 }
@@ -353,10 +389,10 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
             double x = r + p.c * dd;
             if (x < 0.0) x = 0.0;
             if (x > 1.0) x = 1.0;
-            rout[v] = x;
+            stx<CM>(rout + v, x);
             upd += 1;
             degsum += d;
-            cand = x > p.tau && s.key[v] == KEY_OUT;
+            cand = x > p.tau && ldx<CM>(s.key + v) == KEY_OUT;
         }
         const unsigned long long mask = __ballot(cand);
         if (mask) {
@@ -364,7 +400,7 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
             const int leader = __ffsll((long long)mask) - 1;
             if (lane == leader) cb = atomicAdd(clc, __popcll(mask));
             cb = __shfl(cb, leader);
-            if (cand) cl[cb + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+            if (cand) stx<CM>(cl + cb + __popcll(mask & ((1ull << lane) - 1ull)), v);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -373,7 +409,7 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
         }
         __syncthreads();
         const int c = *lds_cnt, b0 = *lds_base;
-        for (int j = threadIdx.x; j < c; j += NT) out[b0 + j] = lds_claims[j];
+        for (int j = threadIdx.x; j < c; j += NT) stx<CM>(out + b0 + j, lds_claims[j]);
         __syncthreads();
     }
     // wave reduction of the counters, one atomic per wave
@@ -462,9 +498,10 @@ __device__ __forceinline__ void regular_insert(const DMesh &m, const DState &s, 
 }
 
 // crossing point of edge (u inside, x outside) at the threshold
+template <int CM>
 __device__ __forceinline__ void crossing_point(const DMesh &m, const double *rho, int32_t u,
                                                int32_t x, double tau, double *pt) {
-    const double ru = rho[u], rx = rho[x];
+    const double ru = ldx<CM>(rho + u), rx = ldx<CM>(rho + x);
     const double den = ru - rx;
     double t;
     if (den <= 0.0) {
@@ -482,6 +519,7 @@ __device__ __forceinline__ void crossing_point(const DMesh &m, const double *rho
 
 // Saddle or vanish insertion of v at step t, resolved by wave 0 (all 64
 // lanes call it with the same v).
+template <int CM>
 __device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                               int32_t v, KSh *sh, const double *rho) {
     Ctl *ctl = s.ctl;
@@ -613,7 +651,7 @@ __device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p,
                 const int32_t uu = m.src[e], xx = m.cyc[e];
                 s.lp_he[2 * pos] = uu;
                 s.lp_he[2 * pos + 1] = xx;
-                crossing_point(m, rho, uu, xx, p.tau, s.lp_pts + 3 * pos);
+                crossing_point<CM>(m, rho, uu, xx, p.tau, s.lp_pts + 3 * pos);
                 i++;
                 e = he_next(m, s.key, e, kv, v, false);
             } while (e != e0);
@@ -825,6 +863,7 @@ __device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p,
     __threadfence_block();
 }
 
+template <int CM>
 __device__ void phase_topo_global(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                                   KSh *sh, uint64_t *lsort) {
     Ctl *ctl = s.ctl;
@@ -838,8 +877,8 @@ __device__ void phase_topo_global(const DMesh &m, const DState &s, const DParams
     const int32_t *cl = s.cand[t & 1];
     const int32_t *pl = s.pend[(t - 1) & 1];
     for (int i = tid; i < nc + np; i += NT) {
-        const int32_t x = i < nc ? cl[i] : pl[i - nc];
-        if (s.key[x] == KEY_OUT && rho[x] > p.tau) {
+        const int32_t x = i < nc ? ldx<CM>(cl + i) : pl[i - nc];
+        if (s.key[x] == KEY_OUT && ldx<CM>(rho + x) > p.tau) {
             if (atomicExch(&s.cstamp[x], (int32_t)t) != (int32_t)t) {
                 const int slot = atomicAdd(&sh->nL, 1);
                 s.L[slot] = x;
@@ -956,7 +995,7 @@ __device__ void phase_topo_global(const DMesh &m, const DState &s, const DParams
                 }
                 if (q < nN) {
                     if (tid < WAVE)
-                        resolve_event(m, s, p, t, (int32_t)((arr[q] >> 1) & 0xffffffffull), sh, rho);
+                        resolve_event<CM>(m, s, p, t, (int32_t)((arr[q] >> 1) & 0xffffffffull), sh, rho);
                     __syncthreads();
                     if (ld_relaxed(&ctl->status) != 0) break;
                 }
@@ -1029,6 +1068,7 @@ __device__ __forceinline__ void gather_link(const DMesh &m, const uint64_t *key,
     for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? key[nb[j]] : KEY_OUT;
 }
 
+template <int CM>
 __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                                KSh *sh, KL *kl, uint64_t *lsort, int nc, int np) {
     Ctl *ctl = s.ctl;
@@ -1042,10 +1082,10 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
     const int32_t *cl = s.cand[t & 1];
     const int32_t *pl = s.pend[(t - 1) & 1];
     for (int i = tid; i < nc + np; i += NT) {
-        const int32_t x = i < nc ? cl[i] : pl[i - nc];
+        const int32_t x = i < nc ? ldx<CM>(cl + i) : pl[i - nc];
         // crossers of step t were checked against rho_t by the field phase;
         // pending ones are re-checked here
-        if (s.key[x] != KEY_OUT || (i >= nc && !(rho[x] > p.tau))) continue;
+        if (s.key[x] != KEY_OUT || (i >= nc && !(ldx<CM>(rho + x) > p.tau))) continue;
         uint32_t h = hslot(x);
         for (int g = 0; g < HCAP; ++g) {
             const int32_t old = atomicCAS(&kl->hk[h], -1, x);
@@ -1223,7 +1263,7 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
             }
             if (q < nN) {
                 if (tid < WAVE)
-                    resolve_event(m, s, p, t, (int32_t)((arr[q] >> 1) & 0xffffffffull), sh, rho);
+                    resolve_event<CM>(m, s, p, t, (int32_t)((arr[q] >> 1) & 0xffffffffull), sh, rho);
                 __syncthreads();
                 if (ld_relaxed(&ctl->status) != 0) break;
             }
@@ -1237,16 +1277,17 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
     __syncthreads();
 }
 
+template <int CM>
 __device__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                            KSh *sh, KL *kl, uint64_t *lsort) {
     Ctl *ctl = s.ctl;
     const int nc = ld_relaxed(&ctl->cnt_cand[t & 3]);
     const int np = ctl->cnt_pend[(t - 1) & 1];
     if (p.topo_global || nc + np > LCAP) {
-        phase_topo_global(m, s, p, t, sh, lsort);
+        phase_topo_global<CM>(m, s, p, t, sh, lsort);
         return;
     }
-    phase_topo_lds(m, s, p, t, sh, kl, lsort, nc, np);
+    phase_topo_lds<CM>(m, s, p, t, sh, kl, lsort, nc, np);
     if (threadIdx.x == 0) {
         ctl->cnt_pend[t & 1] = sh->npend;
         const int nN = sh->nN;
@@ -1267,6 +1308,7 @@ __device__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, in
 // ---------------------------------------------------------------------------
 // the persistent step kernel
 // ---------------------------------------------------------------------------
+template <int CM>
 __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
     extern __shared__ __align__(16) unsigned char lds[];
     const unsigned G = gridDim.x;
@@ -1286,7 +1328,7 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->cnt_act[(j + 3) & 3] = 0;
                 ctl->cnt_cand[(j + 2) & 3] = 0;
             }
-            if (j >= 1) phase_topo(m, s, p, j, ksh, kl, lsort);
+            if (j >= 1) phase_topo<CM>(m, s, p, j, ksh, kl, lsort);
             __syncthreads();
             // publish this iteration's decision in its own slot: the slot is
             // rewritten two iterations later, after every workgroup read it
@@ -1294,10 +1336,10 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->stop[j & 1] = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (G == 1) {
                 __syncthreads();
-                phase_field(m, s, p, j + 1, 0, 1, claims, fcnt, fcnt + 1);
+                phase_field<CM>(m, s, p, j + 1, 0, 1, claims, fcnt, fcnt + 1);
             }
         } else {
-            phase_field(m, s, p, j + 1, blockIdx.x - 1, G - 1, claims, fcnt, fcnt + 1);
+            phase_field<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1, claims, fcnt, fcnt + 1);
         }
         // field snapshots of step j (its buffer is not written in this iteration)
         for (int q = 0; q < s.n_ckpt; ++q) {
@@ -1307,10 +1349,10 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
             const int nb = G > 1 ? G - 1 : 1;
             const int bi = G > 1 ? (int)blockIdx.x - 1 : 0;
             if (bi < 0) continue;
-            for (int64_t i = (int64_t)bi * NT + threadIdx.x; i < m.nv; i += (int64_t)nb * NT) dst[i] = src[i];
+            for (int64_t i = (int64_t)bi * NT + threadIdx.x; i < m.nv; i += (int64_t)nb * NT) dst[i] = ldx<CM>(src + i);
         }
         const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
-        grid_sync(ctl, G, epoch);
+        grid_sync<CM>(ctl, G, epoch);
         const unsigned long long c2 = __builtin_amdgcn_s_memrealtime();
         c_work += c1 - c0;
         c_wait += c2 - c1;
@@ -1322,6 +1364,77 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// batched mode: many meshes in one launch.  A persistent pool of workgroups
+// pulls meshes (largest first) from a counter; one workgroup advances one
+// mesh through all its steps, topology of step t then field of step t+1,
+// separated by workgroup barriers only (no grid barrier, no cross-workgroup
+// sharing inside a mesh).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss, const DParams *ps,
+                                              const int32_t *order, int n, int *next_mesh) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int cur;
+    KSh *ksh = (KSh *)lds;
+    uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
+    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
+    int *fcnt = (int *)lds;
+    int32_t *claims = (int32_t *)(lds + 16);
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(next_mesh, 1);
+        __syncthreads();
+        const int w = cur;
+        __syncthreads();
+        if (w >= n) break;
+        const int mi = order[w];
+        const DMesh m = ms[mi];
+        const DState s = ss[mi];
+        const DParams p = ps[mi];
+        Ctl *ctl = s.ctl;
+        const unsigned long long c_start = __builtin_amdgcn_s_memrealtime();
+        if (!ctl->done) {
+            for (int64_t j = 0;; ++j) {
+                if (threadIdx.x == 0) {
+                    ctl->cnt_act[(j + 3) & 3] = 0;
+                    ctl->cnt_cand[(j + 2) & 3] = 0;
+                }
+                __syncthreads();
+                if (j >= 1) phase_topo<0>(m, s, p, j, ksh, kl, lsort);
+                __syncthreads();
+                const int stop = ctl->done;
+                __syncthreads();
+                if (stop) break;
+                phase_field<0>(m, s, p, j + 1, 0, 1, claims, fcnt, fcnt + 1);
+                for (int q = 0; q < s.n_ckpt; ++q) {
+                    if (s.ckpt_steps[q] != j || j == 0) continue;
+                    const double *src = (j & 1) ? s.rho1 : s.rho0;
+                    double *dst = s.ckpt + (int64_t)q * m.nv;
+                    for (int64_t i = threadIdx.x; i < m.nv; i += NT) dst[i] = src[i];
+                }
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x == 0) ctl->clk_topo = __builtin_amdgcn_s_memrealtime() - c_start;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order, int n,
+                        int *next_mesh, int grid, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(NT), lds, st, ms, ss, ps, order, n, next_mesh);
+    return hipGetLastError();
+}
+
+int max_coresident_batch(size_t lds_bytes) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, NT, lds_bytes) != hipSuccess) return 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return per_cu * cus;
+}
+
 size_t step_lds_bytes(int block, int dmax) {
     const size_t kb = ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t) + sizeof(KL);
     const size_t fb = 16 + (size_t)block * (dmax + 1) * sizeof(int32_t);
@@ -1330,7 +1443,7 @@ size_t step_lds_bytes(int block, int dmax) {
 
 int max_coresident_blocks(int block, size_t lds_bytes) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_steps, block, lds_bytes) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_steps<1>, block, lds_bytes) != hipSuccess)
         return 0;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -1346,8 +1459,8 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
     DState ss = s;
     DParams pp = p;
     void *args[] = {&mm, &ss, &pp};
-    return hipLaunchCooperativeKernel((const void *)k_steps, dim3(grid), dim3(block), args,
-                                      (unsigned)lds, st);
+    const void *fn = p.full_fences ? (const void *)k_steps<0> : (const void *)k_steps<1>;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -76,6 +76,18 @@ def test_parity_global_topology_path(ctx, oracle_mod, name, make, ck):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("name,make,ck", [SMALL[0], SMALL[6]], ids=["torus", "pretzel48"])
+def test_parity_full_fence_variant(ctx, oracle_mod, name, make, ck):
+    """Sharing data between workgroups through plain accesses plus full
+    fences at every barrier gives the same results as the coherent-access
+    default."""
+    import paper_2105_13168_amd as vls
+    m = make()
+    g, o = _run_both(ctx, oracle_mod, m, ck, flags=vls.VLS_FULL_FENCES)
+    bad = compare(g, o, m.nv)
+    assert not bad, bad
+
+
 def test_parity_dt_literal_and_radius(ctx, oracle_mod):
     # literal dt = 0.25/dmax on a tiny torus; and a radius-1 / radius-3 seed
     m = mg.torus_grid(16, 8, R=1.0, r=0.4, jitter=1e-3, rng_seed=5)
