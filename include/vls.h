@@ -160,6 +160,8 @@ typedef struct {
        topology work and its barrier wait, workgroup 1 field work and wait */
     double topo_ms, wait0_ms, field_ms, wait1_ms;
     int64_t event_steps;       /* steps resolved through the sequential event path           */
+    double topo_split_ms[4];   /* topology: candidates, closure, classification, insert/events */
+    double field_split_ms[3];  /* field (workgroup 1): gather + update, claims, list flush     */
 } vls_summary;
 vls_status vls_result_summary(const struct vls_result *r, vls_summary *s);
 

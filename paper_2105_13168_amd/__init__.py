@@ -46,7 +46,8 @@ class vls_summary(C.Structure):
                 ("n_inside", C.c_int64), ("seed_vertex", C.c_int64), ("run_status", C.c_int32),
                 ("grid", C.c_int32), ("block", C.c_int32), ("kernel_ms", C.c_double),
                 ("total_ms", C.c_double), ("topo_ms", C.c_double), ("wait0_ms", C.c_double),
-                ("field_ms", C.c_double), ("wait1_ms", C.c_double), ("event_steps", C.c_int64)]
+                ("field_ms", C.c_double), ("wait1_ms", C.c_double), ("event_steps", C.c_int64),
+                ("topo_split_ms", C.c_double * 4), ("field_split_ms", C.c_double * 3)]
 
 
 class vls_reeb_node(C.Structure):

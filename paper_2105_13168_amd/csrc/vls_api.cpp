@@ -342,7 +342,7 @@ static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
     hipError_t e = hipSuccess;
 #define A(ptr, n) if (e == hipSuccess) e = dalloc(rb.get(), &(ptr), (n))
     A(s.rho0, nv); A(s.rho1, nv); A(s.key, nv); A(s.parent, nv); A(s.depth, nv);
-    A(s.lid, nnz); A(s.stamp, nv); A(s.cstamp, nv);
+    A(s.lid, nnz); A(s.stamp, nv); A(s.cstamp, nv); A(s.mark[0], nv); A(s.mark[1], nv);
     A(s.act[0], nv); A(s.act[1], nv); A(s.cand[0], nv); A(s.cand[1], nv);
     A(s.pend[0], nv); A(s.pend[1], nv); A(s.L, nv); A(s.Lrnd, nv); A(s.Lcls, nv);
     A(s.ord, npow);
@@ -680,6 +680,8 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     S.field_ms = (double)c.clk_field * 1e-5;
     S.wait1_ms = (double)c.clk_wait1 * 1e-5;
     S.event_steps = c.event_steps;
+    for (int q = 0; q < 4; ++q) S.topo_split_ms[q] = (double)c.clk_t[q] * 1e-5;
+    for (int q = 0; q < 3; ++q) S.field_split_ms[q] = (double)c.clk_f[q] * 1e-5;
     vls_status rs = c.status;
     if (rs == VLS_E_INVARIANT || rs == VLS_E_CAPACITY)
         set_err(ctx, rs, "device reported %s (detail %d) at step %lld", vls_status_string(rs), c.err_code, (long long)c.steps);

@@ -60,6 +60,9 @@ struct Ctl {
     // phase clocks (s_memrealtime ticks, 100 MHz): workgroup 0 topology,
     // workgroup 0 barrier wait, workgroup 1 field, workgroup 1 barrier wait
     unsigned long long clk_topo, clk_wait0, clk_field, clk_wait1;
+    // finer split: topology (gather, closure, classify, insert/events),
+    // field on workgroup 1 (gather+update, claims, list flush)
+    unsigned long long clk_t[4], clk_f[3];
 };
 
 // run state in HBM
@@ -69,7 +72,8 @@ struct DState {
     int32_t *parent;         // [nv]
     int32_t *depth;          // [nv]
     int32_t *lid;            // [nnz] front tag of a crossed half-edge (inside -> outside)
-    int32_t *stamp;          // [nv] update-list claims (step number)
+    int32_t *stamp;          // [nv] claims of new list entries (step number)
+    int32_t *mark[2];        // [nv] update-set membership per step parity (step number)
     int32_t *cstamp;         // [nv] candidate de-duplication (step number)
     int32_t *act[2];         // [nv] update lists (step parity)
     int32_t *cand[2];        // [nv] crosser candidates (step parity)

@@ -127,6 +127,8 @@ __global__ void k_init(DState s, int32_t nv, int64_t nnz) {
             s.parent[i] = -1;
             s.depth[i] = 0;
             s.stamp[i] = 0;
+            s.mark[0][i] = 0;
+            s.mark[1][i] = 0;
             s.cstamp[i] = -1;
         }
     }
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
     int32_t *list = s.L;       // BFS order, hop in Lrnd
     if (tid == 0) {
         sh.n = 1; sh.layer_beg = 0; sh.layer_end = 1; sh.nball = 0; sh.ne = 0; sh.nf = 0;
-        sh.nloops = 0; sh.bad = 0;
+        sh.nloops = 0; sh.bad = 0; sh.add = 0;
         list[0] = (int32_t)p.seed;
         s.Lrnd[0] = 0;
         s.cstamp[p.seed] = -2;
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
             myball++;
         }
         s.act[1][i] = v;
-        s.stamp[v] = 1;
+        s.mark[1][v] = 1;
     }
     atomicAdd(&sh.nball, myball);
     __syncthreads();
@@ -300,17 +302,21 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 // ---------------------------------------------------------------------------
 #define GB 16   // neighbours gathered per batch (registers)
 
-// claim u for the next update list (de-duplicated by the step stamp)
-__device__ __forceinline__ void claim_one(const DState &s, int32_t u, int32_t next, int32_t *lds_claims,
-                                          int *lds_cnt) {
-    if (s.stamp[u] != next && atomicExch(&s.stamp[u], next) != next)
-        lds_claims[atomicAdd(lds_cnt, 1)] = u;
-}
-
+// Field phase of step t: rho_t from rho_{t-1} over the update set C_t.
+//
+// C_t = A_{t-2} u N(A_{t-2}), A_s = vertices that are not fixed points of
+// the step at rho_s (a value 0 or 1 with every neighbour equal is rewritten
+// unchanged).  Every vertex that can change at step t is in C_t, so the
+// double buffer stays exact for the others.  Membership is kept in a mark
+// array per step parity: while computing step t, a vertex of A_{t-1} writes
+// mark[t+1] on itself and its ring (plain stores, all writers store the same
+// value); C_{t+1} = {mark == t+1}.  The list L_t handed to step t+1 holds
+// C_t (each member appends itself) plus the neighbours of A_{t-1} outside
+// C_t (claimed once through an exchange on a step stamp); a listed vertex
+// whose mark says it is not in C_{t+1} is dropped by step t+1.
 template <int CM>
 __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
-                            int worker, int nworkers, int32_t *lds_claims, int *lds_cnt,
-                            int *lds_base) {
+                            int worker, int nworkers) {
     Ctl *ctl = s.ctl;
     const int n = ld_relaxed(&ctl->cnt_act[t & 3]);
     const int32_t *__restrict__ list = s.act[t & 1];
@@ -318,81 +324,119 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
     int *outcnt = &ctl->cnt_act[(t + 1) & 3];
     const double *__restrict__ rin = ((t - 1) & 1) ? s.rho1 : s.rho0;
     double *__restrict__ rout = (t & 1) ? s.rho1 : s.rho0;
+    const int32_t *__restrict__ mk_cur = s.mark[t & 1];
+    int32_t *__restrict__ mk_next = s.mark[(t + 1) & 1];
     int32_t *__restrict__ cl = s.cand[t & 1];
     int *clc = &ctl->cnt_cand[t & 3];
-    const int32_t next = (int32_t)(t + 1);
+    const int32_t cur = (int32_t)t, next = (int32_t)(t + 1);
+    const int lane = __lane_id();
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const int per = (n + nworkers - 1) / nworkers;
     const int beg = worker * per;
     const int end = min(n, beg + per);
-    const int lane = __lane_id();
     long long upd = 0, degsum = 0;
     for (int base = beg; base < end; base += NT) {
-        if (threadIdx.x == 0) *lds_cnt = 0;
-        __syncthreads();
         const int i = base + threadIdx.x;
-        bool cand = false;
+        bool cand = false, keep = false;
         int32_t v = -1;
+        uint32_t cmask = 0;          // bit j: neighbour nb[j] claimed as new
+        int32_t nb[GB];
         if (i < end) {
             v = ldx<CM>(list + i);
             const int32_t b = m.rp[v], e = m.rp[v + 1];
+            keep = ldx<CM>(mk_cur + v) == cur;
             const int d = e - b;
-            const double r = ldx<CM>(rin + v);
-            double sum;
-            bool quiet = (r == 0.0 || r == 1.0);
-            if (d <= GB) {
-                // one batch: all neighbour ids, then all neighbour values
-                int32_t nb[GB];
-                double xs[GB];
+            if (keep) {
+                const double r = ldx<CM>(rin + v);
+                double sum;
+                bool quiet = (r == 0.0 || r == 1.0);
+                if (d <= GB) {
+                    // one batch: neighbour ids; then values and membership marks
+                    double xs[GB];
+                    int32_t mu[GB];
 #pragma unroll
-                for (int j = 0; j < GB; ++j) nb[j] = j < d ? m.adj[b + j] : v;
+                    for (int j = 0; j < GB; ++j) nb[j] = j < d ? m.adj[b + j] : v;
 #pragma unroll
-                for (int j = 0; j < GB; ++j) xs[j] = ldx<CM>(rin + nb[j]);
-                sum = xs[0];
-                quiet = quiet && xs[0] == r;
+                    for (int j = 0; j < GB; ++j) xs[j] = ldx<CM>(rin + nb[j]);
 #pragma unroll
-                for (int j = 1; j < GB; ++j)
-                    if (j < d) {
-                        sum = sum + xs[j];
-                        quiet = quiet && xs[j] == r;
+                    for (int j = 0; j < GB; ++j) mu[j] = ldx<CM>(mk_cur + nb[j]);
+                    sum = xs[0];
+                    quiet = quiet && xs[0] == r;
+#pragma unroll
+                    for (int j = 1; j < GB; ++j)
+                        if (j < d) {
+                            sum = sum + xs[j];
+                            quiet = quiet && xs[j] == r;
+                        }
+                    if (!quiet) {
+                        stx<CM>(mk_next + v, next);
+#pragma unroll
+                        for (int j = 0; j < GB; ++j)
+                            if (j < d) {
+                                stx<CM>(mk_next + nb[j], next);
+                                // outside C_t: not listed by itself, claim it once
+                                if (mu[j] != cur && s.stamp[nb[j]] != next &&
+                                    atomicExch(&s.stamp[nb[j]], next) != next)
+                                    cmask |= 1u << j;
+                            }
                     }
-                if (!quiet) {
-                    // v and its ring may change at step t+1: stamps first, then
-                    // the claiming exchanges, each as one batch
-                    int32_t st[GB + 1];
-                    st[0] = s.stamp[v];
-#pragma unroll
-                    for (int j = 0; j < GB; ++j) st[j + 1] = j < d ? s.stamp[nb[j]] : next;
-                    int32_t ol[GB + 1];
-                    ol[0] = st[0] != next ? atomicExch(&s.stamp[v], next) : next;
-#pragma unroll
-                    for (int j = 0; j < GB; ++j) ol[j + 1] = st[j + 1] != next ? atomicExch(&s.stamp[nb[j]], next) : next;
-                    if (ol[0] != next) lds_claims[atomicAdd(lds_cnt, 1)] = v;
-#pragma unroll
-                    for (int j = 0; j < GB; ++j)
-                        if (ol[j + 1] != next) lds_claims[atomicAdd(lds_cnt, 1)] = nb[j];
+                } else {
+                    sum = ldx<CM>(rin + m.adj[b]);
+                    quiet = quiet && sum == r;
+                    for (int32_t j = b + 1; j < e; ++j) {
+                        const double xn = ldx<CM>(rin + m.adj[j]);
+                        sum = sum + xn;
+                        quiet = quiet && xn == r;
+                    }
+                    if (!quiet) {
+                        stx<CM>(mk_next + v, next);
+                        for (int32_t j = b; j < e; ++j) {
+                            const int32_t u = m.adj[j];
+                            stx<CM>(mk_next + u, next);
+                            if (ldx<CM>(mk_cur + u) != cur && s.stamp[u] != next &&
+                                atomicExch(&s.stamp[u], next) != next) {
+                                // rare (degree above the batch): append alone
+                                stx<CM>(out + atomicAdd(outcnt, 1), u);
+                            }
+                        }
+                    }
                 }
-            } else {
-                sum = ldx<CM>(rin + m.adj[b]);
-                quiet = quiet && sum == r;
-                for (int32_t j = b + 1; j < e; ++j) {
-                    const double xn = ldx<CM>(rin + m.adj[j]);
-                    sum = sum + xn;
-                    quiet = quiet && xn == r;
-                }
-                if (!quiet) {
-                    claim_one(s, v, next, lds_claims, lds_cnt);
-                    for (int32_t j = b; j < e; ++j) claim_one(s, m.adj[j], next, lds_claims, lds_cnt);
+                const double lap = sum - (double)d * r;
+                const double dd = (p.a * lap + p.w * (2.0 * r - 1.0)) + p.e * sqrt(r * (1.0 - r));
+                double x = r + p.c * dd;
+                if (x < 0.0) x = 0.0;
+                if (x > 1.0) x = 1.0;
+                stx<CM>(rout + v, x);
+                upd += 1;
+                degsum += d;
+                cand = x > p.tau && ldx<CM>(s.key + v) == KEY_OUT;
+            }
+        }
+        // next list: members of C_t (keep), then claimed new vertices, each
+        // appended with one atomic per wave
+        {
+            const unsigned long long mk = __ballot(keep);
+            if (mk) {
+                const int leader = __ffsll((long long)mk) - 1;
+                int cb = 0;
+                if (lane == leader) cb = atomicAdd(outcnt, __popcll(mk));
+                cb = __shfl(cb, leader);
+                if (keep) stx<CM>(out + cb + __popcll(mk & lt), v);
+            }
+        }
+        if (__ballot(cmask != 0)) {
+#pragma unroll
+            for (int j = 0; j < GB; ++j) {
+                const bool c = (cmask >> j) & 1u;
+                const unsigned long long mk = __ballot(c);
+                if (mk) {
+                    const int leader = __ffsll((long long)mk) - 1;
+                    int cb = 0;
+                    if (lane == leader) cb = atomicAdd(outcnt, __popcll(mk));
+                    cb = __shfl(cb, leader);
+                    if (c) stx<CM>(out + cb + __popcll(mk & lt), nb[j]);
                 }
             }
-            const double lap = sum - (double)d * r;
-            const double dd = (p.a * lap + p.w * (2.0 * r - 1.0)) + p.e * sqrt(r * (1.0 - r));
-            double x = r + p.c * dd;
-            if (x < 0.0) x = 0.0;
-            if (x > 1.0) x = 1.0;
-            stx<CM>(rout + v, x);
-            upd += 1;
-            degsum += d;
-            cand = x > p.tau && ldx<CM>(s.key + v) == KEY_OUT;
         }
         const unsigned long long mask = __ballot(cand);
         if (mask) {
@@ -400,17 +444,8 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
             const int leader = __ffsll((long long)mask) - 1;
             if (lane == leader) cb = atomicAdd(clc, __popcll(mask));
             cb = __shfl(cb, leader);
-            if (cand) stx<CM>(cl + cb + __popcll(mask & ((1ull << lane) - 1ull)), v);
+            if (cand) stx<CM>(cl + cb + __popcll(mask & lt), v);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int c = *lds_cnt;
-            *lds_base = c ? atomicAdd(outcnt, c) : 0;
-        }
-        __syncthreads();
-        const int c = *lds_cnt, b0 = *lds_base;
-        for (int j = threadIdx.x; j < c; j += NT) stx<CM>(out + b0 + j, lds_claims[j]);
-        __syncthreads();
     }
     // wave reduction of the counters, one atomic per wave
     for (int off = 32; off > 0; off >>= 1) {
@@ -1040,6 +1075,8 @@ struct KL {
     int32_t Lc[LCAP];       // lower arcs (-1: full link)
     int32_t Lp[LCAP];       // parent vertex
     int32_t Lq[LCAP];       // link position of the parent
+    int32_t Lt[LCAP];       // round 0: tag of the half-edge (parent -> v)
+    int32_t Ld[LCAP];       // round 0: depth of v
     uint64_t Lm[LCAP];      // lower-neighbour mask (link positions < 64)
     int32_t hk[HCAP];       // hash: vertex id (-1 empty)
     int32_t hv[HCAP];       // hash: entry index
@@ -1075,6 +1112,8 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
     const int tid = threadIdx.x;
     const uint64_t tk = (uint64_t)t << 32;
+    const unsigned long long k0 = __builtin_amdgcn_s_memrealtime();
+    unsigned long long k1 = k0, k2 = k0, k3 = k0;
     for (int i = tid; i < HCAP; i += NT) kl->hk[i] = -1;
     if (tid == 0) { sh->nL = 0; sh->nN = 0; sh->nnew = 0; sh->event = 0; sh->npend = 0; }
     __syncthreads();
@@ -1102,9 +1141,18 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
     }
     __syncthreads();
     const int nL = sh->nL;
-    if (nL == 0) return;
+    k1 = __builtin_amdgcn_s_memrealtime();
+    if (nL == 0) {
+        if (tid == 0) ctl->clk_t[0] += k1 - k0;
+        return;
+    }
     // 2. closure round 0: touches the inside set of step t-1
     int n0 = 0;
+    // the first entry of each thread keeps its link (ids and pre-step keys)
+    // in registers for the classification below
+    int32_t cnb[GB];
+    uint64_t ckn[GB];
+    bool cached = false;
     for (int i = tid; i < nL; i += NT) {
         const int32_t x = kl->Lv[i];
         const int32_t b = m.rp[x];
@@ -1116,6 +1164,11 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
             gather_link(m, s.key, b, d, c0, nb, kn);
 #pragma unroll
             for (int j = 0; j < GB; ++j) hit = hit || kn[j] < tk;
+            if (i == tid && d <= GB) {
+#pragma unroll
+                for (int j = 0; j < GB; ++j) { cnb[j] = nb[j]; ckn[j] = kn[j]; }
+                cached = true;
+            }
         }
         kl->Lr[i] = hit ? 0 : -1;
         n0 += hit;
@@ -1155,6 +1208,7 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
         }
     }
     __syncthreads();
+    k2 = __builtin_amdgcn_s_memrealtime();
     // 3. lower-link classification: a neighbour is lower if it was inside
     //    before step t, or joined in this step with a smaller (round, id)
     for (int i = tid; i < nL; i += NT) {
@@ -1171,7 +1225,12 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
         for (int c0 = 0; c0 < d; c0 += GB) {
             int32_t nb[GB];
             uint64_t kn[GB];
-            gather_link(m, s.key, b, d, c0, nb, kn);
+            if (i == tid && cached) {
+#pragma unroll
+                for (int j = 0; j < GB; ++j) { nb[j] = cnb[j]; kn[j] = ckn[j]; }
+            } else {
+                gather_link(m, s.key, b, d, c0, nb, kn);
+            }
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
                 if (c0 + j >= d) continue;
@@ -1206,10 +1265,17 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
         kl->Lm[i] = mask;
         s.key[x] = tk | (uint64_t)rv;
         s.parent[x] = par;
+        if (rv == 0 && ppos >= 0) {
+            // the parent was inside before step t: its half-edge to x and
+            // its depth are final already
+            kl->Lt[i] = s.lid[m.rev[b + ppos]];
+            kl->Ld[i] = s.depth[par] + 1;
+        }
         if (cls != 1) atomicOr(&sh->event, 1);
         if (nlow == 0 || d > MAXDEG) atomicOr(&sh->event, 2);
     }
     __syncthreads();
+    k3 = __builtin_amdgcn_s_memrealtime();
     if (sh->event & 2) {
         if (tid == 0) fail(s, ST_INVARIANT, 12);
     } else if (!sh->event) {
@@ -1222,8 +1288,14 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
                 const int32_t b = m.rp[v];
                 const int d = m.rp[v + 1] - b;
                 const int32_t par = kl->Lp[i];
-                const int32_t tag = s.lid[m.rev[b + kl->Lq[i]]];
-                s.depth[v] = s.depth[par] + 1;
+                int32_t tag;
+                if (r == 0) {
+                    tag = kl->Lt[i];
+                    s.depth[v] = kl->Ld[i];
+                } else {
+                    tag = s.lid[m.rev[b + kl->Lq[i]]];
+                    s.depth[v] = s.depth[par] + 1;
+                }
                 const uint64_t mask = kl->Lm[i];
                 for (int j = 0; j < d; ++j)
                     if (!(mask >> j & 1ull)) s.lid[b + j] = tag;
@@ -1275,6 +1347,13 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
     for (int i = tid; i < nL; i += NT)
         if (kl->Lr[i] < 0) s.pend[t & 1][atomicAdd(&sh->npend, 1)] = kl->Lv[i];
     __syncthreads();
+    if (tid == 0) {
+        const unsigned long long k4 = __builtin_amdgcn_s_memrealtime();
+        ctl->clk_t[0] += k1 - k0;
+        ctl->clk_t[1] += k2 - k1;
+        ctl->clk_t[2] += k3 - k2;
+        ctl->clk_t[3] += k4 - k3;
+    }
 }
 
 template <int CM>
@@ -1317,8 +1396,6 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
     KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
-    int *fcnt = (int *)lds;
-    int32_t *claims = (int32_t *)(lds + 16);
     if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     unsigned long long c_work = 0, c_wait = 0;
     for (int64_t j = 0;; ++j) {
@@ -1336,10 +1413,10 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->stop[j & 1] = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (G == 1) {
                 __syncthreads();
-                phase_field<CM>(m, s, p, j + 1, 0, 1, claims, fcnt, fcnt + 1);
+                phase_field<CM>(m, s, p, j + 1, 0, 1);
             }
         } else {
-            phase_field<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1, claims, fcnt, fcnt + 1);
+            phase_field<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
         }
         // field snapshots of step j (its buffer is not written in this iteration)
         for (int q = 0; q < s.n_ckpt; ++q) {
@@ -1378,8 +1455,6 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
     KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
-    int *fcnt = (int *)lds;
-    int32_t *claims = (int32_t *)(lds + 16);
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(next_mesh, 1);
         __syncthreads();
@@ -1404,7 +1479,7 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
                 const int stop = ctl->done;
                 __syncthreads();
                 if (stop) break;
-                phase_field<0>(m, s, p, j + 1, 0, 1, claims, fcnt, fcnt + 1);
+                phase_field<0>(m, s, p, j + 1, 0, 1);
                 for (int q = 0; q < s.n_ckpt; ++q) {
                     if (s.ckpt_steps[q] != j || j == 0) continue;
                     const double *src = (j & 1) ? s.rho1 : s.rho0;
