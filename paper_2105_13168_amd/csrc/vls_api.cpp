@@ -569,7 +569,7 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     dp.stall_steps = p->stall_steps;
     dp.max_steps = p->max_steps;
     dp.topo_global = (p->flags & VLS_TOPO_GLOBAL_PATH) ? 1 : 0;
-    dp.full_fences = (p->flags & VLS_FULL_FENCES) ? 1 : 0;
+    dp.coherent = (p->flags & VLS_COHERENT_SHARING) ? 1 : 0;
     HIPCHK(ctx, hipEventCreate(&rp.e0));
     HIPCHK(ctx, hipEventCreate(&rp.e1));
     HIPCHK(ctx, hipEventCreate(&rp.e2));
@@ -712,7 +712,7 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     const size_t lds = step_lds_bytes(block, m->dmax);
     const int maxg = max_coresident_blocks(block, lds);
     if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
-    int grid = p->grid > 0 ? p->grid : 128;
+    int grid = p->grid > 0 ? p->grid : 64;
     if (grid > maxg) grid = maxg;
     hipError_t le = launch_steps(m->d, rp.s, rp.dp, grid, block, ctx->stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le));

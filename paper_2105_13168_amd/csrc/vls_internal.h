@@ -113,7 +113,7 @@ struct DParams {
     int32_t stall_steps;
     int64_t max_steps;
     int32_t topo_global;     // 1: always use the global-memory topology path
-    int32_t full_fences;     // 1: plain shared accesses + full fences at the barrier
+    int32_t coherent;        // 1: coherent atomic shared accesses, release-only barrier
 };
 
 // host launchers (vls_kernels.hip)
