@@ -87,6 +87,75 @@ def copy_calibration(nbytes=1 << 30):
     log(f"copy calibration: {nbytes} bytes read and written")
 
 
+def batch_leg(ctx, n, seq_sample):
+    """configs[3]-style batch: n uneven meshes in one launch (one workgroup
+    per mesh) against the same meshes run one at a time (default launch) on
+    a sample, as meshes per second."""
+    import ctypes as C
+    import meshgen as mg
+    import paper_2105_13168_amd as vls
+    import torch
+    t0 = time.time()
+    ms = mg.batch_workload(n, base_seed=0)
+    log(f"batch workload: {n} meshes, sum V = {sum(m.nv for m in ms)} ({time.time() - t0:.1f}s)")
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    genus = [x.euler_genus for x in M]
+
+    def run_batch(idx):
+        hm = (C.c_void_p * len(idx))(*[M[i].h.value for i in idx])
+        ps = (vls.vls_params * len(idx))()
+        for k, i in enumerate(idx):
+            ps[k] = vls.default_params(seed_vertex=ms[i].seed, flags=vls.VLS_DEFER_RESULTS)
+        outs = (C.c_void_p * len(idx))()
+        st = vls.vls_batch_run(ctx.h, len(idx), hm, ps, outs)
+        sums = []
+        for k in range(len(idx)):
+            s = vls.vls_summary()
+            vls.vls_result_summary(C.c_void_p(outs[k]), C.byref(s))
+            sums.append({f: getattr(s, f) for f, _ in vls.vls_summary._fields_})
+            vls.vls_result_destroy(C.c_void_p(outs[k]))
+        if st != 0:
+            raise vls.VLSError(st, ctx.last_error())
+        return sums
+
+    run_batch(list(range(n)))                     # warm-up: allocates every mesh's run buffers
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sums = run_batch(list(range(n)))
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t1
+    ok = all(s["run_status"] == 0 and s["n_handles"] == g for s, g in zip(sums, genus))
+    vsteps = sum(m.nv * s["steps"] for m, s in zip(ms, sums))
+    ab = sum(alg_bytes(s["active_vertex_updates"], s["active_degree_sum"]) for s in sums)
+    kernel_ms = sums[0]["kernel_ms"]
+    # one at a time, on an evenly spaced sample of the same meshes
+    sample = list(range(0, n, max(1, n // seq_sample)))[:seq_sample]
+    t2 = time.perf_counter()
+    seq_ms = 0.0
+    for i in sample:
+        p = vls.default_params(seed_vertex=ms[i].seed, flags=vls.VLS_DEFER_RESULTS)
+        h = C.c_void_p()
+        st = vls.vls_run(ctx.h, M[i].h, C.byref(p), C.byref(h))
+        vls.vls_result_destroy(h)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t2
+    for x in M:
+        x.close()
+    seq_rate = len(sample) / ts
+    # the sample's share of the batch's vertex-steps, to compare like with like
+    sample_vsteps = sum(ms[i].nv * sums[i]["steps"] for i in sample)
+    return {
+        "meshes": n, "total_vertices": int(sum(m.nv for m in ms)), "all_handles_equal_genus": ok,
+        "seconds": tb, "meshes_per_s": n / tb, "batch_kernel_ms": kernel_ms,
+        "vertex_steps_per_s": vsteps / tb,
+        "hbm_roofline_frac": ab / (kernel_ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
+        "sequential_sample": len(sample), "sequential_seconds": ts,
+        "sequential_meshes_per_s": seq_rate,
+        "sequential_vertex_steps_per_s": sample_vsteps / ts,
+        "speedup_vertex_steps": (vsteps / tb) / (sample_vsteps / ts),
+    }
+
+
 def cpu_baseline(m, max_steps):
     import oracle
     oracle.build(force=False)
@@ -109,6 +178,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batch", type=int, default=1024, help="meshes in the batched leg (0: skip)")
+    ap.add_argument("--batch-seq-sample", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -195,6 +266,8 @@ def main():
                      "kernel": "k_steps", "algorithmic_bytes": ab,
                      "kernel_source_hash": kernel_source_hash()},
     }
+    if args.batch > 0:
+        out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample)
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:

@@ -29,7 +29,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "Mesh", "torus_grid", "marching_tets", "sdf_surface", "pretzel",
+    "Mesh", "torus_grid", "marching_tets", "sdf_surface", "pretzel", "batch_workload",
     "sdf_sphere", "sdf_torus", "sdf_union_tori", "sdf_box", "jittered",
     "pick_seed", "euler_characteristic", "pretzel_sdf", "multi_torus",
 ]
@@ -349,3 +349,30 @@ def pretzel(n: int = 256, sigma: float = 1e-4, rng_seed: int = 0) -> Mesh:
     centres x = -1.6, 0, 1.6), n samples per axis fitted to the bounding box
     plus two cells, N(0, sigma^2) jitter, then a seed vertex."""
     return multi_torus(3, n, 1.0, 0.35, 1.6, sigma, rng_seed)
+
+
+def batch_workload(n: int = 1024, base_seed: int = 0, pretzel_grids=(32, 48, 64, 80, 96)):
+    """Uneven batch of closed meshes: each mesh is a torus grid with
+    V ~ logU[1e3, 2e5] (n2 = round(sqrt(V/2)), n1 = 2 n2) or a chain of g tori
+    (g ~ U{2..10}, spacing 1.6) extracted on an n^3 grid fitted per axis, n
+    drawn from ``pretzel_grids``; type ~ Bernoulli(1/2).  The chain surfaces
+    for each (g, n) are extracted once and shared; every mesh gets its own
+    N(0,1e-4) jitter and seed vertex from stream base_seed + i."""
+    rng = np.random.default_rng(base_seed)
+    kinds = rng.integers(0, 2, size=n)
+    cache = {}
+    out = []
+    for i in range(n):
+        if kinds[i] == 0:
+            V = float(np.exp(rng.uniform(np.log(1e3), np.log(2e5))))
+            n2 = max(4, int(round(np.sqrt(V / 2.0))))
+            m = torus_grid(2 * n2, n2, 1.0, 0.4, 1e-3, rng_seed=base_seed + i)
+        else:
+            g = int(rng.integers(2, 11))
+            gn = int(pretzel_grids[int(rng.integers(len(pretzel_grids)))])
+            if (g, gn) not in cache:
+                cache[(g, gn)] = multi_torus(g, gn, sigma=0.0, rng_seed=0)
+            base = cache[(g, gn)]
+            m = jittered(base, 1e-4, base_seed + i, f"torus_chain{g}_{gn}")
+        out.append(m)
+    return out

@@ -335,10 +335,12 @@ static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
     const int64_t g = std::max<int64_t>(0, m->euler_genus);
     s.tag_cap = (int32_t)std::min<int64_t>((int64_t)nv + 4096, INT32_MAX);
     s.front_cap = s.tag_cap;
-    s.ev_cap = (int32_t)std::min<int64_t>((int64_t)nv, (int64_t)1 << 22);
+    // event records: one per saddle / vanish insertion (at most nv); loop
+    // buffers: the involved loops of merges (each at most the whole front)
+    s.ev_cap = (int32_t)std::min<int64_t>((int64_t)nv, 65536 + (int64_t)nv / 16);
     s.ev_ids_cap = 4 * (int64_t)s.ev_cap + 64;
     s.lp_cap = (int32_t)(2 * g + 64);
-    s.lp_he_cap = 4 * (int64_t)nnz + (1 << 20);
+    s.lp_he_cap = (int64_t)nnz / 4 + 65536;
     hipError_t e = hipSuccess;
 #define A(ptr, n) if (e == hipSuccess) e = dalloc(rb.get(), &(ptr), (n))
     A(s.rho0, nv); A(s.rho1, nv); A(s.key, nv); A(s.parent, nv); A(s.depth, nv);
