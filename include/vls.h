@@ -67,6 +67,8 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
 #define VLS_TOPO_GLOBAL_PATH 4u  /* always run the topology phase from global memory (the path
                                     otherwise taken only by steps with more than 1024 crossers);
                                     results are identical, the flag exists for testing */
+#define VLS_LOCKSTEP 16u         /* one grid barrier per step (topology of t beside field of t+1)
+                                    instead of the decoupled kernel; identical results, for testing */
 #define VLS_COHERENT_SHARING 8u  /* share data between workgroups through coherent atomic accesses
                                     and a release-only step barrier instead of plain accesses and
                                     full agent-scope fences; identical results, for testing */

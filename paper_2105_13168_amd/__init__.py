@@ -25,6 +25,7 @@ VLS_RECORD_FIELD = 1
 VLS_DEFER_RESULTS = 2
 VLS_TOPO_GLOBAL_PATH = 4
 VLS_COHERENT_SHARING = 8
+VLS_LOCKSTEP = 16
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 

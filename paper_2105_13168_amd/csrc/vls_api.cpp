@@ -182,7 +182,7 @@ vls_status vls_context_destroy(vls_context *ctx) {
 namespace {
 
 struct HostAdj {
-    std::vector<int32_t> rp, adj, cyc, src, rev, succ, nin;
+    std::vector<int32_t> rp, adj, cyc, src, rev, succ, nin, ell;
     int32_t dmax = 0;
 };
 
@@ -256,6 +256,18 @@ vls_status build_adjacency(vls_context *ctx, int64_t nv, int64_t nf, const int32
                 return set_err(ctx, VLS_E_MESH_NOT_MANIFOLD, "link of vertex %lld repeats vertex %d", (long long)v, h.adj[b + i]);
     }
     h.dmax = dmax;
+    // padded rows of the field gather: ascending neighbours, then the vertex
+    // itself; a row whose vertex has more than ELL_W neighbours is marked -1
+    h.ell.assign((size_t)nv * ELL_W, 0);
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t b = cnt[v], d = cnt[v + 1] - b;
+        int32_t *row = h.ell.data() + (size_t)v * ELL_W;
+        if (d > ELL_W) {
+            for (int j = 0; j < ELL_W; ++j) row[j] = -1;
+            continue;
+        }
+        for (int j = 0; j < ELL_W; ++j) row[j] = j < d ? h.adj[b + j] : (int32_t)v;
+    }
     // opposite half-edges, and the (y->x) successor
     auto find = [&](int32_t u, int32_t x) -> int64_t {
         for (int64_t j = cnt[u]; j < cnt[u + 1]; ++j)
@@ -463,7 +475,8 @@ vls_status vls_mesh_create(vls_context *ctx, int64_t nv, const double *xyz, int6
     if ((st = upload(m.get(), h.rp, &d.rp)) || (st = upload(m.get(), h.adj, &d.adj)) ||
         (st = upload(m.get(), h.cyc, &d.cyc)) || (st = upload(m.get(), h.src, &d.src)) ||
         (st = upload(m.get(), h.rev, &d.rev)) || (st = upload(m.get(), h.succ, &d.succ)) ||
-        (st = upload(m.get(), h.nin, &d.nin)) || (st = upload(m.get(), m->xyz, &d.xyz))) {
+        (st = upload(m.get(), h.nin, &d.nin)) || (st = upload(m.get(), h.ell, &d.ell)) ||
+        (st = upload(m.get(), m->xyz, &d.xyz))) {
         for (void *p : m->allocs) (void)hipFree(p);
         return st;
     }
@@ -572,6 +585,7 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     dp.max_steps = p->max_steps;
     dp.topo_global = (p->flags & VLS_TOPO_GLOBAL_PATH) ? 1 : 0;
     dp.coherent = (p->flags & VLS_COHERENT_SHARING) ? 1 : 0;
+    dp.lockstep = (p->flags & VLS_LOCKSTEP) ? 1 : 0;
     HIPCHK(ctx, hipEventCreate(&rp.e0));
     HIPCHK(ctx, hipEventCreate(&rp.e1));
     HIPCHK(ctx, hipEventCreate(&rp.e2));

@@ -24,14 +24,20 @@ struct DMesh {
     const int32_t *rev;   // [nnz]  index of the opposite half-edge
     const int32_t *succ;  // [nnz]  next half-edge of the same owner (ccw, wrapping)
     const int32_t *nin;   // [nnz]  e=(u->x), y=cyc[succ[e]]: index of half-edge (y->x)
+    const int32_t *ell;   // [nv][ELL_W] ascending neighbours padded with the vertex itself;
+                          //   first entry -1 when the degree exceeds ELL_W
     const double *xyz;    // [nv][3]
 };
 
+constexpr int ELL_W = 16;             // width of the padded neighbour rows (64 B)
 constexpr uint64_t KEY_OUT = ~0ull;   // rank key of a vertex not yet inside
 
 // control block (device memory), zeroed by the host before a run
 struct Ctl {
     unsigned long long bar;  // grid barrier arrivals (monotonic)
+    unsigned long long fbar; // field-step completions (decoupled kernel): W per step
+    long long kdone;         // last topology step completed (decoupled kernel)
+    long long stop_step;     // step at which the topology stopped (decoupled kernel)
     int32_t stop[2];         // per-iteration exit decision, slot j&1
     int32_t done;
     int32_t status;
@@ -114,6 +120,8 @@ struct DParams {
     int64_t max_steps;
     int32_t topo_global;     // 1: always use the global-memory topology path
     int32_t coherent;        // 1: coherent atomic shared accesses, release-only barrier
+    int32_t lockstep;        // 1: one grid barrier per step instead of the decoupled kernel
+    int32_t pad2;
 };
 
 // host launchers (vls_kernels.hip)

@@ -287,6 +287,7 @@ __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
         }
         sh.nloops = nl;
         Ctl *c = s.ctl;
+        c->stop_step = LLONG_MAX;
         const long long chi = (long long)sh.nball - (long long)sh.ne + (long long)sh.nf;
         c->chi = chi;
         c->b = nl;
@@ -310,7 +311,9 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 // ---------------------------------------------------------------------------
 // field phase of step t: rho_t from rho_{t-1} over the update list C_t
 // ---------------------------------------------------------------------------
-#define GB 16   // neighbours gathered per batch (registers)
+#define GB ELL_W   // neighbours gathered per vertex in registers (one padded row)
+#define FK 2       // list entries per thread per pass (independent latency chains)
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 // Field phase of step t: rho_t from rho_{t-1} over the update set C_t.
 //
@@ -324,8 +327,14 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 // C_t (each member appends itself) plus the neighbours of A_{t-1} outside
 // C_t (claimed once through an exchange on a step stamp); a listed vertex
 // whose mark says it is not in C_{t+1} is dropped by step t+1.
+//
+// The work is one chain of dependent memory round trips per list entry:
+// entry -> (padded neighbour row, own value, mark, key) -> (neighbour
+// values, marks, stamps) -> (stores, claim exchanges) -> (one list and one
+// candidate reservation per wave) -> list stores.  Each thread runs FK
+// entries through every stage together so that their round trips overlap.
 template <int CM>
-__device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+__device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                             int worker, int nworkers) {
     Ctl *ctl = s.ctl;
     const int n = ld_relaxed(&ctl->cnt_act[t & 3]);
@@ -340,121 +349,166 @@ __device__ void phase_field(const DMesh &m, const DState &s, const DParams &p, i
     int *clc = &ctl->cnt_cand[t & 3];
     const int32_t cur = (int32_t)t, next = (int32_t)(t + 1);
     const int lane = __lane_id();
-    const unsigned long long lt = (1ull << lane) - 1ull;
     const int per = (n + nworkers - 1) / nworkers;
     const int beg = worker * per;
     const int end = min(n, beg + per);
     long long upd = 0, degsum = 0;
-    for (int base = beg; base < end; base += NT) {
-        const int i = base + threadIdx.x;
-        bool cand = false, keep = false;
-        int32_t v = -1;
-        uint32_t cmask = 0;          // bit j: neighbour nb[j] claimed as new
-        int32_t nb[GB];
-        if (i < end) {
-            v = ldx<CM>(list + i);
-            const int32_t b = ldg(m.rp + v), e = ldg(m.rp + v + 1);
-            keep = ldx<CM>(mk_cur + v) == cur;
-            const int d = e - b;
-            if (keep) {
-                const double r = ldx<CM>(rin + v);
-                double sum;
-                bool quiet = (r == 0.0 || r == 1.0);
-                if (d <= GB) {
-                    // one batch: neighbour ids; then values and membership marks
-                    double xs[GB];
-                    int32_t mu[GB];
+    for (int base = beg; base < end; base += FK * NT) {
+        int32_t v[FK], d[FK];
+        bool keep[FK], cand[FK], big[FK];
+        uint32_t cmask[FK];          // bit j: neighbour nb[k][j] claimed as new
+        int32_t nb[FK][GB];
+        double r[FK];
+        uint64_t kv[FK];
+        int nbig = 0;                // claims of a wide vertex, appended one by one
+        // entries
 #pragma unroll
-                    for (int j = 0; j < GB; ++j) nb[j] = j < d ? ldg(m.adj + b + j) : v;
+        for (int k = 0; k < FK; ++k) {
+            const int i = base + k * NT + threadIdx.x;
+            v[k] = i < end ? ldx<CM>(list + i) : -1;
+        }
+        // padded neighbour row, own value, own mark, own key
+        int32_t mv[FK];
 #pragma unroll
-                    for (int j = 0; j < GB; ++j) xs[j] = ldx<CM>(rin + nb[j]);
+        for (int k = 0; k < FK; ++k) {
+            keep[k] = false; cand[k] = false; big[k] = false; cmask[k] = 0; d[k] = 0;
+            if (v[k] >= 0) {
+                const GLOBAL_AS v4i *row = (const GLOBAL_AS v4i *)(m.ell + (int64_t)v[k] * GB);
 #pragma unroll
-                    for (int j = 0; j < GB; ++j) mu[j] = ldx<CM>(mk_cur + nb[j]);
-                    sum = xs[0];
-                    quiet = quiet && xs[0] == r;
+                for (int q = 0; q < GB / 4; ++q) {
+                    const v4i w = row[q];
+                    nb[k][4 * q] = w.x; nb[k][4 * q + 1] = w.y; nb[k][4 * q + 2] = w.z; nb[k][4 * q + 3] = w.w;
+                }
+                r[k] = ldx<CM>(rin + v[k]);
+                mv[k] = ldx<CM>(mk_cur + v[k]);
+                kv[k] = ldx<CM>(s.key + v[k]);
+            } else {
 #pragma unroll
-                    for (int j = 1; j < GB; ++j)
-                        if (j < d) {
-                            sum = sum + xs[j];
-                            quiet = quiet && xs[j] == r;
+                for (int j = 0; j < GB; ++j) nb[k][j] = 0;
+                r[k] = 0.0; mv[k] = 0; kv[k] = 0;
+            }
+        }
+        // neighbour values, marks and stamps; sum, fixed-point test, marks,
+        // claims, new value
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+            keep[k] = v[k] >= 0 && mv[k] == cur;
+            big[k] = keep[k] && nb[k][0] < 0;
+        }
+        double xs[FK][GB];
+        int32_t mu[FK][GB], st[FK][GB];
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+            if (keep[k] && !big[k]) {
+#pragma unroll
+                for (int j = 0; j < GB; ++j) xs[k][j] = ldx<CM>(rin + nb[k][j]);
+#pragma unroll
+                for (int j = 0; j < GB; ++j) mu[k][j] = ldx<CM>(mk_cur + nb[k][j]);
+#pragma unroll
+                for (int j = 0; j < GB; ++j) st[k][j] = *(const GLOBAL_AS int32_t *)(s.stamp + nb[k][j]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+            if (!keep[k]) continue;
+            const int32_t vk = v[k];
+            const double rk = r[k];
+            bool quiet = (rk == 0.0 || rk == 1.0);
+            double sum;
+            int dk;
+            if (!big[k]) {
+                // row padded with the vertex itself after its d neighbours
+                dk = 0;
+#pragma unroll
+                for (int j = 0; j < GB; ++j) dk += nb[k][j] != vk;
+                sum = xs[k][0];
+                quiet = quiet && xs[k][0] == rk;
+#pragma unroll
+                for (int j = 1; j < GB; ++j)
+                    if (j < dk) {
+                        sum = sum + xs[k][j];
+                        quiet = quiet && xs[k][j] == rk;
+                    }
+                if (!quiet) {
+                    stx<CM>(mk_next + vk, next);
+#pragma unroll
+                    for (int j = 0; j < GB; ++j)
+                        if (j < dk) {
+                            stx<CM>(mk_next + nb[k][j], next);
+                            // outside C_t: not listed by itself, claim it once
+                            if (mu[k][j] != cur && st[k][j] != next && atomicExch(&s.stamp[nb[k][j]], next) != next)
+                                cmask[k] |= 1u << j;
                         }
-                    if (!quiet) {
-                        stx<CM>(mk_next + v, next);
-#pragma unroll
-                        for (int j = 0; j < GB; ++j)
-                            if (j < d) {
-                                stx<CM>(mk_next + nb[j], next);
-                                // outside C_t: not listed by itself, claim it once
-                                if (mu[j] != cur && s.stamp[nb[j]] != next &&
-                                    atomicExch(&s.stamp[nb[j]], next) != next)
-                                    cmask |= 1u << j;
-                            }
-                    }
-                } else {
-                    sum = ldx<CM>(rin + m.adj[b]);
-                    quiet = quiet && sum == r;
-                    for (int32_t j = b + 1; j < e; ++j) {
-                        const double xn = ldx<CM>(rin + m.adj[j]);
-                        sum = sum + xn;
-                        quiet = quiet && xn == r;
-                    }
-                    if (!quiet) {
-                        stx<CM>(mk_next + v, next);
-                        for (int32_t j = b; j < e; ++j) {
-                            const int32_t u = m.adj[j];
-                            stx<CM>(mk_next + u, next);
-                            if (ldx<CM>(mk_cur + u) != cur && s.stamp[u] != next &&
-                                atomicExch(&s.stamp[u], next) != next) {
-                                // rare (degree above the batch): append alone
-                                stx<CM>(out + atomicAdd(outcnt, 1), u);
-                            }
+                }
+            } else {
+                // degree above the row width: row offsets and the ascending list
+                const int32_t b = ldg(m.rp + vk), e = ldg(m.rp + vk + 1);
+                dk = e - b;
+                sum = ldx<CM>(rin + m.adj[b]);
+                quiet = quiet && sum == rk;
+                for (int32_t j = b + 1; j < e; ++j) {
+                    const double xn = ldx<CM>(rin + m.adj[j]);
+                    sum = sum + xn;
+                    quiet = quiet && xn == rk;
+                }
+                if (!quiet) {
+                    stx<CM>(mk_next + vk, next);
+                    for (int32_t j = b; j < e; ++j) {
+                        const int32_t u = m.adj[j];
+                        stx<CM>(mk_next + u, next);
+                        if (ldx<CM>(mk_cur + u) != cur && s.stamp[u] != next && atomicExch(&s.stamp[u], next) != next) {
+                            stx<CM>(out + atomicAdd(outcnt, 1), u);
+                            ++nbig;
                         }
                     }
                 }
-                const double lap = sum - (double)d * r;
-                const double dd = (p.a * lap + p.w * (2.0 * r - 1.0)) + p.e * sqrt(r * (1.0 - r));
-                double x = r + p.c * dd;
-                if (x < 0.0) x = 0.0;
-                if (x > 1.0) x = 1.0;
-                stx<CM>(rout + v, x);
-                upd += 1;
-                degsum += d;
-                cand = x > p.tau && ldx<CM>(s.key + v) == KEY_OUT;
             }
+            d[k] = dk;
+            const double lap = sum - (double)dk * rk;
+            const double dd = (p.a * lap + p.w * (2.0 * rk - 1.0)) + p.e * sqrt(rk * (1.0 - rk));
+            double x = rk + p.c * dd;
+            if (x < 0.0) x = 0.0;
+            if (x > 1.0) x = 1.0;
+            stx<CM>(rout + vk, x);
+            upd += 1;
+            degsum += dk;
+            cand[k] = x > p.tau && kv[k] == KEY_OUT;
         }
-        // next list: members of C_t (keep), then claimed new vertices, each
-        // appended with one atomic per wave
-        {
-            const unsigned long long mk = __ballot(keep);
-            if (mk) {
-                const int leader = __ffsll((long long)mk) - 1;
-                int cb = 0;
-                if (lane == leader) cb = atomicAdd(outcnt, __popcll(mk));
-                cb = __shfl(cb, leader);
-                if (keep) stx<CM>(out + cb + __popcll(mk & lt), v);
-            }
-        }
-        if (__ballot(cmask != 0)) {
+        (void)nbig;
+        // appends: members of C_t and claimed vertices to the next list,
+        // crossers to the candidate list; one wave-wide prefix sum (both
+        // counts packed in one word) and one reservation per list per wave
+        int nl = 0, nc = 0;
 #pragma unroll
-            for (int j = 0; j < GB; ++j) {
-                const bool c = (cmask >> j) & 1u;
-                const unsigned long long mk = __ballot(c);
-                if (mk) {
-                    const int leader = __ffsll((long long)mk) - 1;
-                    int cb = 0;
-                    if (lane == leader) cb = atomicAdd(outcnt, __popcll(mk));
-                    cb = __shfl(cb, leader);
-                    if (c) stx<CM>(out + cb + __popcll(mk & lt), nb[j]);
-                }
-            }
+        for (int k = 0; k < FK; ++k) {
+            nl += (int)keep[k] + __popc(cmask[k]);
+            nc += (int)cand[k];
         }
-        const unsigned long long mask = __ballot(cand);
-        if (mask) {
-            int cb = 0;
-            const int leader = __ffsll((long long)mask) - 1;
-            if (lane == leader) cb = atomicAdd(clc, __popcll(mask));
-            cb = __shfl(cb, leader);
-            if (cand) stx<CM>(cl + cb + __popcll(mask & lt), v);
+        const int own = nl | (nc << 16);
+        int inc = own;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int y = __shfl_up(inc, off);
+            if (lane >= off) inc += y;
+        }
+        const int tot = __shfl(inc, WAVE - 1);
+        if (tot == 0) continue;
+        int lb = 0, cb = 0;
+        if (lane == WAVE - 1) {
+            if (tot & 0xffff) lb = atomicAdd(outcnt, tot & 0xffff);
+            if (tot >> 16) cb = atomicAdd(clc, tot >> 16);
+        }
+        lb = __shfl(lb, WAVE - 1);
+        cb = __shfl(cb, WAVE - 1);
+        int lo = lb + ((inc - own) & 0xffff);
+        int co = cb + ((inc - own) >> 16);
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+            if (keep[k]) stx<CM>(out + lo++, v[k]);
+#pragma unroll
+            for (int j = 0; j < GB; ++j)
+                if ((cmask[k] >> j) & 1u) stx<CM>(out + lo++, nb[k][j]);
+            if (cand[k]) stx<CM>(cl + co++, v[k]);
         }
     }
     // wave reduction of the counters, one atomic per wave
@@ -565,7 +619,7 @@ __device__ __forceinline__ void crossing_point(const DMesh &m, const double *rho
 // Saddle or vanish insertion of v at step t, resolved by wave 0 (all 64
 // lanes call it with the same v).
 template <int CM>
-__device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+__device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                               int32_t v, KSh *sh, const double *rho) {
     Ctl *ctl = s.ctl;
     const int lane = __lane_id();
@@ -909,7 +963,7 @@ __device__ void resolve_event(const DMesh &m, const DState &s, const DParams &p,
 }
 
 template <int CM>
-__device__ void phase_topo_global(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+__device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                                   KSh *sh, uint64_t *lsort) {
     Ctl *ctl = s.ctl;
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
@@ -1116,7 +1170,7 @@ __device__ __forceinline__ void gather_link(const DMesh &m, const uint64_t *key,
 }
 
 template <int CM>
-__device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+__device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                                KSh *sh, KL *kl, uint64_t *lsort, int nc, int np) {
     Ctl *ctl = s.ctl;
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
@@ -1367,7 +1421,7 @@ __device__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p
 }
 
 template <int CM>
-__device__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+__device__ __forceinline__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                            KSh *sh, KL *kl, uint64_t *lsort) {
     Ctl *ctl = s.ctl;
     const int nc = ld_relaxed(&ctl->cnt_cand[t & 3]);
@@ -1452,6 +1506,124 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// the decoupled step kernel: the field never depends on the fronts, so the
+// field workgroups (1..G-1) step on with a barrier among themselves, while
+// workgroup 0 runs the topology of step t as soon as field step t is
+// complete.  Field step t rewrites the buffer of step t-2 and the crosser
+// list of step t-2, so it waits until topology step t-2 is done: the field
+// runs at most two steps ahead and never waits on the current topology.
+// Every spin has a wall-clock bound that records an error instead of
+// hanging.
+// ---------------------------------------------------------------------------
+#define SPIN_LIMIT 2000000000ull   // s_memrealtime ticks (100 MHz): 20 s
+#define KDONE_STOP (1ll << 60)
+
+__device__ __forceinline__ bool spin_ge(const unsigned long long *p, unsigned long long target, const DState &s) {
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__builtin_amdgcn_s_memrealtime() - t0 > SPIN_LIMIT) { fail(s, ST_INVARIANT, 20); return false; }
+    }
+    return true;
+}
+__device__ __forceinline__ bool spin_ge64(const long long *p, long long target, const DState &s) {
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__builtin_amdgcn_s_memrealtime() - t0 > SPIN_LIMIT) { fail(s, ST_INVARIANT, 21); return false; }
+    }
+    return true;
+}
+
+template <int CM>
+__global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int go;
+    const unsigned long long W = gridDim.x - 1;          // field workgroups
+    Ctl *ctl = s.ctl;
+    KSh *ksh = (KSh *)lds;
+    uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
+    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
+    if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    unsigned long long c_work = 0, c_wait = 0;
+    if (blockIdx.x == 0) {
+        for (int64_t t = 1;; ++t) {
+            const unsigned long long c0 = __builtin_amdgcn_s_memrealtime();
+            if (threadIdx.x == 0) {
+                go = spin_ge(&ctl->fbar, (unsigned long long)t * W, s) ? 1 : 0;
+                __threadfence();
+            }
+            __syncthreads();
+            const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
+            if (go) phase_topo<CM>(m, s, p, t, ksh, kl, lsort);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int d = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || !go;
+                __threadfence();
+                if (d) {
+                    // the stop step becomes visible before the jump of kdone
+                    __hip_atomic_store(&ctl->stop_step, (long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __threadfence();
+                    __hip_atomic_store(&ctl->kdone, KDONE_STOP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    __hip_atomic_store(&ctl->kdone, (long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                go = d;
+            }
+            __syncthreads();
+            const unsigned long long c2 = __builtin_amdgcn_s_memrealtime();
+            c_wait += c1 - c0;
+            c_work += c2 - c1;
+            if (go) break;
+        }
+        if (threadIdx.x == 0) { ctl->clk_topo = c_work; ctl->clk_wait0 = c_wait; }
+        return;
+    }
+    const int worker = (int)blockIdx.x - 1;
+    for (int64_t t = 1;; ++t) {
+        const unsigned long long c0 = __builtin_amdgcn_s_memrealtime();
+        if (threadIdx.x == 0) {
+            // topology t-2 done (its field buffer and crosser list are free)
+            int ok = spin_ge64(&ctl->kdone, t - 2, s);
+            __threadfence();
+            const long long stop = __hip_atomic_load(&ctl->stop_step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!ok || stop <= t - 2) {
+                go = 0;
+            } else {
+                // field step t-1 complete on every field workgroup
+                ok = spin_ge(&ctl->fbar, (unsigned long long)(t - 1) * W, s);
+                __threadfence();
+                go = ok;
+            }
+            if (go && worker == 0) {
+                ctl->cnt_act[(t + 2) & 3] = 0;
+                ctl->cnt_cand[(t + 2) & 3] = 0;
+            }
+        }
+        __syncthreads();
+        const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
+        if (!go) break;
+        phase_field<CM>(m, s, p, t, worker, (int)W);
+        // field snapshot of step t-1 (its buffer is not written by step t)
+        for (int q = 0; q < s.n_ckpt; ++q) {
+            if (s.ckpt_steps[q] != t - 1 || t == 1) continue;
+            const double *src = ((t - 1) & 1) ? s.rho1 : s.rho0;
+            double *dst = s.ckpt + (int64_t)q * m.nv;
+            for (int64_t i = (int64_t)worker * NT + threadIdx.x; i < m.nv; i += (int64_t)W * NT) dst[i] = ldx<CM>(src + i);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            atomicAdd(&ctl->fbar, 1ull);
+        }
+        const unsigned long long c2 = __builtin_amdgcn_s_memrealtime();
+        c_wait += c1 - c0;
+        c_work += c2 - c1;
+    }
+    if (threadIdx.x == 0 && worker == 0) { ctl->clk_field = c_work; ctl->clk_wait1 = c_wait; }
+}
+
+// ---------------------------------------------------------------------------
 // batched mode: many meshes in one launch.  A persistent pool of workgroups
 // pulls meshes (largest first) from a counter; one workgroup advances one
 // mesh through all its steps, topology of step t then field of step t+1,
@@ -1527,9 +1699,15 @@ size_t step_lds_bytes(int block, int dmax) {
 }
 
 int max_coresident_blocks(int block, size_t lds_bytes) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_steps<0>, block, lds_bytes) != hipSuccess)
-        return 0;
+    // the smallest residency over every variant the launcher may pick
+    const void *fns[4] = {(const void *)k_steps<0>, (const void *)k_steps<1>, (const void *)k_steps_dec<0>,
+                          (const void *)k_steps_dec<1>};
+    int per_cu = 1 << 30;
+    for (const void *f : fns) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds_bytes) != hipSuccess) return 0;
+        per_cu = n < per_cu ? n : per_cu;
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     int cus = 0;
@@ -1544,7 +1722,9 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
     DState ss = s;
     DParams pp = p;
     void *args[] = {&mm, &ss, &pp};
-    const void *fn = p.coherent ? (const void *)k_steps<1> : (const void *)k_steps<0>;
+    const void *fn;
+    if (p.lockstep || grid < 2) fn = p.coherent ? (const void *)k_steps<1> : (const void *)k_steps<0>;
+    else fn = p.coherent ? (const void *)k_steps_dec<1> : (const void *)k_steps_dec<0>;
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, st);
 }
 

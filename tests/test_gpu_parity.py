@@ -88,6 +88,25 @@ def test_parity_coherent_sharing_variant(ctx, oracle_mod, name, make, ck):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("flags", ["lockstep", "lockstep+coherent", "coherent"])
+@pytest.mark.parametrize("name,make,ck", [SMALL[0], SMALL[6]], ids=["torus", "pretzel48"])
+def test_parity_step_kernel_variants(ctx, oracle_mod, name, make, ck, flags):
+    """The lockstep step kernel (one grid barrier per step, topology of step
+    t beside the field of step t+1) and the decoupled default (the field
+    runs ahead up to two steps, the topology follows each completed field
+    step) give the same results, with either sharing mode."""
+    import paper_2105_13168_amd as vls
+    f = 0
+    if "lockstep" in flags:
+        f |= vls.VLS_LOCKSTEP
+    if "coherent" in flags:
+        f |= vls.VLS_COHERENT_SHARING
+    m = make()
+    g, o = _run_both(ctx, oracle_mod, m, ck, flags=f)
+    bad = compare(g, o, m.nv)
+    assert not bad, bad
+
+
 def test_parity_dt_literal_and_radius(ctx, oracle_mod):
     # literal dt = 0.25/dmax on a tiny torus; and a radius-1 / radius-3 seed
     m = mg.torus_grid(16, 8, R=1.0, r=0.4, jitter=1e-3, rng_seed=5)
