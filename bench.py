@@ -88,9 +88,9 @@ def copy_calibration(nbytes=1 << 30):
 
 
 def batch_leg(ctx, n, seq_sample):
-    """configs[3]-style batch: n uneven meshes in one launch (one workgroup
-    per mesh) against the same meshes run one at a time (default launch) on
-    a sample, as meshes per second."""
+    """Batch of n uneven meshes in one launch (one workgroup per mesh)
+    against the same meshes run one at a time (default launch) on a sample,
+    as meshes per second."""
     import ctypes as C
     import meshgen as mg
     import paper_2105_13168_amd as vls
@@ -157,14 +157,18 @@ def batch_leg(ctx, n, seq_sample):
 
 
 def cpu_baseline(m, max_steps):
+    """The oracle, single-threaded, on the same mesh and seed: the whole pass
+    (max_steps 0) or its first max_steps diffusion steps."""
     import oracle
     oracle.build(force=False)
+    kw = {"max_steps": max_steps} if max_steps > 0 else {}
     t0 = time.perf_counter()
-    r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed, max_steps=max_steps)
+    r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed, **kw)
     dt = time.perf_counter() - t0
     steps = r.steps
+    what = "the whole pass" if max_steps <= 0 else f"the first {steps} diffusion steps of the pass"
     return {"value": m.nv * steps / dt, "unit": "vertex-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} diffusion steps of the same pass (single thread, {dt:.1f} s)",
+            "sample": f"{what} ({steps} diffusion steps, single thread, {dt:.1f} s)",
             "seconds": round(dt, 3)}
 
 
@@ -175,7 +179,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pretzel256")
     ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=10000)
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle diffusion steps (0: whole pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch", type=int, default=1024, help="meshes in the batched leg (0: skip)")
