@@ -52,7 +52,9 @@ enum {
     VLS_E_BUFFER_TOO_SMALL = -10,
     VLS_E_CAPACITY = -11,             /* an internal device buffer bound was exceeded            */
     VLS_E_TOO_LARGE = -12,            /* mesh beyond the 32-bit index range                      */
-    VLS_E_INVARIANT = -13             /* a topological invariant failed (see vls_last_error)     */
+    VLS_E_INVARIANT = -13,            /* a topological invariant failed (see vls_last_error)     */
+    VLS_E_PENDING = -14,              /* server request not finished yet                         */
+    VLS_E_CANCELLED = -15             /* server request dropped by vls_server_destroy            */
 };
 
 /* Reeb node types (Section "Initial Pass": branching and collision;
@@ -163,7 +165,13 @@ typedef struct {
     double topo_ms, wait0_ms, field_ms, wait1_ms;
     int64_t event_steps;       /* steps resolved through the sequential event path           */
     double topo_split_ms[4];   /* topology: candidates, closure, classification, insert/events */
-    double field_split_ms[3];  /* field (workgroup 1): gather + update, claims, list flush     */
+    double topo_event_ms;      /* topology: time in steps with events (rank-ordered insertion) */
+    double topo_rounds_ms;     /* topology: closure rounds after round 0                       */
+    int32_t topo_round_steps;  /* steps that needed closure rounds after round 0               */
+    int32_t topo_global_steps; /* steps whose candidates took the global-memory path           */
+    /* server requests only (0 otherwise), host wall clock: submission to
+       admission (queueing) and submission to result ready (latency) */
+    double server_queue_ms, server_latency_ms;
 } vls_summary;
 vls_status vls_result_summary(const struct vls_result *r, vls_summary *s);
 
@@ -224,6 +232,47 @@ vls_status vls_result_vertices(const struct vls_result *r, int32_t *step, int32_
  */
 vls_status vls_batch_run(struct vls_context *ctx, int32_t n, const struct vls_mesh *const *meshes,
                          const vls_params *per_mesh, struct vls_result **out);
+
+/*
+ * Serving: a request loop over one device with continuous batching.  The
+ * paper runs its secondary passes concurrently up to what GPU memory allows
+ * (Section "Tunnel loop pass", "Implementation details"); here whole
+ * initial passes of different meshes share the device the same way.
+ *
+ * vls_server_create: a scheduler thread with its own stream on ctx's
+ *   device.  hbm_budget_bytes caps the device run state of the admitted
+ *   requests (per request: the per-vertex and per-half-edge run arrays,
+ *   event/loop buffers and checkpoints; the mesh itself is the caller's);
+ *   max_slots caps how many run at once.  A request larger than the budget
+ *   is admitted only when nothing else runs.
+ * vls_server_submit: queues an initial pass of mesh m with parameters p
+ *   (copied, checkpoint list included); thread-safe; *ticket identifies it.
+ *   The mesh must stay alive until the request is polled; one mesh may be
+ *   in several requests at once (each has its own run state).
+ * Scheduling: admitted requests advance together in bounded launches of
+ *   the batched step kernel (one workgroup per mesh, each visit bounded to
+ *   slice_us microseconds of device time at a step boundary); between
+ *   launches finished requests are completed (post-passes, results to host)
+ *   and queued ones admitted as slots and budget free up.  A request's
+ *   results are identical to a vls_run of the same mesh and parameters.
+ * vls_server_poll: VLS_E_PENDING until the request is done; then *out
+ *   receives its result (owned by the caller) and the call returns the run
+ *   status; the ticket is then forgotten.  Thread-safe.
+ * vls_server_destroy: stops the scheduler; queued and running requests are
+ *   dropped (their polls can no longer happen), unpolled results freed.
+ * Errors: VLS_E_INVALID_ARG (bad handle/ticket), VLS_E_DEVICE.
+ */
+struct vls_server;
+vls_status vls_server_create(struct vls_context *ctx, size_t hbm_budget_bytes, int32_t max_slots,
+                             int64_t slice_us, struct vls_server **out);
+vls_status vls_server_submit(struct vls_server *srv, const struct vls_mesh *m, const vls_params *p,
+                             uint64_t *ticket);
+vls_status vls_server_poll(struct vls_server *srv, uint64_t ticket, struct vls_result **out);
+/* counters: launches of the step kernel, requests completed, device run
+   state currently admitted (bytes), requests queued and running */
+vls_status vls_server_stats(const struct vls_server *srv, int64_t *launches, int64_t *completed,
+                            int64_t *admitted_bytes, int32_t *queued, int32_t *running);
+vls_status vls_server_destroy(struct vls_server *srv);
 
 /* Copies the bulk results of a VLS_DEFER_RESULTS run to the host (no-op
    otherwise).  Called implicitly by every accessor, by the next vls_run on

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libvls.so")
 
 VLS_OK = 0
 VLS_E_BUFFER_TOO_SMALL = -10
+VLS_E_PENDING = -14
+VLS_E_CANCELLED = -15
 VLS_RECORD_FIELD = 1
 VLS_DEFER_RESULTS = 2
 VLS_TOPO_GLOBAL_PATH = 4
@@ -48,7 +50,10 @@ class vls_summary(C.Structure):
                 ("grid", C.c_int32), ("block", C.c_int32), ("kernel_ms", C.c_double),
                 ("total_ms", C.c_double), ("topo_ms", C.c_double), ("wait0_ms", C.c_double),
                 ("field_ms", C.c_double), ("wait1_ms", C.c_double), ("event_steps", C.c_int64),
-                ("topo_split_ms", C.c_double * 4), ("field_split_ms", C.c_double * 3)]
+                ("topo_split_ms", C.c_double * 4), ("topo_event_ms", C.c_double),
+                ("topo_rounds_ms", C.c_double), ("topo_round_steps", C.c_int32),
+                ("topo_global_steps", C.c_int32), ("server_queue_ms", C.c_double),
+                ("server_latency_ms", C.c_double)]
 
 
 class vls_reeb_node(C.Structure):
@@ -89,6 +94,11 @@ _sig = {
     "vls_result_vertices": (C.c_int32, [_P, _P, _P, _P]),
     "vls_result_fetch": (C.c_int32, [_P]),
     "vls_result_destroy": (C.c_int32, [_P]),
+    "vls_server_create": (C.c_int32, [_P, C.c_size_t, C.c_int32, C.c_int64, _PP]),
+    "vls_server_submit": (C.c_int32, [_P, _P, C.POINTER(vls_params), C.POINTER(C.c_uint64)]),
+    "vls_server_poll": (C.c_int32, [_P, C.c_uint64, _PP]),
+    "vls_server_stats": (C.c_int32, [_P, _I64P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "vls_server_destroy": (C.c_int32, [_P]),
 }
 for _n, (_rt, _at) in _sig.items():
     _f = getattr(_lib, _n)
@@ -284,6 +294,69 @@ def batch_run(ctx: Context, meshes, seeds, raise_on_error: bool = True, **kw):
         r.error = ""
         res.append(r)
     return res
+
+
+class Server:
+    """Request loop with continuous batching on one device: submit()
+    returns a ticket, poll() returns None while the request runs and its
+    Result once done.  A mesh must stay open until its requests are polled."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 1024, slice_us: int = 2000):
+        h = C.c_void_p()
+        st = vls_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), int(slice_us), C.byref(h))
+        if st != VLS_OK:
+            raise VLSError(st, ctx.last_error())
+        self.h = h
+        self.ctx = ctx
+        self._meshes = {}
+        self._ck = {}
+
+    def submit(self, mesh: Mesh, seed_vertex: int = 0, ckpt_steps=(), **kw) -> int:
+        ck = np.ascontiguousarray(np.asarray(ckpt_steps, dtype=np.int64).reshape(-1))
+        p = default_params(seed_vertex=seed_vertex, **kw)
+        if ck.size:
+            p.flags |= VLS_RECORD_FIELD
+            p.n_ckpt = ck.size
+            p.ckpt_steps = ck.ctypes.data_as(_I64P)
+        t = C.c_uint64()
+        st = vls_server_submit(self.h, mesh.h, C.byref(p), C.byref(t))
+        if st != VLS_OK:
+            raise VLSError(st, "submit")
+        self._meshes[t.value] = mesh
+        self._ck[t.value] = ck
+        return t.value
+
+    def poll(self, ticket: int):
+        h = C.c_void_p()
+        st = vls_server_poll(self.h, C.c_uint64(ticket), C.byref(h))
+        if st == VLS_E_PENDING:
+            return None
+        mesh = self._meshes.pop(ticket)
+        ck = self._ck.pop(ticket)
+        if not h:
+            raise VLSError(st, "request failed")
+        r = Result(h, mesh, ck)
+        r.status = int(st)
+        r.error = ""
+        return r
+
+    def stats(self) -> dict:
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        q, r = C.c_int32(), C.c_int32()
+        vls_server_stats(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(q), C.byref(r))
+        return {"launches": a.value, "completed": b.value, "admitted_bytes": c.value,
+                "queued": q.value, "running": r.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            vls_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run(xyz, tri, seed_vertex=0, device=0, stream=None, **kw) -> Result:

@@ -6,11 +6,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "vls.h"
@@ -142,6 +148,8 @@ const char *vls_status_string(vls_status s) {
     case VLS_E_CAPACITY: return "VLS_E_CAPACITY";
     case VLS_E_TOO_LARGE: return "VLS_E_TOO_LARGE";
     case VLS_E_INVARIANT: return "VLS_E_INVARIANT";
+    case VLS_E_PENDING: return "VLS_E_PENDING";
+    case VLS_E_CANCELLED: return "VLS_E_CANCELLED";
     default: return "VLS_E_UNKNOWN";
     }
 }
@@ -182,7 +190,7 @@ vls_status vls_context_destroy(vls_context *ctx) {
 namespace {
 
 struct HostAdj {
-    std::vector<int32_t> rp, adj, cyc, src, rev, succ, nin, ell;
+    std::vector<int32_t> rp, adj, cyc, src, rev, succ, nin, ell, lrow;
     int32_t dmax = 0;
 };
 
@@ -268,6 +276,19 @@ vls_status build_adjacency(vls_context *ctx, int64_t nv, int64_t nf, const int32
         }
         for (int j = 0; j < ELL_W; ++j) row[j] = j < d ? h.adj[b + j] : (int32_t)v;
     }
+    // link rows of the topology: counter-clockwise neighbours, -1 padding,
+    // and the first half-edge index in the last slot (-2 first: too wide)
+    h.lrow.assign((size_t)nv * ELL_W, -1);
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t b = cnt[v], d = cnt[v + 1] - b;
+        int32_t *row = h.lrow.data() + (size_t)v * ELL_W;
+        row[ELL_W - 1] = (int32_t)b;
+        if (d > ELL_W - 1) {
+            row[0] = -2;
+            continue;
+        }
+        for (int j = 0; j < d; ++j) row[j] = h.cyc[b + j];
+    }
     // opposite half-edges, and the (y->x) successor
     auto find = [&](int32_t u, int32_t x) -> int64_t {
         for (int64_t j = cnt[u]; j < cnt[u + 1]; ++j)
@@ -336,6 +357,30 @@ static hipError_t dalloc(RunBuffers *rb, T **p, size_t n) {
     if (e == hipSuccess) rb->allocs.push_back(q);
     *p = (T *)q;
     return e;
+}
+
+// device bytes make_run_buffers allocates for mesh m (the server's HBM
+// admission charges a request this much plus its checkpoints)
+static size_t run_buffer_bytes(const vls_mesh *m) {
+    const size_t nv = (size_t)m->nv, nnz = (size_t)m->nnz;
+    size_t npow = 1;
+    while (npow < nv) npow <<= 1;
+    const int64_t g = std::max<int64_t>(0, m->euler_genus);
+    const size_t tag_cap = (size_t)std::min<int64_t>((int64_t)nv + 4096, INT32_MAX);
+    const size_t ev_cap = (size_t)std::min<int64_t>((int64_t)nv, 65536 + (int64_t)nv / 16);
+    const size_t ev_ids_cap = 4 * ev_cap + 64;
+    const size_t lp_cap = (size_t)(2 * g + 64);
+    const size_t lp_he_cap = nnz / 4 + 65536;
+    size_t b = 0;
+    b += nv * (8 + 8 + 8 + 4 + 4);                 // rho0, rho1, key, parent, depth
+    b += nnz * 4;                                  // lid
+    b += nv * 4 * 13;                              // stamp .. Lcls (13 int32 arrays)
+    b += npow * 8;                                 // ord
+    b += tag_cap * 4 * 2 + tag_cap * 4 * 2;        // tag_parent, tag_fid, front_birth, front_death
+    b += ev_cap * 16 * 8 + ev_cap * 16 * 4 + ev_ids_cap * 8;
+    b += lp_cap * 8 * 8 + lp_he_cap * 2 * 4 + lp_he_cap * 3 * 8 + lp_cap * 4 * 4;
+    b += sizeof(Ctl);
+    return b;
 }
 
 static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
@@ -476,6 +521,7 @@ vls_status vls_mesh_create(vls_context *ctx, int64_t nv, const double *xyz, int6
         (st = upload(m.get(), h.cyc, &d.cyc)) || (st = upload(m.get(), h.src, &d.src)) ||
         (st = upload(m.get(), h.rev, &d.rev)) || (st = upload(m.get(), h.succ, &d.succ)) ||
         (st = upload(m.get(), h.nin, &d.nin)) || (st = upload(m.get(), h.ell, &d.ell)) ||
+        (st = upload(m.get(), h.lrow, &d.lrow)) ||
         (st = upload(m.get(), m->xyz, &d.xyz))) {
         for (void *p : m->allocs) (void)hipFree(p);
         return st;
@@ -521,6 +567,7 @@ static uint64_t splitmix64(uint64_t x) {
 // the step kernel, and what finishing it needs afterwards.
 struct RunPrep {
     vls_mesh *m = nullptr;
+    bool priv = false;          // device state owned by the caller (server request), not by the mesh
     DState s{};
     DParams dp{};
     int64_t seed = 0;
@@ -534,9 +581,10 @@ struct RunPrep {
 };
 
 // checks, device buffers, parameters; enqueues init + seed on the stream
-static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p, RunPrep &rp) {
+static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p, RunPrep &rp,
+                              RunBuffers *priv = nullptr) {
     if (p->struct_size != sizeof(vls_params)) return set_err(ctx, VLS_E_INVALID_ARG, "vls_params.struct_size mismatch");
-    if (m->pending) {
+    if (!priv && m->pending) {
         vls_status fs = fetch_results(m->pending);
         if (fs) return fs;
     }
@@ -551,11 +599,16 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     rp.m = m;
     rp.seed = seed;
     rp.rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
-    if (!m->rb) {
-        vls_status st = make_run_buffers(m, &m->rb);
-        if (st) return st;
+    if (priv) {
+        rp.priv = true;
+        rp.s = priv->s;
+    } else {
+        if (!m->rb) {
+            vls_status st = make_run_buffers(m, &m->rb);
+            if (st) return st;
+        }
+        rp.s = m->rb->s;
     }
-    rp.s = m->rb->s;
     DState &s = rp.s;
     hipStream_t stream = ctx->stream;
     s.n_ckpt = 0;
@@ -660,7 +713,7 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     Pending &pd = r->pend;
     pd.active = true;
     pd.ctx = ctx;
-    pd.mesh = m;
+    pd.mesh = rp.priv ? nullptr : m;
     pd.s = s;
     pd.c = c;
     pd.dpos = dpos;
@@ -670,7 +723,7 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     rp.tmp_allocs.clear();
     pd.rec_field = rp.rec_field;
     if (rp.rec_field) r->ckpt_steps.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
-    m->pending = r.get();
+    if (!rp.priv) m->pending = r.get();
     r->seed_xyz.assign(m->xyz.begin() + 3 * rp.seed, m->xyz.begin() + 3 * rp.seed + 3);
     vls_summary &S = r->sum;
     S.n_handles = (int32_t)c.gsum_h;
@@ -697,7 +750,10 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     S.wait1_ms = (double)c.clk_wait1 * 1e-5;
     S.event_steps = c.event_steps;
     for (int q = 0; q < 4; ++q) S.topo_split_ms[q] = (double)c.clk_t[q] * 1e-5;
-    for (int q = 0; q < 3; ++q) S.field_split_ms[q] = (double)c.clk_f[q] * 1e-5;
+    S.topo_event_ms = (double)c.clk_ev * 1e-5;
+    S.topo_rounds_ms = (double)c.clk_rounds * 1e-5;
+    S.topo_round_steps = c.n_round_steps;
+    S.topo_global_steps = c.n_global_steps;
     vls_status rs = c.status;
     if (rs == VLS_E_INVARIANT || rs == VLS_E_CAPACITY)
         set_err(ctx, rs, "device reported %s (detail %d) at step %lld", vls_status_string(rs), c.err_code, (long long)c.steps);
@@ -706,7 +762,7 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
                 (long long)c.n_inside, (long long)nv);
     else if (rs == VLS_E_SEED_INVALID)
         set_err(ctx, rs, "seed region around vertex %lld is not a disk-like region", (long long)rp.seed);
-    if (!(p->flags & VLS_DEFER_RESULTS)) {
+    if (rp.priv || !(p->flags & VLS_DEFER_RESULTS)) {
         vls_status fs = fetch_results(r.get());
         if (fs) return fs;
     }
@@ -793,7 +849,7 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
     HIPCHK(ctx, hipEventCreate(&b1));
     HIPCHK(ctx, hipEventRecord(b0, stream));
     hipError_t le = launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dpp, (const int32_t *)dord, n,
-                                 (int *)dnext, grid, lds, stream);
+                                 (int *)dnext, grid, lds, ~0ull, nullptr, stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "batch kernel launch: %s", hipGetErrorString(le));
     HIPCHK(ctx, hipEventRecord(b1, stream));
     HIPCHK(ctx, hipEventSynchronize(b1));
@@ -987,6 +1043,293 @@ vls_status vls_result_destroy(vls_result *r) {
         for (void *q : pd.tmp_allocs) (void)hipFree(q);
     }
     delete r;
+    return VLS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching over bounded launches of the batched kernel
+// ---------------------------------------------------------------------------
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvReq {
+    uint64_t ticket = 0;
+    vls_mesh *m = nullptr;
+    vls_params p{};
+    std::vector<int64_t> ckpt;
+    size_t bytes = 0;
+    std::unique_ptr<RunBuffers> rb;
+    std::unique_ptr<RunPrep> prep;
+    vls_status status = VLS_E_PENDING;
+    vls_result *res = nullptr;
+    Clock::time_point t_submit, t_admit, t_done;
+    bool done = false;
+};
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+}  // namespace
+
+struct vls_server {
+    vls_context ctx;                 // private stream on the caller's device
+    size_t budget = 0;
+    int max_slots = 0;
+    unsigned long long slice_ticks = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<SrvReq *> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<SrvReq>> reqs;
+    std::vector<SrvReq *> active;    // touched by the scheduler thread only
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    size_t used = 0;
+    int64_t launches = 0, completed = 0;
+    std::thread th;
+    // launch descriptors on the device, rebuilt when the running set changes
+    void *dm = nullptr, *ds = nullptr, *dp = nullptr, *dord = nullptr, *dnext = nullptr, *ddone = nullptr;
+    int cap = 0;
+    std::vector<int32_t> hdone;
+    std::string thread_err;
+
+    ~vls_server() {
+        for (void *q : {dm, ds, dp, dord, dnext, ddone}) if (q) (void)hipFree(q);
+        if (ctx.own_stream && ctx.stream) (void)hipStreamDestroy(ctx.stream);
+    }
+    void finish(SrvReq *q, vls_status st, vls_result *r);
+    void complete(SrvReq *q);
+    bool admit_one(SrvReq *q);
+    bool launch_slice();
+    void loop();
+};
+
+// marks q done (status, result), releases its admission charge
+void vls_server::finish(SrvReq *q, vls_status st, vls_result *r) {
+    q->rb.reset();
+    q->prep.reset();
+    std::lock_guard<std::mutex> lk(mu);
+    q->status = st;
+    q->res = r;
+    q->t_done = Clock::now();
+    if (r) {
+        r->sum.server_queue_ms = ms_between(q->t_submit, q->t_admit);
+        r->sum.server_latency_ms = ms_between(q->t_submit, q->t_done);
+    }
+    q->done = true;
+    used -= q->bytes;
+    completed += 1;
+}
+
+// a request whose step kernel finished: post-passes, results to the host
+void vls_server::complete(SrvReq *q) {
+    std::unique_ptr<vls_result> r;
+    if (hipEventRecord(q->prep->e2, ctx.stream) != hipSuccess) { finish(q, VLS_E_DEVICE, nullptr); return; }
+    vls_status rs = finish_run(&ctx, *q->prep, &q->p, 0, 256, -1.0, r);
+    finish(q, r ? rs : (rs ? rs : VLS_E_DEVICE), r.release());
+}
+
+// device run state and seed initialisation of a newly admitted request
+bool vls_server::admit_one(SrvReq *q) {
+    q->t_admit = Clock::now();
+    RunBuffers *rb = nullptr;
+    vls_status st = make_run_buffers(q->m, &rb);
+    if (st) { finish(q, st, nullptr); return false; }
+    q->rb.reset(rb);
+    q->prep = std::make_unique<RunPrep>();
+    vls_params pp = q->p;
+    pp.ckpt_steps = q->ckpt.empty() ? nullptr : q->ckpt.data();
+    q->p = pp;
+    st = prepare_run(&ctx, q->m, &q->p, *q->prep, q->rb.get());
+    if (st) { finish(q, st, nullptr); return false; }
+    return true;
+}
+
+// one bounded launch over the running requests (largest first); false on a
+// device error (every running request then fails)
+bool vls_server::launch_slice() {
+    const int n = (int)active.size();
+    if (n > cap) {
+        for (void *q : {dm, ds, dp, dord, dnext, ddone}) if (q) (void)hipFree(q);
+        dm = ds = dp = dord = dnext = ddone = nullptr;
+        int c = 64;
+        while (c < n) c <<= 1;
+        if (hipMalloc(&dm, c * sizeof(DMesh)) || hipMalloc(&ds, c * sizeof(DState)) ||
+            hipMalloc(&dp, c * sizeof(DParams)) || hipMalloc(&dord, c * sizeof(int32_t)) ||
+            hipMalloc(&dnext, sizeof(int)) || hipMalloc(&ddone, c * sizeof(int32_t)))
+            return false;
+        cap = c;
+    }
+    std::vector<DMesh> hm(n);
+    std::vector<DState> hs(n);
+    std::vector<DParams> hp(n);
+    std::vector<int32_t> order(n);
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+        hm[i] = active[i]->m->d;
+        hs[i] = active[i]->prep->s;
+        hp[i] = active[i]->prep->dp;
+        order[i] = i;
+        lds = std::max(lds, step_lds_bytes(256, active[i]->m->dmax));
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return active[a]->m->nv > active[b]->m->nv; });
+    hipStream_t st = ctx.stream;
+    if (hipMemcpyAsync(dm, hm.data(), n * sizeof(DMesh), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(ds, hs.data(), n * sizeof(DState), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(dp, hp.data(), n * sizeof(DParams), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(dord, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st) ||
+        hipMemsetAsync(dnext, 0, sizeof(int), st))
+        return false;
+    int grid = max_coresident_batch(lds);
+    if (grid <= 0) return false;
+    if (grid > n) grid = n;
+    if (launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dp, (const int32_t *)dord, n, (int *)dnext,
+                     grid, lds, slice_ticks, (int32_t *)ddone, st) != hipSuccess)
+        return false;
+    hdone.assign(n, 0);
+    if (hipMemcpyAsync(hdone.data(), ddone, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
+        hipStreamSynchronize(st))
+        return false;
+    launches += 1;
+    // done_out is indexed by visit order
+    std::vector<SrvReq *> still;
+    std::vector<SrvReq *> fin;
+    std::vector<int32_t> flag(n, 0);
+    for (int w = 0; w < n; ++w) flag[order[w]] = hdone[w];
+    for (int i = 0; i < n; ++i) (flag[i] ? fin : still).push_back(active[i]);
+    active.swap(still);
+    for (SrvReq *q : fin) complete(q);
+    return true;
+}
+
+void vls_server::loop() {
+    (void)hipSetDevice(ctx.device);
+    for (;;) {
+        std::vector<SrvReq *> admit;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            if (stop) break;
+            while (!queue.empty() && (int)(active.size() + admit.size()) < max_slots) {
+                SrvReq *q = queue.front();
+                if (used + q->bytes > budget && !(active.empty() && admit.empty())) break;
+                queue.pop_front();
+                used += q->bytes;
+                admit.push_back(q);
+            }
+        }
+        for (SrvReq *q : admit)
+            if (admit_one(q)) active.push_back(q);
+        if (active.empty()) continue;
+        if (!launch_slice()) {
+            thread_err = "device error in the server's step launch";
+            for (SrvReq *q : active) finish(q, VLS_E_DEVICE, nullptr);
+            active.clear();
+        }
+    }
+}
+
+extern "C" {
+
+vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t max_slots, int64_t slice_us,
+                             vls_server **out) {
+    if (!ctx || !out || max_slots < 1 || slice_us < 1 || hbm_budget_bytes == 0)
+        return set_err(ctx, VLS_E_INVALID_ARG, "bad server arguments");
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    auto s = std::make_unique<vls_server>();
+    s->ctx.device = ctx->device;
+    if (hipStreamCreateWithFlags(&s->ctx.stream, hipStreamNonBlocking) != hipSuccess)
+        return set_err(ctx, VLS_E_DEVICE, "server stream");
+    s->ctx.own_stream = true;
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    s->slice_ticks = (unsigned long long)slice_us * 100ull;    // s_memrealtime runs at 100 MHz
+    vls_server *raw = s.get();
+    try {
+        s->th = std::thread([raw] { raw->loop(); });
+    } catch (...) {
+        return set_err(ctx, VLS_E_OUT_OF_MEMORY, "server thread");
+    }
+    *out = s.release();
+    return VLS_OK;
+}
+
+vls_status vls_server_submit(vls_server *srv, const vls_mesh *m, const vls_params *p, uint64_t *ticket) {
+    if (!srv || !m || !p || !ticket) return VLS_E_INVALID_ARG;
+    if (p->struct_size != sizeof(vls_params)) return VLS_E_INVALID_ARG;
+    auto q = std::make_unique<SrvReq>();
+    q->m = const_cast<vls_mesh *>(m);
+    q->p = *p;
+    q->p.flags &= ~VLS_DEFER_RESULTS;
+    const bool rec = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
+    if (rec) q->ckpt.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
+    else { q->p.n_ckpt = 0; q->p.ckpt_steps = nullptr; q->p.flags &= ~VLS_RECORD_FIELD; }
+    q->bytes = run_buffer_bytes(q->m) + (rec ? (size_t)p->n_ckpt * (size_t)m->nv * sizeof(double) : 0);
+    q->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop) return VLS_E_CANCELLED;
+        q->ticket = srv->next_ticket++;
+        *ticket = q->ticket;
+        srv->queue.push_back(q.get());
+        srv->reqs.emplace(q->ticket, std::move(q));
+    }
+    srv->cv.notify_one();
+    return VLS_OK;
+}
+
+vls_status vls_server_poll(vls_server *srv, uint64_t ticket, vls_result **out) {
+    if (!srv || !out) return VLS_E_INVALID_ARG;
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return VLS_E_INVALID_ARG;
+    SrvReq *q = it->second.get();
+    if (!q->done) return VLS_E_PENDING;
+    const vls_status st = q->status;
+    *out = q->res;
+    srv->reqs.erase(it);
+    return st;
+}
+
+vls_status vls_server_stats(const vls_server *srv, int64_t *launches, int64_t *completed, int64_t *admitted_bytes,
+                            int32_t *queued, int32_t *running) {
+    if (!srv) return VLS_E_INVALID_ARG;
+    vls_server *s = const_cast<vls_server *>(srv);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (launches) *launches = s->launches;
+    if (completed) *completed = s->completed;
+    if (admitted_bytes) *admitted_bytes = (int64_t)s->used;
+    if (queued) *queued = (int32_t)s->queue.size();
+    if (running) {
+        int32_t r = 0;
+        for (auto &kv : s->reqs) r += !kv.second->done;
+        *running = r - (int32_t)s->queue.size();
+    }
+    return VLS_OK;
+}
+
+vls_status vls_server_destroy(vls_server *srv) {
+    if (!srv) return VLS_E_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->queue.clear();
+    }
+    srv->cv.notify_all();
+    if (srv->th.joinable()) srv->th.join();
+    (void)hipSetDevice(srv->ctx.device);
+    (void)hipStreamSynchronize(srv->ctx.stream);
+    for (SrvReq *q : srv->active) { q->rb.reset(); q->prep.reset(); }
+    srv->active.clear();
+    for (auto &kv : srv->reqs)
+        if (kv.second->res) (void)vls_result_destroy(kv.second->res);
+    srv->reqs.clear();
+    delete srv;
     return VLS_OK;
 }
 

@@ -26,6 +26,9 @@ struct DMesh {
     const int32_t *nin;   // [nnz]  e=(u->x), y=cyc[succ[e]]: index of half-edge (y->x)
     const int32_t *ell;   // [nv][ELL_W] ascending neighbours padded with the vertex itself;
                           //   first entry -1 when the degree exceeds ELL_W
+    const int32_t *lrow;  // [nv][ELL_W] counter-clockwise neighbours from the smallest id,
+                          //   padded with -1, first half-edge index in the last slot;
+                          //   first entry -2 when the degree exceeds ELL_W - 1
     const double *xyz;    // [nv][3]
 };
 
@@ -66,9 +69,14 @@ struct Ctl {
     // phase clocks (s_memrealtime ticks, 100 MHz): workgroup 0 topology,
     // workgroup 0 barrier wait, workgroup 1 field, workgroup 1 barrier wait
     unsigned long long clk_topo, clk_wait0, clk_field, clk_wait1;
-    // finer split: topology (gather, closure, classify, insert/events),
-    // field on workgroup 1 (gather+update, claims, list flush)
-    unsigned long long clk_t[4], clk_f[3];
+    // finer split of the topology: candidates, closure, classification,
+    // insertion (of which: steps with events, closure rounds after round 0)
+    unsigned long long clk_t[4];
+    unsigned long long clk_ev, clk_rounds;
+    int32_t n_round_steps, n_global_steps;
+    // batched mode: next iteration to run (a mesh may be advanced over
+    // several launches, each visit bounded in time)
+    int64_t biter;
 };
 
 // run state in HBM
@@ -131,7 +139,8 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
                         hipStream_t st);
 int max_coresident_blocks(int block, size_t lds_bytes);
 hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order, int n,
-                        int *next_mesh, int grid, size_t lds, hipStream_t st);
+                        int *next_mesh, int grid, size_t lds, unsigned long long budget_ticks, int32_t *done_out,
+                        hipStream_t st);
 int max_coresident_batch(size_t lds_bytes);
 size_t step_lds_bytes(int block, int dmax);
 hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt,

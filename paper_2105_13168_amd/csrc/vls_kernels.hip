@@ -1142,6 +1142,8 @@ struct KL {
     int32_t Lt[LCAP];       // round 0: tag of the half-edge (parent -> v)
     int32_t Ld[LCAP];       // round 0: depth of v
     uint64_t Lm[LCAP];      // lower-neighbour mask (link positions < 64)
+    int32_t Lb[LCAP];       // first half-edge of v
+    int32_t Lg[LCAP];       // degree of v
     int32_t hk[HCAP];       // hash: vertex id (-1 empty)
     int32_t hv[HCAP];       // hash: entry index
 };
@@ -1167,6 +1169,30 @@ __device__ __forceinline__ void gather_link(const DMesh &m, const uint64_t *key,
     for (int j = 0; j < GB; ++j) nb[j] = c0 + j < d ? ldg(m.cyc + b + c0 + j) : -1;
 #pragma unroll
     for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(key + nb[j]) : KEY_OUT;
+}
+
+// link row of x in one 64 B load: counter-clockwise neighbours from the
+// smallest id (then -1) and the first half-edge of x in the last slot;
+// false for a vertex wider than the row (its link is read through rp/cyc)
+__device__ __forceinline__ bool load_lrow(const DMesh &m, int32_t x, int32_t *nb, int32_t &b, int &d) {
+    const GLOBAL_AS v4i *row = (const GLOBAL_AS v4i *)(m.lrow + (int64_t)x * ELL_W);
+    int32_t r[ELL_W];
+#pragma unroll
+    for (int q = 0; q < ELL_W / 4; ++q) {
+        const v4i w = row[q];
+        r[4 * q] = w.x; r[4 * q + 1] = w.y; r[4 * q + 2] = w.z; r[4 * q + 3] = w.w;
+    }
+    b = r[ELL_W - 1];
+    if (r[0] < -1) return false;
+    int n = 0;
+#pragma unroll
+    for (int j = 0; j < ELL_W - 1; ++j) {
+        nb[j] = r[j];
+        n += r[j] >= 0;
+    }
+    nb[ELL_W - 1] = -1;
+    d = n;
+    return true;
 }
 
 template <int CM>
@@ -1219,21 +1245,32 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     bool cached = false;
     for (int i = tid; i < nL; i += NT) {
         const int32_t x = kl->Lv[i];
-        const int32_t b = ldg(m.rp + x);
-        const int d = ldg(m.rp + x + 1) - b;
+        int32_t b;
+        int d;
         bool hit = false;
-        for (int c0 = 0; c0 < d; c0 += GB) {
-            int32_t nb[GB];
+        int32_t nb[GB];
+        if (load_lrow(m, x, nb, b, d)) {
             uint64_t kn[GB];
-            gather_link(m, s.key, b, d, c0, nb, kn);
+#pragma unroll
+            for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(s.key + nb[j]) : KEY_OUT;
 #pragma unroll
             for (int j = 0; j < GB; ++j) hit = hit || kn[j] < tk;
-            if (i == tid && d <= GB) {
+            if (i == tid) {
 #pragma unroll
                 for (int j = 0; j < GB; ++j) { cnb[j] = nb[j]; ckn[j] = kn[j]; }
                 cached = true;
             }
+        } else {
+            d = ldg(m.rp + x + 1) - b;
+            for (int c0 = 0; c0 < d; c0 += GB) {
+                uint64_t kn[GB];
+                gather_link(m, s.key, b, d, c0, nb, kn);
+#pragma unroll
+                for (int j = 0; j < GB; ++j) hit = hit || kn[j] < tk;
+            }
         }
+        kl->Lb[i] = b;
+        kl->Lg[i] = d;
         kl->Lr[i] = hit ? 0 : -1;
         n0 += hit;
     }
@@ -1242,14 +1279,23 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     int nrounds = sh->nN ? 1 : 0;
     // later rounds (rare): touch the previous round, found through the hash
     if (sh->nN && sh->nN < nL) {
+        const unsigned long long kr = __builtin_amdgcn_s_memrealtime();
         for (int round = 1;; ++round) {
             for (int i = tid; i < nL; i += NT) {
                 int flag = 0;
                 if (kl->Lr[i] == -1) {
-                    const int32_t x = kl->Lv[i];
-                    for (int32_t j = m.rp[x]; j < m.rp[x + 1] && !flag; ++j) {
-                        const int q = hfind(kl, m.cyc[j]);
-                        if (q >= 0 && kl->Lr[q] == round - 1) flag = 1;
+                    if (i == tid && cached) {
+#pragma unroll
+                        for (int j = 0; j < GB; ++j) {
+                            const int q = cnb[j] >= 0 ? hfind(kl, cnb[j]) : -1;
+                            if (q >= 0 && kl->Lr[q] == round - 1) flag = 1;
+                        }
+                    } else {
+                        const int32_t b = kl->Lb[i], e = b + kl->Lg[i];
+                        for (int32_t j = b; j < e && !flag; ++j) {
+                            const int q = hfind(kl, ldg(m.cyc + j));
+                            if (q >= 0 && kl->Lr[q] == round - 1) flag = 1;
+                        }
                     }
                 }
                 kl->Lc[i] = flag;
@@ -1270,6 +1316,10 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
             __syncthreads();
             if (sh->nN == nL) break;
         }
+        if (tid == 0) {
+            ctl->clk_rounds += __builtin_amdgcn_s_memrealtime() - kr;
+            ctl->n_round_steps += 1;
+        }
     }
     __syncthreads();
     k2 = __builtin_amdgcn_s_memrealtime();
@@ -1279,8 +1329,8 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         const int rv = kl->Lr[i];
         if (rv < 0) continue;
         const int32_t x = kl->Lv[i];
-        const int32_t b = ldg(m.rp + x);
-        const int d = ldg(m.rp + x + 1) - b;
+        const int32_t b = kl->Lb[i];
+        const int d = kl->Lg[i];
         int nlow = 0, runs = 0, ppos = -1;
         int32_t par = -1;
         uint64_t kp = KEY_OUT;
@@ -1349,8 +1399,8 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
             for (int i = tid; i < nL; i += NT) {
                 if (kl->Lr[i] != r) continue;
                 const int32_t v = kl->Lv[i];
-                const int32_t b = ldg(m.rp + v);
-                const int d = ldg(m.rp + v + 1) - b;
+                const int32_t b = kl->Lb[i];
+                const int d = kl->Lg[i];
                 const int32_t par = kl->Lp[i];
                 int32_t tag;
                 if (r == 0) {
@@ -1405,7 +1455,10 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
             }
             pos = q + 1;
         }
-        if (tid == 0) ctl->event_steps += 1;
+        if (tid == 0) {
+            ctl->event_steps += 1;
+            ctl->clk_ev += __builtin_amdgcn_s_memrealtime() - k3;
+        }
     }
     // 5. crossers not connected this step wait for the next
     for (int i = tid; i < nL; i += NT)
@@ -1428,6 +1481,7 @@ __device__ __forceinline__ void phase_topo(const DMesh &m, const DState &s, cons
     const int np = ctl->cnt_pend[(t - 1) & 1];
     if (p.topo_global || nc + np > LCAP) {
         phase_topo_global<CM>(m, s, p, t, sh, lsort);
+        if (threadIdx.x == 0) ctl->n_global_steps += 1;
         return;
     }
     phase_topo_lds<CM>(m, s, p, t, sh, kl, lsort, nc, np);
@@ -1630,10 +1684,18 @@ __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) 
 // separated by workgroup barriers only (no grid barrier, no cross-workgroup
 // sharing inside a mesh).
 // ---------------------------------------------------------------------------
+// Batched mode: a pool of workgroups, one mesh per workgroup at a time,
+// meshes taken largest first from a shared counter.  Each workgroup runs
+// the topology of step j and the field of step j+1 back to back.  A visit
+// ends when the mesh is done or, at an iteration boundary, once the visit
+// has used budget_ticks of s_memrealtime (100 MHz); the next iteration is
+// kept in the mesh's control block, so a later launch continues it with
+// the same arithmetic.  done_out[w] reports each visited mesh's state.
 __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss, const DParams *ps,
-                                              const int32_t *order, int n, int *next_mesh) {
+                                              const int32_t *order, int n, int *next_mesh,
+                                              unsigned long long budget_ticks, int32_t *done_out) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int cur;
+    __shared__ int cur, yield;
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
     KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
@@ -1650,7 +1712,15 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
         Ctl *ctl = s.ctl;
         const unsigned long long c_start = __builtin_amdgcn_s_memrealtime();
         if (!ctl->done) {
-            for (int64_t j = 0;; ++j) {
+            const int64_t j0 = ctl->biter;
+            for (int64_t j = j0;; ++j) {
+                if (threadIdx.x == 0)
+                    yield = j > j0 && __builtin_amdgcn_s_memrealtime() - c_start >= budget_ticks;
+                __syncthreads();
+                if (yield) {
+                    if (threadIdx.x == 0) ctl->biter = j;
+                    break;
+                }
                 if (threadIdx.x == 0) {
                     ctl->cnt_act[(j + 3) & 3] = 0;
                     ctl->cnt_cand[(j + 2) & 3] = 0;
@@ -1671,14 +1741,19 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
                 __syncthreads();
             }
         }
-        if (threadIdx.x == 0) ctl->clk_topo = __builtin_amdgcn_s_memrealtime() - c_start;
+        if (threadIdx.x == 0) {
+            ctl->clk_topo += __builtin_amdgcn_s_memrealtime() - c_start;
+            if (done_out) done_out[w] = ctl->done;
+        }
         __syncthreads();
     }
 }
 
 hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order, int n,
-                        int *next_mesh, int grid, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(NT), lds, st, ms, ss, ps, order, n, next_mesh);
+                        int *next_mesh, int grid, size_t lds, unsigned long long budget_ticks, int32_t *done_out,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(NT), lds, st, ms, ss, ps, order, n, next_mesh, budget_ticks,
+                       done_out);
     return hipGetLastError();
 }
 

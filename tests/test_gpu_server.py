@@ -1,0 +1,138 @@
+"""Serving: requests submitted while others run are admitted as slots and
+HBM budget free up and advance together in bounded launches (each mesh's
+visit cut at a step boundary, then continued by a later launch).  Every
+result equals the oracle's element by element, and equals the same mesh
+run alone, whatever the mix, the slice length or the admission order."""
+import time
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+from _parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _meshes():
+    return [
+        mg.torus_grid(rng_seed=0),
+        mg.torus_grid(96, 48, rng_seed=7),
+        mg.sdf_surface(mg.sdf_sphere(), (-1, -1, -1), (1, 1, 1), 16, 1e-4, 0),
+        mg.multi_torus(2, 28, rng_seed=3),
+        mg.pretzel(40, rng_seed=5),
+        mg.multi_torus(4, 40, rng_seed=4),
+    ]
+
+
+def _wait(srv, tickets, timeout=90.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout, f"server requests not done after {timeout} s: {srv.stats()}"
+        time.sleep(0.002)
+    return [out[t] for t in tickets]
+
+
+def _same(a, b):
+    assert a.summary["steps"] == b.summary["steps"]
+    assert np.array_equal(a.rho.view(np.int64), b.rho.view(np.int64))
+    assert np.array_equal(a.step, b.step) and np.array_equal(a.parent, b.parent)
+    assert np.array_equal(a.events, b.events)
+    assert len(a.loops) == len(b.loops)
+    for x, y in zip(a.loops, b.loops):
+        assert np.array_equal(x["he"], y["he"]) and x["length"] == y["length"]
+    assert len(a.tunnels) == len(b.tunnels)
+    for x, y in zip(a.tunnels, b.tunnels):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("slice_us", [150, 5000])
+def test_server_mix_matches_oracle_and_solo(oracle_mod, slice_us):
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    ms = _meshes()
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    srv = vls.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=64, slice_us=slice_us)
+    try:
+        # staggered arrivals; the first torus twice at once (own run state
+        # per request); checkpoints on one request
+        tickets = []
+        for i, (m, h) in enumerate(zip(ms, M)):
+            ck = [1, 100, 300] if i == 0 else ()
+            tickets.append(srv.submit(h, seed_vertex=m.seed, ckpt_steps=ck))
+            if i == 2:
+                tickets.append(srv.submit(M[0], seed_vertex=ms[0].seed))
+            time.sleep(0.003)
+        res = _wait(srv, tickets)
+        st = srv.stats()
+        assert st["completed"] == len(tickets) and st["admitted_bytes"] == 0
+        if slice_us < 1000:
+            assert st["launches"] > 2        # visits were cut and continued
+        order = list(range(len(ms)))
+        order.insert(3, 0)
+        for k, r in zip(order, res):
+            m = ms[k]
+            assert r.summary["run_status"] == 0
+            assert r.summary["server_latency_ms"] >= r.summary["server_queue_ms"] >= 0
+            o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed, ckpt_steps=[1, 100, 300] if r is res[0] else ())
+            bad = compare(r, o, m.nv)
+            assert not bad, (m.name, bad)
+        for k in (0, 5):
+            solo = M[k].run(seed_vertex=ms[k].seed)
+            _same(solo, res[order.index(k)])
+        _same(res[0], res[3])
+    finally:
+        srv.close()
+        for x in M:
+            x.close()
+        ctx.close()
+
+
+def test_server_budget_admission_one_at_a_time(oracle_mod):
+    """A budget below any one request's run state admits one request at a
+    time (the oversize rule); results are unchanged."""
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    ms = _meshes()[:4]
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    srv = vls.Server(ctx, hbm_budget_bytes=1, max_slots=8, slice_us=1000)
+    try:
+        tickets = [srv.submit(h, seed_vertex=m.seed) for m, h in zip(ms, M)]
+        seen_running = 0
+        t0 = time.time()
+        while srv.stats()["completed"] < len(tickets) and time.time() - t0 < 60:
+            seen_running = max(seen_running, srv.stats()["running"])
+            time.sleep(0.0005)
+        assert seen_running <= 1
+        res = _wait(srv, tickets)
+        for m, r in zip(ms, res):
+            bad = compare(r, oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed), m.nv)
+            assert not bad, (m.name, bad)
+    finally:
+        srv.close()
+        for x in M:
+            x.close()
+        ctx.close()
+
+
+def test_server_destroy_with_work_in_flight():
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    m = mg.pretzel(48, rng_seed=1)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    srv = vls.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=2, slice_us=200)
+    for _ in range(6):
+        srv.submit(M, seed_vertex=m.seed)
+    time.sleep(0.01)
+    srv.close()
+    # the context and mesh still work afterwards
+    r = M.run(seed_vertex=m.seed)
+    assert r.summary["run_status"] == 0
+    M.close()
+    ctx.close()
