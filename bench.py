@@ -40,6 +40,11 @@ def make_workload(name):
     elif name == "torus64x32":
         m = mg.torus_grid(rng_seed=0)
         desc = "64x32 torus grid, R=1, r=0.4"
+    elif name.startswith("lattice10_"):
+        grid = int(name.split("_")[1])
+        m = mg.lattice(10, grid, rng_seed=0)
+        desc = (f"strut lattice, 10^3 cells (3630 struts of radius 0.15, genus 2300), level-0 surface on a "
+                f"{grid}^3 grid over [-0.5, 10.5]^3 (marching tetrahedra), random seed vertex")
     else:
         raise SystemExit(f"unknown workload {name}")
     return m, desc
@@ -198,7 +203,9 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = vls.Context(0, stream=stream.cuda_stream)
+    t1 = time.time()
     M = vls.Mesh(ctx, m.xyz, m.tri)
+    log(f"mesh validated, adjacency built and uploaded ({time.time() - t1:.1f}s)")
 
     def one_pass():
         p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_DEFER_RESULTS, grid=args.grid)

@@ -376,3 +376,144 @@ def batch_workload(n: int = 1024, base_seed: int = 0, pretzel_grids=(32, 48, 64,
             m = jittered(base, 1e-4, base_seed + i, f"torus_chain{g}_{gn}")
         out.append(m)
     return out
+
+
+# ---------------------------------------------------------------------------
+# large surfaces: marching tetrahedra streamed by slabs of grid planes
+# ---------------------------------------------------------------------------
+def marching_tets_slabs(plane_f, lo, hi, shape, slab: int = 16, chunk_cells: int = 1 << 21) -> Mesh:
+    """Level-0 surface of a field given plane by plane: ``plane_f(x, Y, Z)``
+    returns f on the grid plane at abscissa x (Y, Z: 2-D coordinate arrays).
+    Same extraction as ``marching_tets`` (six tetrahedra per cell, inside
+    means f < 0, vertices on crossed tet edges welded by grid-edge key and
+    numbered in ascending key order), but only ``slab`` + 1 planes of samples
+    are held at a time, so grids of 1024^3 samples fit in host memory."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    nx, ny, nz = (int(s) for s in shape)
+    npts = nx * ny * nz
+    h = (hi - lo) / (np.array([nx, ny, nz], dtype=np.float64) - 1.0)
+    xs = lo[0] + h[0] * np.arange(nx)
+    ys = lo[1] + h[1] * np.arange(ny)
+    zs = lo[2] + h[2] * np.arange(nz)
+    Y, Z = np.meshgrid(ys, zs, indexing="ij")
+    corner_off = np.array([dx * ny * nz + dy * nz + dz
+                           for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)], dtype=np.int64)
+    keys_u, xyz_u, tri_keys = [], [], []
+    prev = None                                    # last plane of the previous slab
+    for i0 in range(0, nx - 1, slab):
+        i1 = min(nx - 1, i0 + slab)                # cells i0..i1-1, planes i0..i1
+        planes = [prev if (prev is not None and i == i0) else plane_f(xs[i], Y, Z) for i in range(i0, i1 + 1)]
+        F = np.stack(planes)
+        prev = planes[-1]
+        del planes
+        neg = F < 0
+        nxs = i1 - i0 + 1
+        anyin = np.zeros((nxs - 1, ny - 1, nz - 1), dtype=bool)
+        allin = np.ones((nxs - 1, ny - 1, nz - 1), dtype=bool)
+        for dx in (0, 1):
+            for dy in (0, 1):
+                for dz in (0, 1):
+                    s = neg[dx:nxs - 1 + dx, dy:ny - 1 + dy, dz:nz - 1 + dz]
+                    anyin |= s
+                    allin &= s
+        cells = np.flatnonzero(anyin & ~allin)
+        del anyin, allin
+        if cells.size == 0:
+            continue
+        ci, rem = np.divmod(cells, (ny - 1) * (nz - 1))
+        cj, ck = np.divmod(rem, nz - 1)
+        lbase = ci * ny * nz + cj * nz + ck        # local grid id (slab planes)
+        off0 = i0 * ny * nz                        # local -> global grid id
+        Ff = F.ravel()
+        negf = neg.ravel()
+        kl = []
+        for s0 in range(0, lbase.size, chunk_cells):
+            b = lbase[s0:s0 + chunk_cells]
+            for t in range(6):
+                g = b[:, None] + corner_off[_TETS[t]][None, :]
+                ins = negf[g]
+                case = ins[:, 0] * 1 + ins[:, 1] * 2 + ins[:, 2] * 4 + ins[:, 3] * 8
+                for k in (0, 1):
+                    sel = _NTRI[case] > k
+                    if not np.any(sel):
+                        continue
+                    e = _CASES[case[sel], k]
+                    gs = g[sel]
+                    ga = np.take_along_axis(gs, e[:, :, 0], axis=1)
+                    gb = np.take_along_axis(gs, e[:, :, 1], axis=1)
+                    kl.append(np.minimum(ga, gb) * (nxs * ny * nz) + np.maximum(ga, gb))
+        lk = np.concatenate(kl, axis=0)
+        del kl
+        nloc = nxs * ny * nz
+        uk, inv = np.unique(lk.ravel(), return_inverse=True)
+        ga = uk // nloc
+        gb = uk % nloc
+        fa = Ff[ga]
+        fb = Ff[gb]
+        tt = fa / (fa - fb)
+
+        def coords(gid):
+            i, r = np.divmod(gid, ny * nz)
+            j, kk = np.divmod(r, nz)
+            return np.stack([xs[i + i0], ys[j], zs[kk]], axis=1)
+        pa = coords(ga)
+        pb = coords(gb)
+        xyz_u.append(pa + tt[:, None] * (pb - pa))
+        gk = (ga + off0) * npts + (gb + off0)      # global edge keys
+        keys_u.append(gk)
+        tri_keys.append(gk[inv].reshape(-1, 3))
+        del F, neg, lk, uk, inv
+    allk = np.concatenate(keys_u)
+    allx = np.concatenate(xyz_u)
+    del keys_u, xyz_u
+    u, first = np.unique(allk, return_index=True)
+    xyz = allx[first]
+    del allk, allx
+    tri = np.concatenate([np.searchsorted(u, tk).astype(np.int32) for tk in tri_keys])
+    return Mesh(xyz.astype(np.float64), tri, 0, "mt_slabs")
+
+
+def lattice_plane_sdf(n_cells: int, radius: float):
+    """Signed distance to the struts of the cubic lattice with nodes at the
+    integer points of [0, n]^3 and a strut of the given radius on every
+    edge between neighbouring nodes, evaluated on a plane of constant x:
+    for each axis the nearest parallel strut line is found by rounding the
+    two other coordinates into [0, n]; beyond the lattice the distance
+    along the line is measured to the strut's end."""
+    n = float(n_cells)
+
+    def f(x, Y, Z):
+        jj = np.clip(np.rint(Y), 0.0, n)
+        kk = np.clip(np.rint(Z), 0.0, n)
+        ii = min(max(float(np.rint(x)), 0.0), n)
+        ex = max(0.0, -x, x - n)
+        ey = np.maximum(0.0, np.maximum(-Y, Y - n))
+        ez = np.maximum(0.0, np.maximum(-Z, Z - n))
+        dyj = Y - jj
+        dzk = Z - kk
+        dxi = x - ii
+        d1 = np.sqrt(dyj * dyj + dzk * dzk + ex * ex)
+        d2 = np.sqrt(dxi * dxi + dzk * dzk + ey * ey)
+        d3 = np.sqrt(dxi * dxi + dyj * dyj + ez * ez)
+        return np.minimum(np.minimum(d1, d2), d3) - radius
+    return f
+
+
+def lattice_genus(n_cells: int) -> int:
+    """Genus of the thickened cubic lattice graph: edges - nodes + 1."""
+    n = n_cells
+    return 3 * n * (n + 1) ** 2 - (n + 1) ** 3 + 1
+
+
+def lattice(n_cells: int = 10, grid: int = 1024, radius: float = 0.15, sigma: float = 0.0,
+            rng_seed: int = 0, slab: int = 16) -> Mesh:
+    """Strut lattice surface: level 0 of ``lattice_plane_sdf`` on grid^3
+    samples over [-0.5, n + 0.5]^3, optional N(0, sigma^2) jitter, then a
+    random seed vertex from rng_seed.  Genus ``lattice_genus(n_cells)``."""
+    lo = (-0.5, -0.5, -0.5)
+    hi = (n_cells + 0.5,) * 3
+    m = marching_tets_slabs(lattice_plane_sdf(n_cells, radius), lo, hi, (grid, grid, grid), slab)
+    m = jittered(m, sigma, rng_seed, f"lattice{n_cells}_{grid}") if sigma > 0 else \
+        Mesh(m.xyz, m.tri, 0, f"lattice{n_cells}_{grid}")
+    return m if sigma > 0 else pick_seed(m, rng_seed)

@@ -39,7 +39,13 @@ def summarize(r):
     }
 
 
-def main():
+# full-size workloads: digests of every output plus sampled values
+FULL_CASES = {
+    "pretzel256_s0": lambda: mg.pretzel(256, rng_seed=0),
+}
+
+
+def main(full: bool = True):
     import oracle
     oracle.build(force=False)
     out = {}
@@ -49,7 +55,21 @@ def main():
         out[name] = summarize(r)
     with open(os.path.join(HERE, "oracle_summaries.json"), "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
+    if not full:
+        return
+    sys.path.insert(0, os.path.dirname(HERE))
+    from _digest import canon_oracle, digests
+    full_out = {}
+    for name, make in FULL_CASES.items():
+        m = make()
+        r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed)
+        d = digests(canon_oracle(r))
+        d["nv"] = int(m.nv)
+        d["seed_vertex"] = int(m.seed)
+        full_out[name] = d
+    with open(os.path.join(HERE, "oracle_full.json"), "w") as f:
+        json.dump(full_out, f, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(full="--no-full" not in sys.argv)

@@ -44,6 +44,8 @@ SMALL = [
     ("double_torus32", lambda: mg.multi_torus(2, 32), [1, 500, 1000]),
     ("pretzel48", lambda: mg.pretzel(48), [1, 1000, 2000, 3000]),
     ("thin_strip400x6", lambda: mg.torus_grid(400, 6, R=10.0, r=0.2, jitter=1e-3, rng_seed=0), [1, 1000]),
+    ("lattice2_40", lambda: mg.lattice(2, 40, rng_seed=1), [1, 700, 1500]),
+    ("lattice3_48", lambda: mg.lattice(3, 48, rng_seed=0), [1, 1000, 2500]),
 ]
 
 

@@ -138,6 +138,9 @@ GENUS_CASES = [
     ("torus_mt", lambda s: mg.sdf_surface(mg.sdf_torus(), (-1.35, -1.35, -.35), (1.35, 1.35, .35), 24, 1e-4, s), 1),
     ("double_torus", lambda s: mg.multi_torus(2, 32, rng_seed=s), 2),
     ("pretzel", lambda s: mg.pretzel(40, rng_seed=s), 3),
+    # strut lattices: genus = struts - nodes + 1 (5 for one cell, 28 for 2^3)
+    ("lattice1", lambda s: mg.lattice(1, 24, rng_seed=s), mg.lattice_genus(1)),
+    ("lattice2", lambda s: mg.lattice(2, 40, rng_seed=s), mg.lattice_genus(2)),
 ]
 
 
