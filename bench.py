@@ -161,6 +161,105 @@ def batch_leg(ctx, n, seq_sample):
     }
 
 
+def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0):
+    """Serving: Poisson arrivals at ``rate``/s, each request an initial pass
+    of a mesh drawn from the uneven batch distribution or, with probability
+    ``lattice_share``, from two strut lattices of 2-8M triangles; meshes are
+    uploaded once beforehand (resident operators), run state is allocated per
+    request under an HBM budget of half the free device memory.  Latency =
+    submission to results on the host.  The one-at-a-time GPU path is timed
+    on every distinct mesh (vls_run, default launch) and replayed on the
+    same arrival trace as a first-come-first-served single queue."""
+    import ctypes as C
+    import numpy as np
+    import meshgen as mg
+    import paper_2105_13168_amd as vls
+    import torch
+    rng = np.random.default_rng(seed)
+    t0 = time.time()
+    pool = mg.batch_workload(256, base_seed=1000)
+    lat = [mg.lattice(3, 240, rng_seed=1), mg.lattice(4, 256, rng_seed=2)]
+    meshes = pool + lat
+    log(f"serving pool: {len(pool)} batch-distribution meshes + lattices of "
+        f"{[x.nf for x in lat]} triangles ({time.time() - t0:.1f}s)")
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in meshes]
+    genus = [x.euler_genus for x in M]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    pick = np.where(rng.random(n_req) < lattice_share, len(pool) + rng.integers(0, len(lat), size=n_req),
+                    rng.integers(0, len(pool), size=n_req))
+    free, _total = torch.cuda.mem_get_info()
+    srv = vls.Server(ctx, hbm_budget_bytes=free // 2, max_slots=1024, slice_us=slice_us)
+    # warm-up request (first launch, allocations)
+    t = srv.submit(M[0], seed_vertex=meshes[0].seed)
+    while srv.poll(t) is None:
+        time.sleep(0.001)
+    lat_ms, queue_ms, ok = [], [], True
+    outstanding = {}
+    start = time.perf_counter()
+    nxt = 0
+    last_done = start
+    while nxt < n_req or outstanding:
+        now = time.perf_counter() - start
+        while nxt < n_req and arrivals[nxt] <= now:
+            i = int(pick[nxt])
+            p = vls.default_params(seed_vertex=meshes[i].seed)
+            tk = C.c_uint64()
+            st = vls.vls_server_submit(srv.h, M[i].h, C.byref(p), C.byref(tk))
+            if st != 0:
+                raise vls.VLSError(st, "submit")
+            outstanding[tk.value] = i
+            nxt += 1
+        for tk in list(outstanding):
+            h = C.c_void_p()
+            st = vls.vls_server_poll(srv.h, C.c_uint64(tk), C.byref(h))
+            if st == vls.VLS_E_PENDING:
+                continue
+            i = outstanding.pop(tk)
+            sm = vls.vls_summary()
+            vls.vls_result_summary(h, C.byref(sm))
+            ok = ok and st == 0 and sm.n_handles == genus[i]
+            lat_ms.append(sm.server_latency_ms)
+            queue_ms.append(sm.server_queue_ms)
+            vls.vls_result_destroy(h)
+            last_done = time.perf_counter()
+        time.sleep(0.0005)
+    makespan = last_done - start
+    stats = srv.stats()
+    srv.close()
+    # the one-at-a-time path: service time of every distinct mesh used
+    service = {}
+    for i in sorted(set(int(x) for x in pick)):
+        p = vls.default_params(seed_vertex=meshes[i].seed, flags=vls.VLS_DEFER_RESULTS)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = vls.vls_run(ctx.h, M[i].h, C.byref(p), C.byref(h))
+        vls.vls_result_fetch(h)
+        service[i] = time.perf_counter() - a
+        vls.vls_result_destroy(h)
+    free_at = 0.0
+    seq_lat = []
+    for k in range(n_req):
+        begin = max(free_at, arrivals[k])
+        free_at = begin + service[int(pick[k])]
+        seq_lat.append((free_at - arrivals[k]) * 1e3)
+    for x in M:
+        x.close()
+    lat_ms = np.array(lat_ms)
+    seq_lat = np.array(seq_lat)
+    return {
+        "requests": int(n_req), "rate_per_s": rate, "lattice_share": lattice_share,
+        "lattice_requests": int((pick >= len(pool)).sum()), "slice_us": slice_us,
+        "all_handles_equal_genus": bool(ok),
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "mean_ms": float(lat_ms.mean()), "mean_queue_ms": float(np.mean(queue_ms)),
+        "meshes_per_s": n_req / makespan, "makespan_s": makespan, "launches": stats["launches"],
+        "sequential": {"p50_ms": float(np.percentile(seq_lat, 50)), "p99_ms": float(np.percentile(seq_lat, 99)),
+                       "meshes_per_s": n_req / (free_at - 0.0) if free_at > 0 else None,
+                       "service_ms_mean": 1e3 * float(np.mean([service[int(i)] for i in pick]))},
+    }
+
+
 def cpu_baseline(m, max_steps):
     """The oracle, single-threaded, on the same mesh and seed: the whole pass
     (max_steps 0) or its first max_steps diffusion steps."""
@@ -189,6 +288,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch", type=int, default=1024, help="meshes in the batched leg (0: skip)")
     ap.add_argument("--batch-seq-sample", type=int, default=16)
+    ap.add_argument("--serve", type=int, default=1000, help="requests in the serving trace (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-lattice-share", type=float, default=0.05)
+    ap.add_argument("--serve-slice-us", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -274,11 +377,14 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms),
-                     "kernel": "k_steps", "algorithmic_bytes": ab,
+                     "kernel": "k_steps_dec", "algorithmic_bytes": ab,
                      "kernel_source_hash": kernel_source_hash()},
     }
     if args.batch > 0:
         out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample)
+    if args.serve > 0:
+        out["serving"] = serve_leg(ctx, args.serve, args.serve_rate, args.serve_lattice_share,
+                                   args.serve_slice_us)
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:

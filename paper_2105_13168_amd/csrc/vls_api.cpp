@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
@@ -770,6 +771,57 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     return rs;
 }
 
+// Launch plan of the batched kernel.  Tasks (meshes) run largest first; a
+// mesh of nv vertices wants a gang of nv / kGangVerts workgroups (at most
+// kGangMax, and at least 2 to be a gang); the gangs together take at most
+// three quarters of the pool (sizes scaled down, then the smallest gangs
+// demoted to one workgroup), so that all of them run at once.  The slot
+// list holds every gang member first (rank 0 first), then the tasks of one
+// workgroup.
+namespace {
+constexpr int64_t kGangVerts = 65536;
+constexpr int kGangMax = 64;
+std::atomic<unsigned int> g_epoch{0};
+
+struct BatchPlan {
+    std::vector<int32_t> order, task_g, slots;
+    int nslots = 0, grid = 0;
+};
+
+void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp) {
+    const int n = (int)nv.size();
+    bp.order.resize(n);
+    for (int i = 0; i < n; ++i) bp.order[i] = i;
+    std::stable_sort(bp.order.begin(), bp.order.end(), [&](int32_t a, int32_t b) { return nv[a] > nv[b]; });
+    bp.task_g.assign(n, 1);
+    int64_t sum = 0;
+    for (int w = 0; w < n; ++w) {
+        const int64_t want = std::min<int64_t>(kGangMax, nv[bp.order[w]] / kGangVerts);
+        if (want >= 2) { bp.task_g[w] = (int32_t)want; sum += want; }
+    }
+    const int64_t cap = (int64_t)pool * 3 / 4;
+    if (sum > cap) {
+        const double f = (double)cap / (double)sum;
+        sum = 0;
+        for (int w = 0; w < n; ++w)
+            if (bp.task_g[w] >= 2) {
+                bp.task_g[w] = (int32_t)std::max<int64_t>(2, (int64_t)(bp.task_g[w] * f));
+                sum += bp.task_g[w];
+            }
+        for (int w = n - 1; w >= 0 && sum > cap; --w)
+            if (bp.task_g[w] >= 2) { sum -= bp.task_g[w]; bp.task_g[w] = 1; }
+    }
+    bp.slots.clear();
+    for (int w = 0; w < n; ++w)
+        if (bp.task_g[w] >= 2)
+            for (int r = 0; r < bp.task_g[w]; ++r) { bp.slots.push_back(w); bp.slots.push_back(r); }
+    for (int w = 0; w < n; ++w)
+        if (bp.task_g[w] < 2) { bp.slots.push_back(w); bp.slots.push_back(0); }
+    bp.nslots = (int)(bp.slots.size() / 2);
+    bp.grid = std::max(1, std::min(pool, bp.nslots));
+}
+}  // namespace
+
 extern "C" {
 
 vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vls_result **out) {
@@ -821,35 +873,41 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
         hp[i] = preps[i].dp;
         lds = std::max(lds, step_lds_bytes(256, m->dmax));
     }
-    // largest meshes first, so that the longest runs start early
-    std::vector<int32_t> order(n);
-    for (int32_t i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return meshes[a]->nv > meshes[b]->nv; });
-    void *dm = nullptr, *ds = nullptr, *dpp = nullptr, *dord = nullptr, *dnext = nullptr;
+    const int maxg = max_coresident_batch(lds);
+    if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
+    const int pool = per_mesh[0].grid > 0 ? std::min(per_mesh[0].grid, maxg) : maxg;
+    std::vector<int64_t> nvs(n);
+    for (int32_t i = 0; i < n; ++i) nvs[i] = meshes[i]->nv;
+    BatchPlan bp;
+    plan_batch(nvs, pool, bp);
+    const int grid = bp.grid;
+    void *dm = nullptr, *ds = nullptr, *dpp = nullptr, *dord = nullptr, *dnext = nullptr, *dtg = nullptr,
+         *dsl = nullptr;
     struct Guard {
         std::vector<void **> ptrs;
         ~Guard() { for (void **q : ptrs) if (*q) (void)hipFree(*q); }
-    } guard{{&dm, &ds, &dpp, &dord, &dnext}};
+    } guard{{&dm, &ds, &dpp, &dord, &dnext, &dtg, &dsl}};
     HIPCHK(ctx, hipMalloc(&dm, n * sizeof(DMesh)));
     HIPCHK(ctx, hipMalloc(&ds, n * sizeof(DState)));
     HIPCHK(ctx, hipMalloc(&dpp, n * sizeof(DParams)));
     HIPCHK(ctx, hipMalloc(&dord, n * sizeof(int32_t)));
+    HIPCHK(ctx, hipMalloc(&dtg, n * sizeof(int32_t)));
+    HIPCHK(ctx, hipMalloc(&dsl, bp.slots.size() * sizeof(int32_t)));
     HIPCHK(ctx, hipMalloc(&dnext, sizeof(int)));
     HIPCHK(ctx, hipMemcpyAsync(dm, hm.data(), n * sizeof(DMesh), hipMemcpyHostToDevice, stream));
     HIPCHK(ctx, hipMemcpyAsync(ds, hs.data(), n * sizeof(DState), hipMemcpyHostToDevice, stream));
     HIPCHK(ctx, hipMemcpyAsync(dpp, hp.data(), n * sizeof(DParams), hipMemcpyHostToDevice, stream));
-    HIPCHK(ctx, hipMemcpyAsync(dord, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(dord, bp.order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(dtg, bp.task_g.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(dsl, bp.slots.data(), bp.slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIPCHK(ctx, hipMemsetAsync(dnext, 0, sizeof(int), stream));
-    const int maxg = max_coresident_batch(lds);
-    if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
-    int grid = per_mesh[0].grid > 0 ? per_mesh[0].grid : maxg;
-    if (grid > n) grid = n;
     hipEvent_t b0 = nullptr, b1 = nullptr;
     HIPCHK(ctx, hipEventCreate(&b0));
     HIPCHK(ctx, hipEventCreate(&b1));
     HIPCHK(ctx, hipEventRecord(b0, stream));
-    hipError_t le = launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dpp, (const int32_t *)dord, n,
-                                 (int *)dnext, grid, lds, ~0ull, nullptr, stream);
+    hipError_t le = launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dpp, (const int32_t *)dord,
+                                 (const int32_t *)dtg, (const int32_t *)dsl, bp.nslots, (int *)dnext, grid, lds, ~0ull,
+                                 nullptr, ++g_epoch, stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "batch kernel launch: %s", hipGetErrorString(le));
     HIPCHK(ctx, hipEventRecord(b1, stream));
     HIPCHK(ctx, hipEventSynchronize(b1));
@@ -1091,13 +1149,14 @@ struct vls_server {
     int64_t launches = 0, completed = 0;
     std::thread th;
     // launch descriptors on the device, rebuilt when the running set changes
-    void *dm = nullptr, *ds = nullptr, *dp = nullptr, *dord = nullptr, *dnext = nullptr, *ddone = nullptr;
+    void *dm = nullptr, *ds = nullptr, *dp = nullptr, *dord = nullptr, *dnext = nullptr, *ddone = nullptr,
+         *dtg = nullptr, *dsl = nullptr;
     int cap = 0;
     std::vector<int32_t> hdone;
     std::string thread_err;
 
     ~vls_server() {
-        for (void *q : {dm, ds, dp, dord, dnext, ddone}) if (q) (void)hipFree(q);
+        for (void *q : {dm, ds, dp, dord, dnext, ddone, dtg, dsl}) if (q) (void)hipFree(q);
         if (ctx.own_stream && ctx.stream) (void)hipStreamDestroy(ctx.stream);
     }
     void finish(SrvReq *q, vls_status st, vls_result *r);
@@ -1153,41 +1212,47 @@ bool vls_server::admit_one(SrvReq *q) {
 bool vls_server::launch_slice() {
     const int n = (int)active.size();
     if (n > cap) {
-        for (void *q : {dm, ds, dp, dord, dnext, ddone}) if (q) (void)hipFree(q);
-        dm = ds = dp = dord = dnext = ddone = nullptr;
+        for (void *q : {dm, ds, dp, dord, dnext, ddone, dtg, dsl}) if (q) (void)hipFree(q);
+        dm = ds = dp = dord = dnext = ddone = dtg = dsl = nullptr;
         int c = 64;
         while (c < n) c <<= 1;
         if (hipMalloc(&dm, c * sizeof(DMesh)) || hipMalloc(&ds, c * sizeof(DState)) ||
             hipMalloc(&dp, c * sizeof(DParams)) || hipMalloc(&dord, c * sizeof(int32_t)) ||
-            hipMalloc(&dnext, sizeof(int)) || hipMalloc(&ddone, c * sizeof(int32_t)))
+            hipMalloc(&dnext, sizeof(int)) || hipMalloc(&ddone, c * sizeof(int32_t)) ||
+            hipMalloc(&dtg, c * sizeof(int32_t)) || hipMalloc(&dsl, 2 * (size_t)(c + 4096) * sizeof(int32_t)))
             return false;
         cap = c;
     }
     std::vector<DMesh> hm(n);
     std::vector<DState> hs(n);
     std::vector<DParams> hp(n);
-    std::vector<int32_t> order(n);
+    std::vector<int64_t> nvs(n);
     size_t lds = 0;
     for (int i = 0; i < n; ++i) {
         hm[i] = active[i]->m->d;
         hs[i] = active[i]->prep->s;
         hp[i] = active[i]->prep->dp;
-        order[i] = i;
+        nvs[i] = active[i]->m->nv;
         lds = std::max(lds, step_lds_bytes(256, active[i]->m->dmax));
     }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return active[a]->m->nv > active[b]->m->nv; });
+    const int maxg = max_coresident_batch(lds);
+    if (maxg <= 0) return false;
+    BatchPlan bp;
+    plan_batch(nvs, maxg, bp);
+    if (bp.nslots > cap + 4096) return false;      // slot buffer holds cap + 4096 slots
+    const std::vector<int32_t> &order = bp.order;
     hipStream_t st = ctx.stream;
     if (hipMemcpyAsync(dm, hm.data(), n * sizeof(DMesh), hipMemcpyHostToDevice, st) ||
         hipMemcpyAsync(ds, hs.data(), n * sizeof(DState), hipMemcpyHostToDevice, st) ||
         hipMemcpyAsync(dp, hp.data(), n * sizeof(DParams), hipMemcpyHostToDevice, st) ||
         hipMemcpyAsync(dord, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(dtg, bp.task_g.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(dsl, bp.slots.data(), bp.slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) ||
         hipMemsetAsync(dnext, 0, sizeof(int), st))
         return false;
-    int grid = max_coresident_batch(lds);
-    if (grid <= 0) return false;
-    if (grid > n) grid = n;
-    if (launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dp, (const int32_t *)dord, n, (int *)dnext,
-                     grid, lds, slice_ticks, (int32_t *)ddone, st) != hipSuccess)
+    if (launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dp, (const int32_t *)dord,
+                     (const int32_t *)dtg, (const int32_t *)dsl, bp.nslots, (int *)dnext, bp.grid, lds, slice_ticks,
+                     (int32_t *)ddone, ++g_epoch, st) != hipSuccess)
         return false;
     hdone.assign(n, 0);
     if (hipMemcpyAsync(hdone.data(), ddone, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) ||

@@ -75,8 +75,11 @@ struct Ctl {
     unsigned long long clk_ev, clk_rounds;
     int32_t n_round_steps, n_global_steps;
     // batched mode: next iteration to run (a mesh may be advanced over
-    // several launches, each visit bounded in time)
+    // several launches, each visit bounded in time), the first iteration of
+    // the current gang visit, and the launch epoch that opened it
     int64_t biter;
+    int64_t vbase;
+    unsigned int gang_epoch;
 };
 
 // run state in HBM
@@ -138,9 +141,9 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int grid, int block,
                         hipStream_t st);
 int max_coresident_blocks(int block, size_t lds_bytes);
-hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order, int n,
-                        int *next_mesh, int grid, size_t lds, unsigned long long budget_ticks, int32_t *done_out,
-                        hipStream_t st);
+hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order,
+                        const int32_t *task_g, const int32_t *slots, int nslots, int *next_slot, int grid, size_t lds,
+                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, hipStream_t st);
 int max_coresident_batch(size_t lds_bytes);
 size_t step_lds_bytes(int block, int dmax);
 hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt,

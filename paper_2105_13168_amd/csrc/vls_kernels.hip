@@ -582,14 +582,37 @@ __device__ void block_bitonic(uint64_t *a, int np) {
 
 // regular insertion of v (one lower arc): its new crossed half-edges carry
 // the tag of the arc, read from the half-edge (parent -> v)
+__device__ __forceinline__ bool load_lrow(const DMesh &m, int32_t x, int32_t *nb, int32_t &b, int &d);
+
+// insertion of a regular vertex v (parent and key already set): its new
+// crossed half-edges (towards neighbours ranked after it) take the tag of
+// the half-edge (parent -> v); depth = depth(parent) + 1
 __device__ __forceinline__ void regular_insert(const DMesh &m, const DState &s, int32_t v) {
     const int32_t par = ldg(s.parent + v);
-    const int32_t b = ldg(m.rp + v), e = ldg(m.rp + v + 1);
     const uint64_t kv = ldg(s.key + v);
+    int32_t nb[GB];
+    int32_t b;
+    int d;
+    if (load_lrow(m, v, nb, b, d)) {
+        uint64_t kn[GB];
+#pragma unroll
+        for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(s.key + nb[j]) : KEY_OUT;
+        int ppos = -1;
+#pragma unroll
+        for (int j = 0; j < GB; ++j)
+            if (nb[j] == par && par >= 0) ppos = j;
+        const int32_t tag = ppos >= 0 ? ldg(s.lid + ldg(m.rev + b + ppos)) : -1;
+        s.depth[v] = par >= 0 ? ldg(s.depth + par) + 1 : 0;
+#pragma unroll
+        for (int j = 0; j < GB; ++j)
+            if (j < d && !rank_lt(kn[j], nb[j], kv, v)) s.lid[b + j] = tag;
+        return;
+    }
+    const int32_t e = ldg(m.rp + v + 1);
     int32_t tag = -1;
     for (int32_t j = b; j < e; ++j)
         if (ldg(m.cyc + j) == par) tag = ldg(s.lid + ldg(m.rev + j));
-    s.depth[v] = ldg(s.depth + par) + 1;
+    s.depth[v] = par >= 0 ? ldg(s.depth + par) + 1 : 0;
     for (int32_t j = b; j < e; ++j) {
         const int32_t u = ldg(m.cyc + j);
         if (!rank_lt(ldg(s.key + u), u, kv, v)) s.lid[j] = tag;
@@ -993,13 +1016,26 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
         // 2. closure rounds: round 0 touches the inside set of step t-1,
         //    round j touches round j-1
         for (;;) {
+            const uint64_t want = tk | (uint64_t)(round - 1);
             for (int i = tid; i < nL; i += NT) {
                 int flag = 0;
                 if (s.Lrnd[i] == -1) {
                     const int32_t x = s.L[i];
-                    for (int32_t j = m.rp[x]; j < m.rp[x + 1]; ++j) {
-                        const uint64_t kk = s.key[m.adj[j]];
-                        if (round == 0 ? (kk < tk) : (kk == (tk | (uint64_t)(round - 1)))) { flag = 1; break; }
+                    int32_t nb[GB];
+                    int32_t b;
+                    int d;
+                    if (load_lrow(m, x, nb, b, d)) {
+                        uint64_t kn[GB];
+#pragma unroll
+                        for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(s.key + nb[j]) : KEY_OUT;
+#pragma unroll
+                        for (int j = 0; j < GB; ++j)
+                            flag |= nb[j] >= 0 && (round == 0 ? (kn[j] < tk) : (kn[j] == want));
+                    } else {
+                        for (int32_t j = b; j < ldg(m.rp + x + 1); ++j) {
+                            const uint64_t kk = s.key[m.adj[j]];
+                            if (round == 0 ? (kk < tk) : (kk == want)) { flag = 1; break; }
+                        }
                     }
                 }
                 s.Lcls[i] = flag;
@@ -1025,23 +1061,46 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
             if (s.Lrnd[i] < 0) continue;
             const int32_t v = s.L[i];
             const uint64_t kv = s.key[v];
-            const int32_t b = m.rp[v];
-            const int d = m.rp[v + 1] - b;
-            int32_t ulast = m.cyc[b + d - 1];
-            bool prev = rank_lt(s.key[ulast], ulast, kv, v);
+            int32_t nb[GB];
+            int32_t b;
+            int d;
             int nlow = 0, runs = 0;
             int32_t par = -1;
             uint64_t kp = KEY_OUT;
-            for (int j = 0; j < d; ++j) {
-                const int32_t u = m.cyc[b + j];
-                const uint64_t ku = s.key[u];
-                const bool low = rank_lt(ku, u, kv, v);
-                if (low) {
-                    nlow++;
-                    if (!prev) runs++;
-                    if (par < 0 || rank_lt(ku, u, kp, par)) { par = u; kp = ku; }
+            if (load_lrow(m, v, nb, b, d)) {
+                uint64_t kn[GB];
+#pragma unroll
+                for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(s.key + nb[j]) : KEY_OUT;
+                bool prev = false;
+#pragma unroll
+                for (int j = 0; j < GB; ++j)
+                    if (j == d - 1) prev = rank_lt(kn[j], nb[j], kv, v);
+#pragma unroll
+                for (int j = 0; j < GB; ++j) {
+                    if (j >= d) continue;
+                    const bool low = rank_lt(kn[j], nb[j], kv, v);
+                    if (low) {
+                        nlow++;
+                        if (!prev) runs++;
+                        if (par < 0 || rank_lt(kn[j], nb[j], kp, par)) { par = nb[j]; kp = kn[j]; }
+                    }
+                    prev = low;
                 }
-                prev = low;
+            } else {
+                d = ldg(m.rp + v + 1) - b;
+                int32_t ulast = m.cyc[b + d - 1];
+                bool prev = rank_lt(s.key[ulast], ulast, kv, v);
+                for (int j = 0; j < d; ++j) {
+                    const int32_t u = m.cyc[b + j];
+                    const uint64_t ku = s.key[u];
+                    const bool low = rank_lt(ku, u, kv, v);
+                    if (low) {
+                        nlow++;
+                        if (!prev) runs++;
+                        if (par < 0 || rank_lt(ku, u, kp, par)) { par = u; kp = ku; }
+                    }
+                    prev = low;
+                }
             }
             const int cls = nlow == d ? -1 : runs;
             s.Lcls[i] = cls;
@@ -1129,9 +1188,9 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
 // classes and parents live in LDS; an LDS hash maps a vertex to its entry so
 // that same-step neighbours are recognised without re-reading global keys
 // ---------------------------------------------------------------------------
-#define LCAP 1024
-#define HCAP 2048
-#define HBITS 11
+#define LCAP 2048
+#define HCAP 4096
+#define HBITS 12
 
 struct KL {
     int32_t Lv[LCAP];       // candidate vertex
@@ -1589,22 +1648,30 @@ __device__ __forceinline__ bool spin_ge64(const long long *p, long long target, 
     return true;
 }
 
+// One mesh advanced by a gang of G >= 2 co-resident workgroups: rank 0 runs
+// the topology, ranks 1..G-1 the field.  Entry state: iterations below j0
+// complete (topology j0-1 and field j0 done), fbar = 0, kdone <= j0-1,
+// stop_step = LLONG_MAX.  Field step t waits for topology t-2 (it rewrites
+// that step's field buffer and crosser list) and for field t-1 on every
+// field workgroup; topology t waits for field t.  Rank 0 stops after a
+// topology step once the mesh is done or the visit has used budget ticks
+// of s_memrealtime; the field then completes exactly one more step, so the
+// exit state is again "iterations below t+1 complete".  Rank 0 returns the
+// next iteration.  Every wait is bounded (an overrun records an error).
 template <int CM>
-__global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int go;
-    const unsigned long long W = gridDim.x - 1;          // field workgroups
+__device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s, const DParams &p, int rank, int G,
+                                                int64_t j0, unsigned long long budget, KSh *ksh, KL *kl,
+                                                uint64_t *lsort, int &go) {
+    const unsigned long long W = (unsigned long long)(G - 1);       // field workgroups
     Ctl *ctl = s.ctl;
-    KSh *ksh = (KSh *)lds;
-    uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
-    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
-    if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const unsigned long long v0 = __builtin_amdgcn_s_memrealtime();
     unsigned long long c_work = 0, c_wait = 0;
-    if (blockIdx.x == 0) {
-        for (int64_t t = 1;; ++t) {
+    if (rank == 0) {
+        int64_t next = j0;
+        for (int64_t t = j0 < 1 ? 1 : j0;; ++t) {
             const unsigned long long c0 = __builtin_amdgcn_s_memrealtime();
             if (threadIdx.x == 0) {
-                go = spin_ge(&ctl->fbar, (unsigned long long)t * W, s) ? 1 : 0;
+                go = spin_ge(&ctl->fbar, (unsigned long long)(t - j0) * W, s) ? 1 : 0;
                 __threadfence();
             }
             __syncthreads();
@@ -1613,8 +1680,9 @@ __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) 
             __syncthreads();
             if (threadIdx.x == 0) {
                 const int d = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || !go;
+                const int y = !d && __builtin_amdgcn_s_memrealtime() - v0 >= budget;
                 __threadfence();
-                if (d) {
+                if (d || y) {
                     // the stop step becomes visible before the jump of kdone
                     __hip_atomic_store(&ctl->stop_step, (long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __threadfence();
@@ -1622,19 +1690,19 @@ __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) 
                 } else {
                     __hip_atomic_store(&ctl->kdone, (long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                go = d;
+                go = d || y;
             }
             __syncthreads();
             const unsigned long long c2 = __builtin_amdgcn_s_memrealtime();
             c_wait += c1 - c0;
             c_work += c2 - c1;
-            if (go) break;
+            if (go) { next = t + 1; break; }
         }
-        if (threadIdx.x == 0) { ctl->clk_topo = c_work; ctl->clk_wait0 = c_wait; }
-        return;
+        if (threadIdx.x == 0) { ctl->clk_topo += c_work; ctl->clk_wait0 += c_wait; }
+        return next;
     }
-    const int worker = (int)blockIdx.x - 1;
-    for (int64_t t = 1;; ++t) {
+    const int worker = rank - 1;
+    for (int64_t t = j0 + 1;; ++t) {
         const unsigned long long c0 = __builtin_amdgcn_s_memrealtime();
         if (threadIdx.x == 0) {
             // topology t-2 done (its field buffer and crosser list are free)
@@ -1645,7 +1713,7 @@ __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) 
                 go = 0;
             } else {
                 // field step t-1 complete on every field workgroup
-                ok = spin_ge(&ctl->fbar, (unsigned long long)(t - 1) * W, s);
+                ok = spin_ge(&ctl->fbar, (unsigned long long)(t - 1 - j0) * W, s);
                 __threadfence();
                 go = ok;
             }
@@ -1674,45 +1742,114 @@ __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) 
         c_wait += c1 - c0;
         c_work += c2 - c1;
     }
-    if (threadIdx.x == 0 && worker == 0) { ctl->clk_field = c_work; ctl->clk_wait1 = c_wait; }
+    if (threadIdx.x == 0 && worker == 0) { ctl->clk_field += c_work; ctl->clk_wait1 += c_wait; }
+    return 0;
+}
+
+// the decoupled step kernel of one mesh: the whole grid is one gang
+template <int CM>
+__global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int go;
+    KSh *ksh = (KSh *)lds;
+    uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
+    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
+    if (__hip_atomic_load(&s.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    (void)gang_advance<CM>(m, s, p, (int)blockIdx.x, (int)gridDim.x, 0, ~0ull, ksh, kl, lsort, go);
 }
 
 // ---------------------------------------------------------------------------
-// batched mode: many meshes in one launch.  A persistent pool of workgroups
-// pulls meshes (largest first) from a counter; one workgroup advances one
-// mesh through all its steps, topology of step t then field of step t+1,
-// separated by workgroup barriers only (no grid barrier, no cross-workgroup
-// sharing inside a mesh).
+// batched mode: many meshes in one launch
 // ---------------------------------------------------------------------------
-// Batched mode: a pool of workgroups, one mesh per workgroup at a time,
-// meshes taken largest first from a shared counter.  Each workgroup runs
-// the topology of step j and the field of step j+1 back to back.  A visit
-// ends when the mesh is done or, at an iteration boundary, once the visit
-// has used budget_ticks of s_memrealtime (100 MHz); the next iteration is
-// kept in the mesh's control block, so a later launch continues it with
-// the same arithmetic.  done_out[w] reports each visited mesh's state.
+// Batched mode: a cooperative pool of workgroups takes slots from a shared
+// counter; slot k names a task (a mesh) and a rank in that task's gang.
+// A task of one workgroup runs the topology of step j and the field of
+// step j+1 back to back; a gang of g >= 2 runs the decoupled protocol
+// (gang_advance).  Gang slots come first in the slot list and fit in the
+// pool, so every gang's members are running together.  A visit ends when
+// the mesh is done or, at a step boundary, once it has used budget_ticks of
+// s_memrealtime (100 MHz); the next iteration is kept in the mesh's control
+// block (biter), so a later launch, with any gang size, continues it with
+// the same arithmetic.  done_out[task] reports each visited mesh's state.
+__device__ __forceinline__ void zero_dead_counters(Ctl *ctl, int64_t j0) {
+    // counters the field steps j0+1 and j0+2 append to; their previous
+    // contents were consumed by steps below j0
+    ctl->cnt_act[(j0 + 2) & 3] = 0;
+    ctl->cnt_act[(j0 + 3) & 3] = 0;
+    ctl->cnt_cand[(j0 + 1) & 3] = 0;
+    ctl->cnt_cand[(j0 + 2) & 3] = 0;
+}
+
 __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss, const DParams *ps,
-                                              const int32_t *order, int n, int *next_mesh,
-                                              unsigned long long budget_ticks, int32_t *done_out) {
+                                              const int32_t *order, const int32_t *task_g, const int32_t *slots,
+                                              int nslots, int *next_slot, unsigned long long budget_ticks,
+                                              int32_t *done_out, unsigned int epoch) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int cur, yield;
+    __shared__ int cur, yield, go;
+    __shared__ long long jstart;
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
     KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
     for (;;) {
-        if (threadIdx.x == 0) cur = atomicAdd(next_mesh, 1);
+        if (threadIdx.x == 0) cur = atomicAdd(next_slot, 1);
         __syncthreads();
-        const int w = cur;
+        const int k = cur;
         __syncthreads();
-        if (w >= n) break;
+        if (k >= nslots) break;
+        const int w = slots[2 * k], rank = slots[2 * k + 1];
         const int mi = order[w];
-        const DMesh m = ms[mi];
-        const DState s = ss[mi];
-        const DParams p = ps[mi];
+        const int g = task_g[w];
+        // descriptors read in place (uniform loads); a local copy would be
+        // spilled to scratch because of its per-parity pointer arrays
+        const DMesh &m = ms[mi];
+        const DState &s = ss[mi];
+        const DParams &p = ps[mi];
         Ctl *ctl = s.ctl;
         const unsigned long long c_start = __builtin_amdgcn_s_memrealtime();
+        if (g >= 2) {
+            // gang hand-off: rank 0 sets this visit's counters, then opens it
+            if (threadIdx.x == 0) {
+                if (rank == 0) {
+                    const int64_t j0 = ctl->biter;
+                    const int skip = ctl->done;
+                    ctl->fbar = 0;
+                    ctl->kdone = j0 - 1;
+                    ctl->stop_step = skip ? -1 : LLONG_MAX;
+                    ctl->vbase = j0;
+                    if (!skip) zero_dead_counters(ctl, j0);
+                    jstart = skip ? -1 : j0;
+                    __threadfence();
+                    __hip_atomic_store(&ctl->gang_epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+                    while (__hip_atomic_load(&ctl->gang_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (__builtin_amdgcn_s_memrealtime() - t0 > SPIN_LIMIT) { fail(s, ST_INVARIANT, 22); break; }
+                    }
+                    __threadfence();
+                    jstart = __hip_atomic_load(&ctl->gang_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch
+                                 ? (long long)ctl->vbase : -1;
+                }
+            }
+            __syncthreads();
+            const long long j0 = jstart;
+            if (rank == 0 && j0 < 0) {
+                if (threadIdx.x == 0 && done_out) done_out[w] = 1;
+            } else if (rank != 0 && j0 < 0) {
+                // the visit never opened (error already recorded) or the mesh is done
+            } else {
+                const int64_t nx = gang_advance<0>(m, s, p, rank, g, j0, budget_ticks, ksh, kl, lsort, go);
+                if (rank == 0 && threadIdx.x == 0) {
+                    ctl->biter = nx;
+                    if (done_out) done_out[w] = ctl->done;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
         if (!ctl->done) {
             const int64_t j0 = ctl->biter;
+            if (threadIdx.x == 0) zero_dead_counters(ctl, j0);
             for (int64_t j = j0;; ++j) {
                 if (threadIdx.x == 0)
                     yield = j > j0 && __builtin_amdgcn_s_memrealtime() - c_start >= budget_ticks;
@@ -1749,12 +1886,11 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
     }
 }
 
-hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order, int n,
-                        int *next_mesh, int grid, size_t lds, unsigned long long budget_ticks, int32_t *done_out,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(NT), lds, st, ms, ss, ps, order, n, next_mesh, budget_ticks,
-                       done_out);
-    return hipGetLastError();
+hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order,
+                        const int32_t *task_g, const int32_t *slots, int nslots, int *next_slot, int grid, size_t lds,
+                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, hipStream_t st) {
+    void *args[] = {&ms, &ss, &ps, &order, &task_g, &slots, &nslots, &next_slot, &budget_ticks, &done_out, &epoch};
+    return hipLaunchCooperativeKernel((const void *)k_batch, dim3(grid), dim3(NT), args, (unsigned)lds, st);
 }
 
 int max_coresident_batch(size_t lds_bytes) {

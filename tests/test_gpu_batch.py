@@ -57,3 +57,23 @@ def test_batch_repeat_is_deterministic():
     for x in M:
         x.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("pool", [0, 6])
+def test_batch_gangs_match_oracle(oracle_mod, pool):
+    """Meshes of >= 2^17 vertices get gangs of workgroups (one topology
+    workgroup, the rest field) inside the batched launch; with a pool of 6
+    the gangs are scaled down to fit.  Results equal the oracle's."""
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    ms = [mg.pretzel(96, rng_seed=2), mg.lattice(3, 96, rng_seed=3), mg.pretzel(72, rng_seed=1),
+          mg.torus_grid(rng_seed=4), mg.multi_torus(2, 28, rng_seed=5)]
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    res = vls.batch_run(ctx, M, [m.seed for m in ms], grid=pool)
+    for m, g in zip(ms, res):
+        o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
+        bad = compare(g, o, m.nv)
+        assert not bad, (m.name, bad)
+    for x in M:
+        x.close()
+    ctx.close()

@@ -136,3 +136,37 @@ def test_server_destroy_with_work_in_flight():
     assert r.summary["run_status"] == 0
     M.close()
     ctx.close()
+
+
+def test_server_gangs_resize_and_switch(oracle_mod):
+    """Many large requests at once: the planner gives meshes of >= 2^17
+    vertices gangs of workgroups within three quarters of the pool, scaled
+    down and the smallest demoted to one workgroup when they do not fit;
+    as requests finish the remaining ones are re-planned, so a request's
+    visits switch between one workgroup and a gang and between gang sizes.
+    Every result equals the oracle's."""
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    big = [mg.pretzel(72, rng_seed=s) for s in (0, 1)] + [mg.pretzel(96, rng_seed=2), mg.lattice(3, 96, rng_seed=3)]
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in big]
+    srv = vls.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=512, slice_us=300)
+    try:
+        reqs = [(k % 2, srv.submit(M[k % 2], seed_vertex=big[k % 2].seed)) for k in range(110)]
+        reqs += [(2, srv.submit(M[2], seed_vertex=big[2].seed)), (3, srv.submit(M[3], seed_vertex=big[3].seed))]
+        res = _wait(srv, [t for _, t in reqs], timeout=110.0)
+        assert srv.stats()["launches"] > 3
+        oracle_res = {}
+        for (k, _), r in zip(reqs, res):
+            if k not in oracle_res:
+                m = big[k]
+                o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
+                bad = compare(r, o, m.nv)
+                assert not bad, (m.name, bad)
+                oracle_res[k] = r
+            else:
+                _same(r, oracle_res[k])
+    finally:
+        srv.close()
+        for x in M:
+            x.close()
+        ctx.close()
