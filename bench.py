@@ -42,7 +42,7 @@ def make_workload(name):
         desc = "64x32 torus grid, R=1, r=0.4"
     elif name.startswith("lattice10_"):
         grid = int(name.split("_")[1])
-        m = mg.lattice(10, grid, rng_seed=0)
+        m = mg.lattice(10, grid, rng_seed=0, progress=log)
         desc = (f"strut lattice, 10^3 cells (3630 struts of radius 0.15, genus 2300), level-0 surface on a "
                 f"{grid}^3 grid over [-0.5, 10.5]^3 (marching tetrahedra), random seed vertex")
     else:

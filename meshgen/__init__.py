@@ -381,7 +381,8 @@ def batch_workload(n: int = 1024, base_seed: int = 0, pretzel_grids=(32, 48, 64,
 # ---------------------------------------------------------------------------
 # large surfaces: marching tetrahedra streamed by slabs of grid planes
 # ---------------------------------------------------------------------------
-def marching_tets_slabs(plane_f, lo, hi, shape, slab: int = 16, chunk_cells: int = 1 << 21) -> Mesh:
+def marching_tets_slabs(plane_f, lo, hi, shape, slab: int = 16, chunk_cells: int = 1 << 21,
+                        progress=None) -> Mesh:
     """Level-0 surface of a field given plane by plane: ``plane_f(x, Y, Z)``
     returns f on the grid plane at abscissa x (Y, Z: 2-D coordinate arrays).
     Same extraction as ``marching_tets`` (six tetrahedra per cell, inside
@@ -402,6 +403,8 @@ def marching_tets_slabs(plane_f, lo, hi, shape, slab: int = 16, chunk_cells: int
     keys_u, xyz_u, tri_keys = [], [], []
     prev = None                                    # last plane of the previous slab
     for i0 in range(0, nx - 1, slab):
+        if progress is not None and i0 % (slab * 16) == 0:
+            progress(f"extraction: plane {i0} of {nx}")
         i1 = min(nx - 1, i0 + slab)                # cells i0..i1-1, planes i0..i1
         planes = [prev if (prev is not None and i == i0) else plane_f(xs[i], Y, Z) for i in range(i0, i1 + 1)]
         F = np.stack(planes)
@@ -507,13 +510,14 @@ def lattice_genus(n_cells: int) -> int:
 
 
 def lattice(n_cells: int = 10, grid: int = 1024, radius: float = 0.15, sigma: float = 0.0,
-            rng_seed: int = 0, slab: int = 16) -> Mesh:
+            rng_seed: int = 0, slab: int = 16, progress=None) -> Mesh:
     """Strut lattice surface: level 0 of ``lattice_plane_sdf`` on grid^3
     samples over [-0.5, n + 0.5]^3, optional N(0, sigma^2) jitter, then a
     random seed vertex from rng_seed.  Genus ``lattice_genus(n_cells)``."""
     lo = (-0.5, -0.5, -0.5)
     hi = (n_cells + 0.5,) * 3
-    m = marching_tets_slabs(lattice_plane_sdf(n_cells, radius), lo, hi, (grid, grid, grid), slab)
+    m = marching_tets_slabs(lattice_plane_sdf(n_cells, radius), lo, hi, (grid, grid, grid), slab,
+                            progress=progress)
     m = jittered(m, sigma, rng_seed, f"lattice{n_cells}_{grid}") if sigma > 0 else \
         Mesh(m.xyz, m.tri, 0, f"lattice{n_cells}_{grid}")
     return m if sigma > 0 else pick_seed(m, rng_seed)
