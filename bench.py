@@ -106,11 +106,11 @@ def batch_leg(ctx, n, seq_sample):
     M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
     genus = [x.euler_genus for x in M]
 
-    def run_batch(idx):
+    def run_batch(idx, extra=0):
         hm = (C.c_void_p * len(idx))(*[M[i].h.value for i in idx])
         ps = (vls.vls_params * len(idx))()
         for k, i in enumerate(idx):
-            ps[k] = vls.default_params(seed_vertex=ms[i].seed, flags=vls.VLS_DEFER_RESULTS)
+            ps[k] = vls.default_params(seed_vertex=ms[i].seed, flags=vls.VLS_DEFER_RESULTS | extra)
         outs = (C.c_void_p * len(idx))()
         st = vls.vls_batch_run(ctx.h, len(idx), hm, ps, outs)
         sums = []
@@ -125,11 +125,17 @@ def batch_leg(ctx, n, seq_sample):
 
     run_batch(list(range(n)))                     # warm-up: allocates every mesh's run buffers
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sums = run_batch(list(range(n)))
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t1
-    ok = all(s["run_status"] == 0 and s["n_handles"] == g for s, g in zip(sums, genus))
+    # both pool shapes: one workgroup per CU, and two (smaller LDS tables)
+    shapes = {}
+    for name, extra in (("one_per_cu", 0), ("two_per_cu", vls.VLS_BATCH_TWO_PER_CU)):
+        t1 = time.perf_counter()
+        sm = run_batch(list(range(n)), extra)
+        torch.cuda.synchronize()
+        shapes[name] = (time.perf_counter() - t1, sm)
+    best = min(shapes, key=lambda k: shapes[k][0])
+    tb, sums = shapes[best]
+    ok = all(s["run_status"] == 0 and s["n_handles"] == g
+             for _, sm in shapes.values() for s, g in zip(sm, genus))
     vsteps = sum(m.nv * s["steps"] for m, s in zip(ms, sums))
     ab = sum(alg_bytes(s["active_vertex_updates"], s["active_degree_sum"]) for s in sums)
     kernel_ms = sums[0]["kernel_ms"]
@@ -149,7 +155,13 @@ def batch_leg(ctx, n, seq_sample):
     seq_rate = len(sample) / ts
     # the sample's share of the batch's vertex-steps, to compare like with like
     sample_vsteps = sum(ms[i].nv * sums[i]["steps"] for i in sample)
+    slow = sorted(range(n), key=lambda i: -(sums[i]["topo_ms"] + sums[i]["wait0_ms"]))[:5]
     return {
+        "slowest": [{"nv": int(ms[i].nv), "steps": int(sums[i]["steps"]), "events": int(sums[i]["n_events"]),
+                     "ms": round(sums[i]["topo_ms"] + sums[i]["wait0_ms"], 1)} for i in slow],
+        "pool_shape": best,
+        "seconds_by_shape": {k: round(v[0], 3) for k, v in shapes.items()},
+        "kernel_ms_by_shape": {k: round(v[1][0]["kernel_ms"], 1) for k, v in shapes.items()},
         "meshes": n, "total_vertices": int(sum(m.nv for m in ms)), "all_handles_equal_genus": ok,
         "seconds": tb, "meshes_per_s": n / tb, "batch_kernel_ms": kernel_ms,
         "vertex_steps_per_s": vsteps / tb,

@@ -67,13 +67,18 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
 #define VLS_DEFER_RESULTS 2u  /* vls_run returns once the device work is done; bulk results
                                  are copied to the host by vls_result_fetch or on first access */
 #define VLS_TOPO_GLOBAL_PATH 4u  /* always run the topology phase from global memory (the path
-                                    otherwise taken only by steps with more than 1024 crossers);
+                                    otherwise taken only by steps with more candidates than the
+                                    LDS tables hold: 2048 solo, 1024 in two-per-CU launches);
                                     results are identical, the flag exists for testing */
-#define VLS_LOCKSTEP 16u         /* one grid barrier per step (topology of t beside field of t+1)
-                                    instead of the decoupled kernel; identical results, for testing */
 #define VLS_COHERENT_SHARING 8u  /* share data between workgroups through coherent atomic accesses
                                     and a release-only step barrier instead of plain accesses and
                                     full agent-scope fences; identical results, for testing */
+#define VLS_LOCKSTEP 16u         /* one grid barrier per step (topology of t beside field of t+1)
+                                    instead of the decoupled kernel; identical results, for testing */
+#define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]): two workgroups per CU, each
+                                    with a 1024-candidate LDS topology path and one list entry per
+                                    field thread (the server always runs this way); default: one per
+                                    CU with the solo kernel's 2048 candidates and two entries */
 
 /*
  * Parameters.  Defaults (vls_params_default) are the paper's coefficients
@@ -172,6 +177,9 @@ typedef struct {
     /* server requests only (0 otherwise), host wall clock: submission to
        admission (queueing) and submission to result ready (latency) */
     double server_queue_ms, server_latency_ms;
+    /* decoupled kernel: field workgroup 1's wait for the other field
+       workgroups (wait1_ms is then its wait for the topology) */
+    double field_barrier_ms;
 } vls_summary;
 vls_status vls_result_summary(const struct vls_result *r, vls_summary *s);
 

@@ -28,6 +28,7 @@ VLS_DEFER_RESULTS = 2
 VLS_TOPO_GLOBAL_PATH = 4
 VLS_COHERENT_SHARING = 8
 VLS_LOCKSTEP = 16
+VLS_BATCH_TWO_PER_CU = 32
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 
@@ -53,7 +54,7 @@ class vls_summary(C.Structure):
                 ("topo_split_ms", C.c_double * 4), ("topo_event_ms", C.c_double),
                 ("topo_rounds_ms", C.c_double), ("topo_round_steps", C.c_int32),
                 ("topo_global_steps", C.c_int32), ("server_queue_ms", C.c_double),
-                ("server_latency_ms", C.c_double)]
+                ("server_latency_ms", C.c_double), ("field_barrier_ms", C.c_double)]
 
 
 class vls_reeb_node(C.Structure):

@@ -755,6 +755,7 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     S.topo_rounds_ms = (double)c.clk_rounds * 1e-5;
     S.topo_round_steps = c.n_round_steps;
     S.topo_global_steps = c.n_global_steps;
+    S.field_barrier_ms = (double)c.clk_fbar * 1e-5;
     vls_status rs = c.status;
     if (rs == VLS_E_INVARIANT || rs == VLS_E_CAPACITY)
         set_err(ctx, rs, "device reported %s (detail %d) at step %lld", vls_status_string(rs), c.err_code, (long long)c.steps);
@@ -773,11 +774,13 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
 
 // Launch plan of the batched kernel.  Tasks (meshes) run largest first; a
 // mesh of nv vertices wants a gang of nv / kGangVerts workgroups (at most
-// kGangMax, and at least 2 to be a gang); the gangs together take at most
-// three quarters of the pool (sizes scaled down, then the smallest gangs
-// demoted to one workgroup), so that all of them run at once.  The slot
-// list holds every gang member first (rank 0 first), then the tasks of one
-// workgroup.
+// kGangMax, and at least 2 to be a gang).  Gangs are granted in task order
+// (largest first, the longest runs) while they fit in three quarters of the
+// pool; a task whose full gang no longer fits gets what is left if that is
+// at least 2, else one workgroup.  So all gangs run at once, and the tail of
+// the launch is not set by a large mesh on one workgroup.  The slot list
+// holds every gang member first (rank 0 first), then the one-workgroup
+// tasks.
 namespace {
 constexpr int64_t kGangVerts = 65536;
 constexpr int kGangMax = 64;
@@ -794,22 +797,11 @@ void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp) {
     for (int i = 0; i < n; ++i) bp.order[i] = i;
     std::stable_sort(bp.order.begin(), bp.order.end(), [&](int32_t a, int32_t b) { return nv[a] > nv[b]; });
     bp.task_g.assign(n, 1);
-    int64_t sum = 0;
+    int64_t left = (int64_t)pool * 3 / 4;
     for (int w = 0; w < n; ++w) {
         const int64_t want = std::min<int64_t>(kGangMax, nv[bp.order[w]] / kGangVerts);
-        if (want >= 2) { bp.task_g[w] = (int32_t)want; sum += want; }
-    }
-    const int64_t cap = (int64_t)pool * 3 / 4;
-    if (sum > cap) {
-        const double f = (double)cap / (double)sum;
-        sum = 0;
-        for (int w = 0; w < n; ++w)
-            if (bp.task_g[w] >= 2) {
-                bp.task_g[w] = (int32_t)std::max<int64_t>(2, (int64_t)(bp.task_g[w] * f));
-                sum += bp.task_g[w];
-            }
-        for (int w = n - 1; w >= 0 && sum > cap; --w)
-            if (bp.task_g[w] >= 2) { sum -= bp.task_g[w]; bp.task_g[w] = 1; }
+        const int64_t g = std::min(want, left);
+        if (g >= 2) { bp.task_g[w] = (int32_t)g; left -= g; }
     }
     bp.slots.clear();
     for (int w = 0; w < n; ++w)
@@ -871,9 +863,10 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
         hm[i] = m->d;
         hs[i] = preps[i].s;
         hp[i] = preps[i].dp;
-        lds = std::max(lds, step_lds_bytes(256, m->dmax));
     }
-    const int maxg = max_coresident_batch(lds);
+    const int occ = (per_mesh[0].flags & VLS_BATCH_TWO_PER_CU) ? 2 : 1;
+    lds = batch_lds_bytes(occ);
+    const int maxg = max_coresident_batch(lds, occ);
     if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
     const int pool = per_mesh[0].grid > 0 ? std::min(per_mesh[0].grid, maxg) : maxg;
     std::vector<int64_t> nvs(n);
@@ -907,7 +900,7 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
     HIPCHK(ctx, hipEventRecord(b0, stream));
     hipError_t le = launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dpp, (const int32_t *)dord,
                                  (const int32_t *)dtg, (const int32_t *)dsl, bp.nslots, (int *)dnext, grid, lds, ~0ull,
-                                 nullptr, ++g_epoch, stream);
+                                 nullptr, ++g_epoch, occ, stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "batch kernel launch: %s", hipGetErrorString(le));
     HIPCHK(ctx, hipEventRecord(b1, stream));
     HIPCHK(ctx, hipEventSynchronize(b1));
@@ -1137,6 +1130,7 @@ struct vls_server {
     vls_context ctx;                 // private stream on the caller's device
     size_t budget = 0;
     int max_slots = 0;
+    int occ = 2;                     // workgroups per CU of the step launches
     unsigned long long slice_ticks = 0;
     std::mutex mu;
     std::condition_variable cv;
@@ -1233,9 +1227,9 @@ bool vls_server::launch_slice() {
         hs[i] = active[i]->prep->s;
         hp[i] = active[i]->prep->dp;
         nvs[i] = active[i]->m->nv;
-        lds = std::max(lds, step_lds_bytes(256, active[i]->m->dmax));
     }
-    const int maxg = max_coresident_batch(lds);
+    lds = batch_lds_bytes(occ);
+    const int maxg = max_coresident_batch(lds, occ);
     if (maxg <= 0) return false;
     BatchPlan bp;
     plan_batch(nvs, maxg, bp);
@@ -1252,7 +1246,7 @@ bool vls_server::launch_slice() {
         return false;
     if (launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dp, (const int32_t *)dord,
                      (const int32_t *)dtg, (const int32_t *)dsl, bp.nslots, (int *)dnext, bp.grid, lds, slice_ticks,
-                     (int32_t *)ddone, ++g_epoch, st) != hipSuccess)
+                     (int32_t *)ddone, ++g_epoch, occ, st) != hipSuccess)
         return false;
     hdone.assign(n, 0);
     if (hipMemcpyAsync(hdone.data(), ddone, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) ||

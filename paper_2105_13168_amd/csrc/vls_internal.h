@@ -73,6 +73,7 @@ struct Ctl {
     // insertion (of which: steps with events, closure rounds after round 0)
     unsigned long long clk_t[4];
     unsigned long long clk_ev, clk_rounds;
+    unsigned long long clk_fbar;   // field workgroup 1: wait for the other field workgroups
     int32_t n_round_steps, n_global_steps;
     // batched mode: next iteration to run (a mesh may be advanced over
     // several launches, each visit bounded in time), the first iteration of
@@ -143,8 +144,10 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
 int max_coresident_blocks(int block, size_t lds_bytes);
 hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order,
                         const int32_t *task_g, const int32_t *slots, int nslots, int *next_slot, int grid, size_t lds,
-                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, hipStream_t st);
-int max_coresident_batch(size_t lds_bytes);
+                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, int occ,
+                        hipStream_t st);
+int max_coresident_batch(size_t lds_bytes, int occ);
+size_t batch_lds_bytes(int occ);
 size_t step_lds_bytes(int block, int dmax);
 hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt,
                              hipStream_t st);

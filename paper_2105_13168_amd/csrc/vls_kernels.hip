@@ -31,7 +31,6 @@ namespace vls {
 
 #define NT 256               // threads per workgroup (4 wave64)
 #define WAVE 64
-#define SORTCAP 2048         // N_t entries sorted in LDS
 #define MAXDEG 64            // vertex degree bound of the event path (one lane per link position)
 #define GLOBAL_AS __attribute__((address_space(1)))   // global memory (avoids flat accesses)
 
@@ -312,7 +311,6 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 // field phase of step t: rho_t from rho_{t-1} over the update list C_t
 // ---------------------------------------------------------------------------
 #define GB ELL_W   // neighbours gathered per vertex in registers (one padded row)
-#define FK 2       // list entries per thread per pass (independent latency chains)
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 // Field phase of step t: rho_t from rho_{t-1} over the update set C_t.
@@ -333,7 +331,7 @@ typedef int32_t v4i __attribute__((ext_vector_type(4)));
 // values, marks, stamps) -> (stores, claim exchanges) -> (one list and one
 // candidate reservation per wave) -> list stores.  Each thread runs FK
 // entries through every stage together so that their round trips overlap.
-template <int CM>
+template <int CM, int FK = 2>
 __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                             int worker, int nworkers) {
     Ctl *ctl = s.ctl;
@@ -985,7 +983,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
     __threadfence_block();
 }
 
-template <int CM>
+template <int CM, int CAP>
 __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                                   KSh *sh, uint64_t *lsort) {
     Ctl *ctl = s.ctl;
@@ -1124,7 +1122,7 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
             const int nN = sh->nN;
             int npow = 1;
             while (npow < nN) npow <<= 1;
-            uint64_t *arr = npow <= SORTCAP ? lsort : s.ord;
+            uint64_t *arr = npow <= CAP ? lsort : s.ord;
             for (int i = tid; i < npow; i += NT) arr[i] = ~0ull;
             __syncthreads();
             if (tid == 0) sh->nnew = 0;
@@ -1188,29 +1186,37 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
 // classes and parents live in LDS; an LDS hash maps a vertex to its entry so
 // that same-step neighbours are recognised without re-reading global keys
 // ---------------------------------------------------------------------------
-#define LCAP 2048
-#define HCAP 4096
-#define HBITS 12
+#define LCAP 2048            // candidates of the solo kernel's LDS topology path
+#define LCAP_BATCH 1024      // the batched kernel's (two workgroups per CU)
 
+template <int CAP>
 struct KL {
-    int32_t Lv[LCAP];       // candidate vertex
-    int32_t Lr[LCAP];       // closure round (-1: not connected)
-    int32_t Lc[LCAP];       // lower arcs (-1: full link)
-    int32_t Lp[LCAP];       // parent vertex
-    int32_t Lq[LCAP];       // link position of the parent
-    int32_t Lt[LCAP];       // round 0: tag of the half-edge (parent -> v)
-    int32_t Ld[LCAP];       // round 0: depth of v
-    uint64_t Lm[LCAP];      // lower-neighbour mask (link positions < 64)
-    int32_t Lb[LCAP];       // first half-edge of v
-    int32_t Lg[LCAP];       // degree of v
+    static constexpr int HCAP = 2 * CAP;      // hash slots (load factor <= 1/2)
+    int32_t Lv[CAP];        // candidate vertex
+    int32_t Lr[CAP];        // closure round (-1: not connected)
+    int32_t Lc[CAP];        // lower arcs (-1: full link)
+    int32_t Lp[CAP];        // parent vertex
+    int32_t Lq[CAP];        // link position of the parent
+    int32_t Lt[CAP];        // round 0: tag of the half-edge (parent -> v)
+    int32_t Ld[CAP];        // round 0: depth of v
+    uint64_t Lm[CAP];       // lower-neighbour mask (link positions < 64)
+    int32_t Lb[CAP];        // first half-edge of v
+    int32_t Lg[CAP];        // degree of v
     int32_t hk[HCAP];       // hash: vertex id (-1 empty)
     int32_t hv[HCAP];       // hash: entry index
 };
 
-__device__ __forceinline__ uint32_t hslot(int32_t x) { return ((uint32_t)x * 2654435761u) >> (32 - HBITS); }
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
-__device__ __forceinline__ int hfind(const KL *kl, int32_t x) {
-    uint32_t h = hslot(x);
+template <int CAP>
+__device__ __forceinline__ uint32_t hslot(int32_t x) {
+    return ((uint32_t)x * 2654435761u) >> (32 - ilog2(KL<CAP>::HCAP));
+}
+
+template <int CAP>
+__device__ __forceinline__ int hfind(const KL<CAP> *kl, int32_t x) {
+    constexpr int HCAP = KL<CAP>::HCAP;
+    uint32_t h = hslot<CAP>(x);
     for (int g = 0; g < HCAP; ++g) {
         const int32_t k = kl->hk[h];
         if (k == x) return kl->hv[h];
@@ -1254,9 +1260,10 @@ __device__ __forceinline__ bool load_lrow(const DMesh &m, int32_t x, int32_t *nb
     return true;
 }
 
-template <int CM>
+template <int CM, int CAP>
 __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p, int64_t t,
-                               KSh *sh, KL *kl, uint64_t *lsort, int nc, int np) {
+                               KSh *sh, KL<CAP> *kl, uint64_t *lsort, int nc, int np) {
+    constexpr int HCAP = KL<CAP>::HCAP;
     Ctl *ctl = s.ctl;
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
     const int tid = threadIdx.x;
@@ -1274,7 +1281,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         // crossers of step t were checked against rho_t by the field phase;
         // pending ones are re-checked here
         if (ldg(s.key + x) != KEY_OUT || (i >= nc && !(ldx<CM>(rho + x) > p.tau))) continue;
-        uint32_t h = hslot(x);
+        uint32_t h = hslot<CAP>(x);
         for (int g = 0; g < HCAP; ++g) {
             const int32_t old = atomicCAS(&kl->hk[h], -1, x);
             if (old == -1) {
@@ -1480,7 +1487,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         const int nN = sh->nN;
         int npow = 1;
         while (npow < nN) npow <<= 1;
-        uint64_t *arr = npow <= SORTCAP ? lsort : s.ord;
+        uint64_t *arr = npow <= CAP ? lsort : s.ord;
         for (int i = tid; i < npow; i += NT) arr[i] = ~0ull;
         __syncthreads();
         if (tid == 0) sh->nnew = 0;
@@ -1532,18 +1539,18 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     }
 }
 
-template <int CM>
+template <int CM, int CAP>
 __device__ __forceinline__ void phase_topo(const DMesh &m, const DState &s, const DParams &p, int64_t t,
-                           KSh *sh, KL *kl, uint64_t *lsort) {
+                           KSh *sh, KL<CAP> *kl, uint64_t *lsort) {
     Ctl *ctl = s.ctl;
     const int nc = ld_relaxed(&ctl->cnt_cand[t & 3]);
     const int np = ctl->cnt_pend[(t - 1) & 1];
-    if (p.topo_global || nc + np > LCAP) {
-        phase_topo_global<CM>(m, s, p, t, sh, lsort);
+    if (p.topo_global || nc + np > CAP) {
+        phase_topo_global<CM, CAP>(m, s, p, t, sh, lsort);
         if (threadIdx.x == 0) ctl->n_global_steps += 1;
         return;
     }
-    phase_topo_lds<CM>(m, s, p, t, sh, kl, lsort, nc, np);
+    phase_topo_lds<CM, CAP>(m, s, p, t, sh, kl, lsort, nc, np);
     if (threadIdx.x == 0) {
         ctl->cnt_pend[t & 1] = sh->npend;
         const int nN = sh->nN;
@@ -1572,7 +1579,7 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
     Ctl *ctl = s.ctl;
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
-    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
+    KL<LCAP> *kl = (KL<LCAP> *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + LCAP * sizeof(uint64_t));
     if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     unsigned long long c_work = 0, c_wait = 0;
     for (int64_t j = 0;; ++j) {
@@ -1582,7 +1589,7 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->cnt_act[(j + 3) & 3] = 0;
                 ctl->cnt_cand[(j + 2) & 3] = 0;
             }
-            if (j >= 1) phase_topo<CM>(m, s, p, j, ksh, kl, lsort);
+            if (j >= 1) phase_topo<CM, LCAP>(m, s, p, j, ksh, kl, lsort);
             __syncthreads();
             // publish this iteration's decision in its own slot: the slot is
             // rewritten two iterations later, after every workgroup read it
@@ -1658,9 +1665,9 @@ __device__ __forceinline__ bool spin_ge64(const long long *p, long long target, 
 // of s_memrealtime; the field then completes exactly one more step, so the
 // exit state is again "iterations below t+1 complete".  Rank 0 returns the
 // next iteration.  Every wait is bounded (an overrun records an error).
-template <int CM>
+template <int CM, int CAP, int FK>
 __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s, const DParams &p, int rank, int G,
-                                                int64_t j0, unsigned long long budget, KSh *ksh, KL *kl,
+                                                int64_t j0, unsigned long long budget, KSh *ksh, KL<CAP> *kl,
                                                 uint64_t *lsort, int &go) {
     const unsigned long long W = (unsigned long long)(G - 1);       // field workgroups
     Ctl *ctl = s.ctl;
@@ -1676,7 +1683,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
             }
             __syncthreads();
             const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
-            if (go) phase_topo<CM>(m, s, p, t, ksh, kl, lsort);
+            if (go) phase_topo<CM, CAP>(m, s, p, t, ksh, kl, lsort);
             __syncthreads();
             if (threadIdx.x == 0) {
                 const int d = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || !go;
@@ -1702,6 +1709,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         return next;
     }
     const int worker = rank - 1;
+    unsigned long long c_bar = 0;
     for (int64_t t = j0 + 1;; ++t) {
         const unsigned long long c0 = __builtin_amdgcn_s_memrealtime();
         if (threadIdx.x == 0) {
@@ -1713,8 +1721,10 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
                 go = 0;
             } else {
                 // field step t-1 complete on every field workgroup
+                const unsigned long long cb = __builtin_amdgcn_s_memrealtime();
                 ok = spin_ge(&ctl->fbar, (unsigned long long)(t - 1 - j0) * W, s);
                 __threadfence();
+                c_bar += __builtin_amdgcn_s_memrealtime() - cb;
                 go = ok;
             }
             if (go && worker == 0) {
@@ -1725,7 +1735,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         __syncthreads();
         const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
         if (!go) break;
-        phase_field<CM>(m, s, p, t, worker, (int)W);
+        phase_field<CM, FK>(m, s, p, t, worker, (int)W);
         // field snapshot of step t-1 (its buffer is not written by step t)
         for (int q = 0; q < s.n_ckpt; ++q) {
             if (s.ckpt_steps[q] != t - 1 || t == 1) continue;
@@ -1742,7 +1752,11 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         c_wait += c1 - c0;
         c_work += c2 - c1;
     }
-    if (threadIdx.x == 0 && worker == 0) { ctl->clk_field += c_work; ctl->clk_wait1 += c_wait; }
+    if (threadIdx.x == 0 && worker == 0) {
+        ctl->clk_field += c_work;
+        ctl->clk_wait1 += c_wait - c_bar;
+        ctl->clk_fbar += c_bar;
+    }
     return 0;
 }
 
@@ -1753,9 +1767,9 @@ __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) 
     __shared__ int go;
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
-    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
+    KL<LCAP> *kl = (KL<LCAP> *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + LCAP * sizeof(uint64_t));
     if (__hip_atomic_load(&s.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    (void)gang_advance<CM>(m, s, p, (int)blockIdx.x, (int)gridDim.x, 0, ~0ull, ksh, kl, lsort, go);
+    (void)gang_advance<CM, LCAP, 2>(m, s, p, (int)blockIdx.x, (int)gridDim.x, 0, ~0ull, ksh, kl, lsort, go);
 }
 
 // ---------------------------------------------------------------------------
@@ -1780,7 +1794,11 @@ __device__ __forceinline__ void zero_dead_counters(Ctl *ctl, int64_t j0) {
     ctl->cnt_cand[(j0 + 2) & 3] = 0;
 }
 
-__global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss, const DParams *ps,
+// OCC workgroups per CU: OCC = 1 keeps the solo kernel's LDS topology path
+// (LCAP candidates) and two list entries per field thread; OCC = 2 halves
+// both (LCAP_BATCH, one entry) so that two workgroups overlap on each CU.
+template <int OCC>
+__global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState *ss, const DParams *ps,
                                               const int32_t *order, const int32_t *task_g, const int32_t *slots,
                                               int nslots, int *next_slot, unsigned long long budget_ticks,
                                               int32_t *done_out, unsigned int epoch) {
@@ -1789,7 +1807,9 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
     __shared__ long long jstart;
     KSh *ksh = (KSh *)lds;
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
-    KL *kl = (KL *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t));
+    constexpr int CAP = OCC == 2 ? LCAP_BATCH : LCAP;
+    constexpr int FKB = OCC == 2 ? 1 : 2;
+    KL<CAP> *kl = (KL<CAP> *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + CAP * sizeof(uint64_t));
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(next_slot, 1);
         __syncthreads();
@@ -1838,7 +1858,7 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
             } else if (rank != 0 && j0 < 0) {
                 // the visit never opened (error already recorded) or the mesh is done
             } else {
-                const int64_t nx = gang_advance<0>(m, s, p, rank, g, j0, budget_ticks, ksh, kl, lsort, go);
+                const int64_t nx = gang_advance<0, CAP, FKB>(m, s, p, rank, g, j0, budget_ticks, ksh, kl, lsort, go);
                 if (rank == 0 && threadIdx.x == 0) {
                     ctl->biter = nx;
                     if (done_out) done_out[w] = ctl->done;
@@ -1863,12 +1883,12 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
                     ctl->cnt_cand[(j + 2) & 3] = 0;
                 }
                 __syncthreads();
-                if (j >= 1) phase_topo<0>(m, s, p, j, ksh, kl, lsort);
+                if (j >= 1) phase_topo<0, CAP>(m, s, p, j, ksh, kl, lsort);
                 __syncthreads();
                 const int stop = ctl->done;
                 __syncthreads();
                 if (stop) break;
-                phase_field<0>(m, s, p, j + 1, 0, 1);
+                phase_field<0, FKB>(m, s, p, j + 1, 0, 1);
                 for (int q = 0; q < s.n_ckpt; ++q) {
                     if (s.ckpt_steps[q] != j || j == 0) continue;
                     const double *src = (j & 1) ? s.rho1 : s.rho0;
@@ -1888,14 +1908,16 @@ __global__ void __launch_bounds__(NT) k_batch(const DMesh *ms, const DState *ss,
 
 hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order,
                         const int32_t *task_g, const int32_t *slots, int nslots, int *next_slot, int grid, size_t lds,
-                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, hipStream_t st) {
+                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, int occ, hipStream_t st) {
     void *args[] = {&ms, &ss, &ps, &order, &task_g, &slots, &nslots, &next_slot, &budget_ticks, &done_out, &epoch};
-    return hipLaunchCooperativeKernel((const void *)k_batch, dim3(grid), dim3(NT), args, (unsigned)lds, st);
+    const void *fn = occ == 2 ? (const void *)k_batch<2> : (const void *)k_batch<1>;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, (unsigned)lds, st);
 }
 
-int max_coresident_batch(size_t lds_bytes) {
+int max_coresident_batch(size_t lds_bytes, int occ) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, NT, lds_bytes) != hipSuccess) return 0;
+    const void *fn = occ == 2 ? (const void *)k_batch<2> : (const void *)k_batch<1>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds_bytes) != hipSuccess) return 0;
     int dev = 0;
     (void)hipGetDevice(&dev);
     int cus = 0;
@@ -1903,10 +1925,18 @@ int max_coresident_batch(size_t lds_bytes) {
     return per_cu * cus;
 }
 
+// dynamic LDS of the solo step kernels: topology tables of LCAP candidates
 size_t step_lds_bytes(int block, int dmax) {
-    const size_t kb = ((sizeof(KSh) + 15) & ~(size_t)15) + SORTCAP * sizeof(uint64_t) + sizeof(KL);
-    const size_t fb = 16 + (size_t)block * (dmax + 1) * sizeof(int32_t);
-    return kb > fb ? kb : fb;
+    (void)block;
+    (void)dmax;
+    return ((sizeof(KSh) + 15) & ~(size_t)15) + LCAP * sizeof(uint64_t) + sizeof(KL<LCAP>);
+}
+
+// dynamic LDS of the batched kernel: LCAP candidates with one workgroup per
+// CU, LCAP_BATCH with two
+size_t batch_lds_bytes(int occ) {
+    if (occ != 2) return ((sizeof(KSh) + 15) & ~(size_t)15) + LCAP * sizeof(uint64_t) + sizeof(KL<LCAP>);
+    return ((sizeof(KSh) + 15) & ~(size_t)15) + LCAP_BATCH * sizeof(uint64_t) + sizeof(KL<LCAP_BATCH>);
 }
 
 int max_coresident_blocks(int block, size_t lds_bytes) {

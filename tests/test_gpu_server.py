@@ -139,19 +139,19 @@ def test_server_destroy_with_work_in_flight():
 
 
 def test_server_gangs_resize_and_switch(oracle_mod):
-    """Many large requests at once: the planner gives meshes of >= 2^17
-    vertices gangs of workgroups within three quarters of the pool, scaled
-    down and the smallest demoted to one workgroup when they do not fit;
-    as requests finish the remaining ones are re-planned, so a request's
-    visits switch between one workgroup and a gang and between gang sizes.
-    Every result equals the oracle's."""
+    """Many large requests at once: the planner grants meshes of >= 2^17
+    vertices gangs of workgroups, largest first, within three quarters of
+    the pool (512 workgroups at two per CU); the requests that no longer fit
+    run on one workgroup.  As requests finish the rest are re-planned, so a
+    request's visits switch from one workgroup to a gang.  Every result
+    equals the oracle's."""
     import paper_2105_13168_amd as vls
     ctx = vls.Context(0)
     big = [mg.pretzel(72, rng_seed=s) for s in (0, 1)] + [mg.pretzel(96, rng_seed=2), mg.lattice(3, 96, rng_seed=3)]
     M = [vls.Mesh(ctx, m.xyz, m.tri) for m in big]
     srv = vls.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=512, slice_us=300)
     try:
-        reqs = [(k % 2, srv.submit(M[k % 2], seed_vertex=big[k % 2].seed)) for k in range(110)]
+        reqs = [(k % 2, srv.submit(M[k % 2], seed_vertex=big[k % 2].seed)) for k in range(200)]
         reqs += [(2, srv.submit(M[2], seed_vertex=big[2].seed)), (3, srv.submit(M[3], seed_vertex=big[3].seed))]
         res = _wait(srv, [t for _, t in reqs], timeout=110.0)
         assert srv.stats()["launches"] > 3
