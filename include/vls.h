@@ -180,6 +180,9 @@ typedef struct {
     /* decoupled kernel: field workgroup 1's wait for the other field
        workgroups (wait1_ms is then its wait for the topology) */
     double field_barrier_ms;
+    /* event resolution split: merge loop walks and output, split walkers,
+       relabel walks, the rest (classification, ids, records) */
+    double event_split_ms[4];
 } vls_summary;
 vls_status vls_result_summary(const struct vls_result *r, vls_summary *s);
 

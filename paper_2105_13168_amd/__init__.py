@@ -54,7 +54,8 @@ class vls_summary(C.Structure):
                 ("topo_split_ms", C.c_double * 4), ("topo_event_ms", C.c_double),
                 ("topo_rounds_ms", C.c_double), ("topo_round_steps", C.c_int32),
                 ("topo_global_steps", C.c_int32), ("server_queue_ms", C.c_double),
-                ("server_latency_ms", C.c_double), ("field_barrier_ms", C.c_double)]
+                ("server_latency_ms", C.c_double), ("field_barrier_ms", C.c_double),
+                ("event_split_ms", C.c_double * 4)]
 
 
 class vls_reeb_node(C.Structure):

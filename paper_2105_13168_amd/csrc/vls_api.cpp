@@ -191,7 +191,7 @@ vls_status vls_context_destroy(vls_context *ctx) {
 namespace {
 
 struct HostAdj {
-    std::vector<int32_t> rp, adj, cyc, src, rev, succ, nin, ell, lrow;
+    std::vector<int32_t> rp, adj, cyc, src, rev, succ, nin, ell, lrow, hrec;
     int32_t dmax = 0;
 };
 
@@ -307,6 +307,14 @@ vls_status build_adjacency(vls_context *ctx, int64_t nv, int64_t nf, const int32
             if (q < 0) return set_err(ctx, VLS_E_MESH_NOT_MANIFOLD, "triangle (%lld,%d,%d) not closed", (long long)v, x, y);
             h.nin[e] = (int32_t)q;
         }
+    // walk records: successor, (y->x) half-edge, third vertex y, far end x
+    h.hrec.resize(4 * h.cyc.size());
+    for (size_t e = 0; e < h.cyc.size(); ++e) {
+        h.hrec[4 * e] = h.succ[e];
+        h.hrec[4 * e + 1] = h.nin[e];
+        h.hrec[4 * e + 2] = h.cyc[h.succ[e]];
+        h.hrec[4 * e + 3] = h.cyc[e];
+    }
     // connected
     std::vector<int32_t> queue;
     queue.reserve(nv);
@@ -380,6 +388,7 @@ static size_t run_buffer_bytes(const vls_mesh *m) {
     b += tag_cap * 4 * 2 + tag_cap * 4 * 2;        // tag_parent, tag_fid, front_birth, front_death
     b += ev_cap * 16 * 8 + ev_cap * 16 * 4 + ev_ids_cap * 8;
     b += lp_cap * 8 * 8 + lp_he_cap * 2 * 4 + lp_he_cap * 3 * 8 + lp_cap * 4 * 4;
+    b += 64 * 64 * 4 + lp_he_cap * 8;              // walk checkpoints, segment lengths
     b += sizeof(Ctl);
     return b;
 }
@@ -411,6 +420,8 @@ static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
     A(s.front_birth, (size_t)s.front_cap); A(s.front_death, (size_t)s.front_cap);
     A(s.lp, (size_t)s.lp_cap * 8); A(s.lp_he, (size_t)s.lp_he_cap * 2); A(s.lp_pts, (size_t)s.lp_he_cap * 3);
     A(s.tn, (size_t)s.lp_cap * 4);
+    A(s.wck, 64 * 64);
+    A(s.wseg, (size_t)s.lp_he_cap);
     A(s.ctl, 1);
 #undef A
     if (e != hipSuccess) return set_err(m->ctx, VLS_E_OUT_OF_MEMORY, "device allocation failed: %s", hipGetErrorString(e));
@@ -522,7 +533,7 @@ vls_status vls_mesh_create(vls_context *ctx, int64_t nv, const double *xyz, int6
         (st = upload(m.get(), h.cyc, &d.cyc)) || (st = upload(m.get(), h.src, &d.src)) ||
         (st = upload(m.get(), h.rev, &d.rev)) || (st = upload(m.get(), h.succ, &d.succ)) ||
         (st = upload(m.get(), h.nin, &d.nin)) || (st = upload(m.get(), h.ell, &d.ell)) ||
-        (st = upload(m.get(), h.lrow, &d.lrow)) ||
+        (st = upload(m.get(), h.lrow, &d.lrow)) || (st = upload(m.get(), h.hrec, &d.hrec)) ||
         (st = upload(m.get(), m->xyz, &d.xyz))) {
         for (void *p : m->allocs) (void)hipFree(p);
         return st;
@@ -756,6 +767,7 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     S.topo_round_steps = c.n_round_steps;
     S.topo_global_steps = c.n_global_steps;
     S.field_barrier_ms = (double)c.clk_fbar * 1e-5;
+    for (int q = 0; q < 4; ++q) S.event_split_ms[q] = (double)c.clk_evp[q] * 1e-5;
     vls_status rs = c.status;
     if (rs == VLS_E_INVARIANT || rs == VLS_E_CAPACITY)
         set_err(ctx, rs, "device reported %s (detail %d) at step %lld", vls_status_string(rs), c.err_code, (long long)c.steps);

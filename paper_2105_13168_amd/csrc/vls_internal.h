@@ -26,6 +26,7 @@ struct DMesh {
     const int32_t *nin;   // [nnz]  e=(u->x), y=cyc[succ[e]]: index of half-edge (y->x)
     const int32_t *ell;   // [nv][ELL_W] ascending neighbours padded with the vertex itself;
                           //   first entry -1 when the degree exceeds ELL_W
+    const int32_t *hrec;  // [nnz][4] per half-edge e: succ[e], nin[e], cyc[succ[e]], cyc[e]
     const int32_t *lrow;  // [nv][ELL_W] counter-clockwise neighbours from the smallest id,
                           //   padded with -1, first half-edge index in the last slot;
                           //   first entry -2 when the degree exceeds ELL_W - 1
@@ -74,6 +75,8 @@ struct Ctl {
     unsigned long long clk_t[4];
     unsigned long long clk_ev, clk_rounds;
     unsigned long long clk_fbar;   // field workgroup 1: wait for the other field workgroups
+    unsigned long long clk_evp[4]; // events: merge walks, split walkers, relabel walks, the rest
+    unsigned long long clk_ev0;
     int32_t n_round_steps, n_global_steps;
     // batched mode: next iteration to run (a mesh may be advanced over
     // several launches, each visit bounded in time), the first iteration of
@@ -117,6 +120,8 @@ struct DState {
     double *lp_pts;          // [lp_he_cap][3]
     int64_t lp_he_cap;
     int32_t *tn;             // [lp_cap][4]: loop index, v, a_j, a_0
+    int32_t *wck;            // [64][64] walk checkpoints of an event's involved loops
+    double *wseg;            // [lp_he_cap] segment lengths of the loop being written
     double *ckpt;            // [n_ckpt][nv]
     const int64_t *ckpt_steps;  // (device) [n_ckpt]
     int32_t n_ckpt;

@@ -32,7 +32,10 @@ namespace vls {
 #define NT 256               // threads per workgroup (4 wave64)
 #define WAVE 64
 #define MAXDEG 64            // vertex degree bound of the event path (one lane per link position)
+#define WCK 64               // walk checkpoints per involved loop
+#define MAXBP 256            // rank-order breakpoints per event step kept in LDS
 #define GLOBAL_AS __attribute__((address_space(1)))   // global memory (avoids flat accesses)
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 enum { NODE_SEED = 0, NODE_SPLIT = 1, NODE_MERGE = 2, NODE_VANISH = 3, NODE_DEGENERATE = 4 };
 enum { ST_OK = 0, ST_SEED_INVALID = -6, ST_STALLED = -7, ST_CAPACITY = -11, ST_INVARIANT = -13 };
@@ -112,14 +115,15 @@ __device__ __forceinline__ void fail(const DState &s, int code, int detail) {
 // the inside set is {y : rank(y) < rank(v)} (plus v itself when post): the
 // triangle (u, x, y) holding directed edge u->x has one more crossed edge,
 // (y,x) if y is inside, else (u,y).
+// One 16 B record per half-edge gives succ[e], nin[e] and y in one load,
+// so a walk step is two dependent loads (record, then the key of y).
 __device__ __forceinline__ int32_t he_next(const DMesh &m, const uint64_t *__restrict__ key,
                                            int32_t e, uint64_t kv, int32_t v, bool post) {
-    const int32_t j = ldg(m.succ + e);
-    const int32_t ni = ldg(m.nin + e);
-    const int32_t y = ldg(m.cyc + j);
+    const v4i r = *(const GLOBAL_AS v4i *)(m.hrec + 4 * (int64_t)e);
+    const int32_t y = r.z;
     const uint64_t ky = ldg(key + y);
     const bool in = rank_lt(ky, y, kv, v) || (post && y == v);
-    return in ? ni : j;
+    return in ? r.y : r.x;
 }
 
 // ---------------------------------------------------------------------------
@@ -311,7 +315,6 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 // field phase of step t: rho_t from rho_{t-1} over the update list C_t
 // ---------------------------------------------------------------------------
 #define GB ELL_W   // neighbours gathered per vertex in registers (one padded row)
-typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 // Field phase of step t: rho_t from rho_{t-1} over the update set C_t.
 //
@@ -545,6 +548,12 @@ struct KSh {
     long long lpoff[MAXDEG / 2 + 1];
     long long lpmin[MAXDEG / 2 + 1];
     double lplength[MAXDEG / 2 + 1];
+    long long lpk[MAXDEG / 2 + 1];      // checkpoint stride of each involved loop's walk
+    int lpnck[MAXDEG / 2 + 1];          // checkpoints kept
+    // rank-order breakpoints of an event step (events, round starts)
+    int nbp;
+    int bpu[MAXBP];
+    int bps[MAXBP];
 };
 
 // root of a front tag; -1 when the tag is not a valid one (a broken
@@ -644,6 +653,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
                               int32_t v, KSh *sh, const double *rho) {
     Ctl *ctl = s.ctl;
     const int lane = __lane_id();
+    if (lane == 0) ctl->clk_ev0 = __builtin_amdgcn_s_memrealtime();
     const int32_t b = m.rp[v];
     const int d = m.rp[v + 1] - b;
     const uint64_t kv = s.key[v];
@@ -721,14 +731,30 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
     __threadfence_block();
     // ---- merge: the involved loops before v joins (handle loops) ----------
     int keep_loop0 = 0;
+    const unsigned long long q0 = __builtin_amdgcn_s_memrealtime();
     if (!full && sN >= 2) {
         if (sN > MAXDEG / 2) { if (lane == 0) fail(s, ST_CAPACITY, 3); return; }
         long long n = 0, best = LLONG_MAX, bestidx = 0;
         int32_t e0 = -1;
+        // one walk per involved loop (one lane per loop); it keeps at most
+        // WCK checkpoints, evenly spaced at a power-of-two stride K (halved
+        // into every other one and K doubled when full), so the output pass
+        // below re-walks only K-step segments, one lane per segment
+        int32_t *ck = s.wck + (int64_t)lane * WCK;
+        long long K = 1;
+        int nck = 0;
         if (lane < sN) {
             e0 = m.rev[b + sh->srep[lane]];
             int32_t e = e0;
             do {
+                if ((n & (K - 1)) == 0) {
+                    if (nck == WCK) {
+                        for (int c = 0; c < WCK / 2; ++c) ck[c] = ck[2 * c];
+                        nck = WCK / 2;
+                        K *= 2;
+                    }
+                    if ((n & (K - 1)) == 0) ck[nck++] = e;
+                }
                 const long long key = (long long)m.src[e] * m.nv + m.cyc[e];
                 if (key < best) { best = key; bestidx = n; }
                 n++;
@@ -737,6 +763,8 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
             if (n > m.nnz) fail(s, ST_INVARIANT, 4);
             sh->lplen[lane] = n;
             sh->lpmin[lane] = bestidx;
+            sh->lpk[lane] = K;
+            sh->lpnck[lane] = nck;
         }
         __builtin_amdgcn_wave_barrier();
         __threadfence_block();
@@ -762,31 +790,48 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
         const int nl0 = __shfl(sh->flag, 0);
         if (nl0 < 0) return;
         keep_loop0 = nl0;
-        if (lane < sN) {
-            const long long off = sh->lpoff[lane];
-            int32_t e = e0;
-            long long i = 0;
-            do {
-                const long long pos = off + (i - bestidx + n) % n;
-                const int32_t uu = m.src[e], xx = m.cyc[e];
-                s.lp_he[2 * pos] = uu;
-                s.lp_he[2 * pos + 1] = xx;
-                crossing_point<CM>(m, rho, uu, xx, p.tau, s.lp_pts + 3 * pos);
-                i++;
-                e = he_next(m, s.key, e, kv, v, false);
-            } while (e != e0);
-            double L = 0.0;
-            for (long long q = 0; q < n; ++q) {
-                const double *pa = s.lp_pts + 3 * (off + q);
-                const double *pb = s.lp_pts + 3 * (off + (q + 1) % n);
-                const double dx = pb[0] - pa[0], dy = pb[1] - pa[1], dz = pb[2] - pa[2];
-                L = L + sqrt((dx * dx + dy * dy) + dz * dz);
+        // output, loop by loop: crossed edges from the minimum key on, their
+        // crossing points, then the segment lengths; the length is summed in
+        // that order by one lane
+        for (int q = 0; q < sN; ++q) {
+            const long long nq = sh->lplen[q], bq = sh->lpmin[q], Kq = sh->lpk[q], off = sh->lpoff[q];
+            const int ncq = sh->lpnck[q];
+            const int32_t *ckq = s.wck + (int64_t)q * WCK;
+            for (int c = lane; c < ncq; c += WAVE) {
+                int32_t e = ckq[c];
+                const long long i0 = (long long)c * Kq;
+                const long long i1 = i0 + Kq < nq ? i0 + Kq : nq;
+                for (long long i = i0; i < i1; ++i) {
+                    const long long rel = i - bq;
+                    const long long pos = off + (rel < 0 ? rel + nq : rel);
+                    const int32_t uu = m.src[e], xx = m.cyc[e];
+                    s.lp_he[2 * pos] = uu;
+                    s.lp_he[2 * pos + 1] = xx;
+                    crossing_point<CM>(m, rho, uu, xx, p.tau, s.lp_pts + 3 * pos);
+                    e = he_next(m, s.key, e, kv, v, false);
+                }
             }
-            sh->lplength[lane] = L;
+            __builtin_amdgcn_wave_barrier();
+            __threadfence_block();
+            for (long long i = lane; i < nq; i += WAVE) {
+                const double *pa = s.lp_pts + 3 * (off + i);
+                const double *pb = s.lp_pts + 3 * (off + (i + 1 == nq ? 0 : i + 1));
+                const double dx = pb[0] - pa[0], dy = pb[1] - pa[1], dz = pb[2] - pa[2];
+                s.wseg[i] = sqrt((dx * dx + dy * dy) + dz * dz);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __threadfence_block();
+            if (lane == 0) {
+                double L = 0.0;
+                for (long long i = 0; i < nq; ++i) L = L + s.wseg[i];
+                sh->lplength[q] = L;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __threadfence_block();
         }
-        __builtin_amdgcn_wave_barrier();
-        __threadfence_block();
     }
+    const unsigned long long q1 = __builtin_amdgcn_s_memrealtime();
+    unsigned long long q2 = q1, q3 = q1;
     // ---- the loops after v joins: walkers from the end of each new arc ----
     int mN = 0;
     if (!full) {
@@ -814,17 +859,38 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
         int32_t e = lane < k ? b + sh->oend[lane] : -1;
         bool done = lane >= k;
         int steps = 0, tgt = -1;
+        // checkpoints of each walker's arc (same scheme as the merge walks),
+        // for the relabel below
+        int32_t *ckw = s.wck + (int64_t)lane * WCK;
+        long long K = 1;
+        int nck = 0;
+        if (lane < k) ckw[nck++] = e;
         for (;;) {
             const unsigned long long act = __ballot(!done) & ((k == 64) ? ~0ull : ((1ull << k) - 1ull));
             if (__popcll(act) <= 1) break;
             if (!done) {
                 e = he_next(m, s.key, e, kv, v, true);
                 steps++;
+                if ((steps & (K - 1)) == 0) {
+                    if (nck == WCK) {
+                        for (int c = 0; c < WCK / 2; ++c) ckw[c] = ckw[2 * c];
+                        nck = WCK / 2;
+                        K *= 2;
+                    }
+                    if ((steps & (K - 1)) == 0) ckw[nck++] = e;
+                }
                 if (m.src[e] == v) { done = true; tgt = sh->runid[e - b]; }
                 if (steps > m.nnz) { fail(s, ST_INVARIANT, 7); done = true; tgt = 0; }
             }
         }
-        if (lane < k) { sh->fin[lane] = done ? 1 : 0; sh->sig[lane] = tgt; sh->steps_w[lane] = steps; }
+        if (lane < k) {
+            sh->fin[lane] = done ? 1 : 0;
+            sh->sig[lane] = tgt;
+            sh->steps_w[lane] = steps;
+            sh->lpk[lane] = K;
+            sh->lpnck[lane] = nck;
+        }
+        q2 = __builtin_amdgcn_s_memrealtime();
         __builtin_amdgcn_wave_barrier();
         __threadfence_block();
         if (__shfl(ld_relaxed(&ctl->status), 0) != 0) return;
@@ -900,14 +966,24 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
         if (mN < 0) return;
         const int big = __shfl(sh->maxround, 0);
         // tags of the new arcs, and relabel of every loop but the big one
+        q3 = __builtin_amdgcn_s_memrealtime();
         if (lane < d && !low) s.lid[b + lane] = sh->newtag[sh->cyc_of[sh->runid[lane]]];
-        if (lane < k && sh->cyc_of[lane] != big) {
-            const int32_t tg = sh->newtag[sh->cyc_of[lane]];
-            int32_t ee = b + sh->oend[lane];
-            for (int64_t guard = 0; guard <= m.nnz; ++guard) {
-                ee = he_next(m, s.key, ee, kv, v, true);
-                if (m.src[ee] == v) break;
-                s.lid[ee] = tg;
+        // the arcs walked to completion: edges 1 .. steps-1 of each walk,
+        // replayed in K-step segments from its checkpoints, one lane each
+        for (int o = 0; o < k; ++o) {
+            if (sh->cyc_of[o] == big) continue;
+            const int32_t tg = sh->newtag[sh->cyc_of[o]];
+            const long long so = sh->steps_w[o], Ko = sh->lpk[o];
+            const int nco = sh->lpnck[o];
+            const int32_t *cko = s.wck + (int64_t)o * WCK;
+            for (int c = lane; c < nco; c += WAVE) {
+                int32_t ee = cko[c];
+                const long long i0 = (long long)c * Ko;
+                const long long i1 = i0 + Ko < so ? i0 + Ko : so;
+                for (long long i = i0; i < i1; ++i) {
+                    if (i >= 1) s.lid[ee] = tg;
+                    ee = he_next(m, s.key, ee, kv, v, true);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -915,6 +991,11 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
     }
     // ---- bookkeeping: h, x, node, records ----------------------------------
     if (lane == 0) {
+        const unsigned long long q4 = __builtin_amdgcn_s_memrealtime();
+        ctl->clk_evp[0] += q1 - q0;          // merge walks and loop output
+        ctl->clk_evp[1] += q2 - q1;          // split walkers
+        ctl->clk_evp[2] += q4 - q3;          // relabel walks
+        ctl->clk_evp[3] += q0 - ctl->clk_ev0 + (q3 - q2);   // the rest
         long long h = 0, xx = 0;
         bool ok = true;
         if (full) {
@@ -1492,30 +1573,89 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         __syncthreads();
         if (tid == 0) sh->nnew = 0;
         __syncthreads();
+        // sort key: round (21 bits) | vertex (31) | table index (11) | event flag
         for (int i = tid; i < nL; i += NT) {
             if (kl->Lr[i] < 0) continue;
             const int slot = atomicAdd(&sh->nnew, 1);
-            arr[slot] = ((uint64_t)kl->Lr[i] << 33) | ((uint64_t)kl->Lv[i] << 1) | (uint64_t)(kl->Lc[i] != 1);
+            arr[slot] = ((uint64_t)kl->Lr[i] << 43) | ((uint64_t)kl->Lv[i] << 12) | ((uint64_t)i << 1) |
+                        (uint64_t)(kl->Lc[i] != 1);
         }
         __syncthreads();
         block_bitonic(arr, npow);
-        int pos = 0;
+        // breakpoints of the rank order: events and first entries of a round,
+        // gathered in parallel, then ranked (few per step)
+        if (tid == 0) sh->nbp = 0;
+        __syncthreads();
+        for (int i = tid; i < nN; i += NT)
+            if ((arr[i] & 1ull) || (i > 0 && (arr[i] >> 43) != (arr[i - 1] >> 43))) {
+                const int k = atomicAdd(&sh->nbp, 1);
+                if (k < MAXBP) sh->bpu[k] = i;
+            }
+        __syncthreads();
+        const int nbp = sh->nbp < MAXBP ? sh->nbp : MAXBP;
+        const bool bp_ok = sh->nbp <= MAXBP;
+        for (int i = tid; i < nbp; i += NT) {
+            const int x = sh->bpu[i];
+            int r = 0;
+            for (int j = 0; j < nbp; ++j) r += sh->bpu[j] < x;
+            sh->bps[r] = x;
+        }
+        __syncthreads();
+        int pos = 0, kb = 0;
         while (pos < nN) {
-            int q = pos;
-            while (q < nN && !(arr[q] & 1ull)) q++;
-            int a0 = pos;
-            while (a0 < q) {
-                const int r = (int)(arr[a0] >> 33);
-                int a1 = a0;
-                while (a1 < q && (int)(arr[a1] >> 33) == r) a1++;
-                for (int i = a0 + tid; i < a1; i += NT)
-                    regular_insert(m, s, (int32_t)((arr[i] >> 1) & 0xffffffffull));
+            int q, a0 = pos, qr;
+            if (bp_ok) {
+                // next breakpoint at or after pos; regular entries of one
+                // round lie between consecutive breakpoints
+                while (kb < nbp && sh->bps[kb] < pos) kb++;
+                qr = kb < nbp ? sh->bps[kb] : nN;
+                if (qr == pos && !(arr[pos] & 1ull)) {
+                    // a round starts here: its range runs to the next breakpoint
+                    kb++;
+                    qr = kb < nbp ? sh->bps[kb] : nN;
+                }
+                q = (qr < nN && (arr[qr] & 1ull)) ? qr : nN;
+                if (qr < nN && !(arr[qr] & 1ull)) q = -1;     // round change, no event yet
+            } else {
+                q = pos;
+                while (q < nN && !(arr[q] & 1ull)) q++;
+                qr = q;
+            }
+            const int stop = q < 0 ? qr : q;
+            while (a0 < stop) {
+                const int r = (int)(arr[a0] >> 43);
+                int a1 = stop;
+                if (!bp_ok) {
+                    a1 = a0;
+                    while (a1 < stop && (int)(arr[a1] >> 43) == r) a1++;
+                }
+                // regular insertions from the classification tables; the tag
+                // of (parent -> v) is read now (an earlier event of this step
+                // may have relabelled it), and the parent is of an earlier
+                // round, so its depth is final
+                for (int i = a0 + tid; i < a1; i += NT) {
+                    const int ix = (int)((arr[i] >> 1) & 0x7ffull);
+                    const int32_t v = kl->Lv[ix];
+                    const int32_t b = kl->Lb[ix];
+                    const int d = kl->Lg[ix];
+                    const int32_t par = kl->Lp[ix];
+                    const int ppos = kl->Lq[ix];
+                    const uint64_t mask = kl->Lm[ix];
+                    const int32_t tag = ppos >= 0 ? ldg(s.lid + ldg(m.rev + b + ppos)) : -1;
+                    s.depth[v] = par >= 0 ? ldg(s.depth + par) + 1 : 0;
+                    for (int j = 0; j < d; ++j)
+                        if (!(mask >> j & 1ull)) s.lid[b + j] = tag;
+                }
                 __syncthreads();
                 a0 = a1;
             }
+            if (q < 0) {
+                pos = qr;              // continue with the next round
+                continue;
+            }
             if (q < nN) {
                 if (tid < WAVE)
-                    resolve_event<CM>(m, s, p, t, (int32_t)((arr[q] >> 1) & 0xffffffffull), sh, rho);
+                    resolve_event<CM>(m, s, p, t, (int32_t)((arr[q] >> 12) & 0x7fffffffull), sh, rho);
                 __syncthreads();
                 if (ld_relaxed(&ctl->status) != 0) break;
             }
