@@ -165,6 +165,7 @@ def batch_leg(ctx, n, seq_sample):
         "meshes": n, "total_vertices": int(sum(m.nv for m in ms)), "all_handles_equal_genus": ok,
         "seconds": tb, "meshes_per_s": n / tb, "batch_kernel_ms": kernel_ms,
         "vertex_steps_per_s": vsteps / tb,
+        "dense_equivalent_frac": (vsteps / tb) * 56.0 / (HBM_PEAK_GBPS * 1e9),
         "hbm_roofline_frac": ab / (kernel_ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
         "sequential_sample": len(sample), "sequential_seconds": ts,
         "sequential_meshes_per_s": seq_rate,
@@ -364,6 +365,7 @@ def main():
     ab = alg_bytes(upd, deg)
     achieved = ab / (kernel_ms * 1e-3) / 1e9
     value = m.nv * steps / (ms * 1e-3)
+    dense_bytes = 32.0 + 4.0 * (3.0 * m.nf) / m.nv          # per vertex: 32 B + 4 B per neighbour id
     out = {
         "metric": "vertex-diffusion-steps/sec",
         "value": value,
@@ -390,6 +392,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms),
                      "kernel": "k_steps_dec", "algorithmic_bytes": ab,
+                     # a dense step (every vertex, 32 + 4 deg bytes) at this
+                     # vertex-steps/s would need this share of HBM peak
+                     "dense_equivalent_frac": value * dense_bytes / (HBM_PEAK_GBPS * 1e9),
                      "kernel_source_hash": kernel_source_hash()},
     }
     if args.batch > 0:

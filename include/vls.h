@@ -100,7 +100,9 @@ typedef struct vls_params {
     uint32_t flags;            /* VLS_RECORD_FIELD                                        */
     int32_t n_ckpt;            /* number of entries in ckpt_steps                         */
     const int64_t *ckpt_steps; /* (host) steps whose field is kept (with VLS_RECORD_FIELD) */
-    int32_t grid;              /* persistent workgroups; 0 = chosen by the library        */
+    int32_t grid;              /* persistent workgroups; 0 = chosen by the library: about
+                                  one per 22k vertices, 16..128, at most what is co-resident;
+                                  vls_batch_run: pool size of per_mesh[0]                 */
     int32_t block;             /* threads per workgroup: 256 (0 = default)                */
 } vls_params;
 

@@ -840,7 +840,9 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     const size_t lds = step_lds_bytes(block, m->dmax);
     const int maxg = max_coresident_blocks(block, lds);
     if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
-    int grid = p->grid > 0 ? p->grid : 64;
+    // default launch: about one workgroup per 22k vertices (the field's share
+    // of a step grows with the band; the topology workgroup does not), 16..128
+    int grid = p->grid > 0 ? p->grid : (int)std::min<int64_t>(128, std::max<int64_t>(16, m->nv / 22000));
     if (grid > maxg) grid = maxg;
     hipError_t le = launch_steps(m->d, rp.s, rp.dp, grid, block, ctx->stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le));
