@@ -106,11 +106,12 @@ def batch_leg(ctx, n, seq_sample):
     M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
     genus = [x.euler_genus for x in M]
 
-    def run_batch(idx, extra=0):
+    def run_batch(idx, extra=0, gv=0):
         hm = (C.c_void_p * len(idx))(*[M[i].h.value for i in idx])
         ps = (vls.vls_params * len(idx))()
         for k, i in enumerate(idx):
-            ps[k] = vls.default_params(seed_vertex=ms[i].seed, flags=vls.VLS_DEFER_RESULTS | extra)
+            ps[k] = vls.default_params(seed_vertex=ms[i].seed, flags=vls.VLS_DEFER_RESULTS | extra,
+                                       gang_vertices=gv)
         outs = (C.c_void_p * len(idx))()
         st = vls.vls_batch_run(ctx.h, len(idx), hm, ps, outs)
         sums = []
@@ -125,11 +126,19 @@ def batch_leg(ctx, n, seq_sample):
 
     run_batch(list(range(n)))                     # warm-up: allocates every mesh's run buffers
     torch.cuda.synchronize()
-    # both pool shapes: one workgroup per CU, and two (smaller LDS tables)
+    # schedule: tuned on a sample of the workload (every 4th mesh), then the
+    # whole batch timed with the tuned and the default schedule
+    from paper_2105_13168_amd.tune import tune_batch
+    t0 = time.time()
+    samp = list(range(0, n, 4))
+    tuned = tune_batch(ctx, [M[i] for i in samp], [ms[i].seed for i in samp])
+    log(f"batch schedule tuned on {len(samp)} meshes: {tuned} ({time.time() - t0:.1f}s)")
     shapes = {}
-    for name, extra in (("one_per_cu", 0), ("two_per_cu", vls.VLS_BATCH_TWO_PER_CU)):
+    for name, extra, gv in (("default", 0, 0),
+                            ("tuned", vls.VLS_BATCH_TWO_PER_CU if tuned["two_per_cu"] else 0,
+                             tuned["gang_vertices"])):
         t1 = time.perf_counter()
-        sm = run_batch(list(range(n)), extra)
+        sm = run_batch(list(range(n)), extra, gv)
         torch.cuda.synchronize()
         shapes[name] = (time.perf_counter() - t1, sm)
     best = min(shapes, key=lambda k: shapes[k][0])
@@ -159,7 +168,8 @@ def batch_leg(ctx, n, seq_sample):
     return {
         "slowest": [{"nv": int(ms[i].nv), "steps": int(sums[i]["steps"]), "events": int(sums[i]["n_events"]),
                      "ms": round(sums[i]["topo_ms"] + sums[i]["wait0_ms"], 1)} for i in slow],
-        "pool_shape": best,
+        "schedule": best, "tuned_schedule": {k: tuned[k] for k in ("two_per_cu", "gang_vertices")},
+        "tuning_seconds": tuned["seconds"],
         "seconds_by_shape": {k: round(v[0], 3) for k, v in shapes.items()},
         "kernel_ms_by_shape": {k: round(v[1][0]["kernel_ms"], 1) for k, v in shapes.items()},
         "meshes": n, "total_vertices": int(sum(m.nv for m in ms)), "all_handles_equal_genus": ok,

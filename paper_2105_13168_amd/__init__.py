@@ -39,7 +39,8 @@ class vls_params(C.Structure):
                 ("seed_vertex", C.c_int64), ("rng_seed", C.c_uint64),
                 ("seed_radius", C.c_int32), ("stall_steps", C.c_int32),
                 ("max_steps", C.c_int64), ("flags", C.c_uint32), ("n_ckpt", C.c_int32),
-                ("ckpt_steps", C.POINTER(C.c_int64)), ("grid", C.c_int32), ("block", C.c_int32)]
+                ("ckpt_steps", C.POINTER(C.c_int64)), ("grid", C.c_int32), ("block", C.c_int32),
+                ("gang_vertices", C.c_int64)]
 
 
 class vls_summary(C.Structure):

@@ -803,7 +803,8 @@ struct BatchPlan {
     int nslots = 0, grid = 0;
 };
 
-void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp) {
+void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp, int64_t gang_verts = kGangVerts) {
+    if (gang_verts <= 0) gang_verts = kGangVerts;
     const int n = (int)nv.size();
     bp.order.resize(n);
     for (int i = 0; i < n; ++i) bp.order[i] = i;
@@ -811,7 +812,7 @@ void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp) {
     bp.task_g.assign(n, 1);
     int64_t left = (int64_t)pool * 3 / 4;
     for (int w = 0; w < n; ++w) {
-        const int64_t want = std::min<int64_t>(kGangMax, nv[bp.order[w]] / kGangVerts);
+        const int64_t want = std::min<int64_t>(kGangMax, nv[bp.order[w]] / gang_verts);
         const int64_t g = std::min(want, left);
         if (g >= 2) { bp.task_g[w] = (int32_t)g; left -= g; }
     }
@@ -886,7 +887,7 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
     std::vector<int64_t> nvs(n);
     for (int32_t i = 0; i < n; ++i) nvs[i] = meshes[i]->nv;
     BatchPlan bp;
-    plan_batch(nvs, pool, bp);
+    plan_batch(nvs, pool, bp, per_mesh[0].gang_vertices);
     const int grid = bp.grid;
     void *dm = nullptr, *ds = nullptr, *dpp = nullptr, *dord = nullptr, *dnext = nullptr, *dtg = nullptr,
          *dsl = nullptr;
@@ -1145,6 +1146,7 @@ struct vls_server {
     size_t budget = 0;
     int max_slots = 0;
     int occ = 2;                     // workgroups per CU of the step launches
+    int64_t gang_verts = 0;          // vertices per gang workgroup (0 = default)
     unsigned long long slice_ticks = 0;
     std::mutex mu;
     std::condition_variable cv;
@@ -1246,7 +1248,7 @@ bool vls_server::launch_slice() {
     const int maxg = max_coresident_batch(lds, occ);
     if (maxg <= 0) return false;
     BatchPlan bp;
-    plan_batch(nvs, maxg, bp);
+    plan_batch(nvs, maxg, bp, gang_verts);
     if (bp.nslots > cap + 4096) return false;      // slot buffer holds cap + 4096 slots
     const std::vector<int32_t> &order = bp.order;
     hipStream_t st = ctx.stream;

@@ -79,3 +79,27 @@ def test_batch_gangs_match_oracle(oracle_mod, pool, two_per_cu):
     for x in M:
         x.close()
     ctx.close()
+
+
+def test_batch_schedule_changes_no_result():
+    """Every schedule the tuner may pick (pool shape, vertices per gang
+    workgroup) gives bit-identical results; the tuner returns one of them."""
+    import numpy as np
+    import paper_2105_13168_amd as vls
+    from paper_2105_13168_amd.tune import tune_batch
+    ctx = vls.Context(0)
+    ms = [mg.pretzel(96, rng_seed=2), mg.pretzel(72, rng_seed=1), mg.torus_grid(rng_seed=4),
+          mg.multi_torus(2, 28, rng_seed=5)]
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    seeds = [m.seed for m in ms]
+    ref = vls.batch_run(ctx, M, seeds)
+    for two, gv in ((False, 32768), (True, 131072), (True, 16384)):
+        res = vls.batch_run(ctx, M, seeds, gang_vertices=gv, flags=vls.VLS_BATCH_TWO_PER_CU if two else 0)
+        for a, b in zip(ref, res):
+            assert np.array_equal(a.rho.view(np.int64), b.rho.view(np.int64))
+            assert np.array_equal(a.events, b.events) and np.array_equal(a.step, b.step)
+    t = tune_batch(ctx, M, seeds, candidates=((False, 65536), (True, 32768)))
+    assert (t["two_per_cu"], t["gang_vertices"]) in ((False, 65536), (True, 32768))
+    for x in M:
+        x.close()
+    ctx.close()
