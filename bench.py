@@ -65,12 +65,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_ms):
+def measured_traffic(kernel_ms, workload):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     runs (FETCH_SIZE, WRITE_SIZE scaled by a copy of known size), as GB/s over
-    the live kernel time; None when the counters were taken on other kernel
-    sources."""
-    path = os.path.join(ROOT, "profiles", "k_steps_pretzel256_traffic.json")
+    the live kernel time; None when the counters were taken on another
+    workload or on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_steps_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -400,7 +400,7 @@ def main():
             "event_steps": last["event_steps"],
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms, args.workload),
                      "kernel": "k_steps_dec", "algorithmic_bytes": ab,
                      # a dense step (every vertex, 32 + 4 deg bytes) at this
                      # vertex-steps/s would need this share of HBM peak

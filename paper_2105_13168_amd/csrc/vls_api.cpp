@@ -679,15 +679,19 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     r->nv = nv;
     std::vector<int64_t> cnt(std::max(nev, ntn) + 1, 0), off;
     void *dcnt = nullptr, *doff = nullptr, *dbuf = nullptr, *dpos = nullptr, *dtn = nullptr;
-    void *dtcnt = nullptr, *dtoff = nullptr, *dtlen = nullptr;
+    void *dtcnt = nullptr, *dtoff = nullptr, *dtlen = nullptr, *dck = nullptr, *dmeta = nullptr;
     struct Guard {
         std::vector<void **> ptrs;
         ~Guard() { for (void **q : ptrs) if (*q) (void)hipFree(*q); }
-    } guard{{&dcnt, &doff, &dbuf, &dtcnt, &dtoff}};
+    } guard{{&dcnt, &doff, &dbuf, &dtcnt, &dtoff, &dck, &dmeta}};
     if (nev > 0) {
         HIPCHK(ctx, hipMalloc(&dcnt, (nev + 1) * sizeof(int64_t)));
         HIPCHK(ctx, hipMalloc(&doff, (nev + 1) * sizeof(int64_t)));
-        HIPCHK(ctx, launch_reeb_count(m->d, s, nev, (int64_t *)dcnt, stream));
+        // per event and involved loop (at most 16): 64 walk checkpoints and
+        // {length, stride, checkpoints, offset}
+        HIPCHK(ctx, hipMalloc(&dck, (size_t)nev * 16 * 64 * sizeof(int32_t)));
+        HIPCHK(ctx, hipMalloc(&dmeta, (size_t)nev * 16 * 4 * sizeof(int64_t)));
+        HIPCHK(ctx, launch_reeb_count(m->d, s, nev, (int64_t *)dcnt, (int32_t *)dck, (int64_t *)dmeta, stream));
         HIPCHK(ctx, hipMemcpyAsync(cnt.data(), dcnt, nev * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
         off.assign(nev + 1, 0);
@@ -699,7 +703,8 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
         HIPCHK(ctx, hipMemcpyAsync(doff, off.data(), (nev + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
         HIPCHK(ctx, hipMalloc(&dbuf, off[nev] * sizeof(int32_t) + 16));
         HIPCHK(ctx, hipMalloc(&dpos, nev * 3 * sizeof(double)));
-        HIPCHK(ctx, launch_reeb_fill(m->d, s, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dbuf, stream));
+        HIPCHK(ctx, launch_reeb_fill(m->d, s, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dck,
+                                     (int64_t *)dmeta, (int32_t *)dbuf, stream));
         HIPCHK(ctx, launch_reeb_mean(m->d, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dbuf, (double *)dpos, stream));
     }
     std::vector<int64_t> tcnt(ntn + 1, 0);

@@ -2114,43 +2114,87 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
 // front triangles of the involved loops just before the event vertex joins,
 // summed in ascending vertex id
 // ---------------------------------------------------------------------------
-__device__ int64_t walk_event_loops(const DMesh &m, const DState &s, int ev, int32_t *out) {
+// Count pass: one wave per event, one lane per involved loop.  Each lane
+// walks its loop once (inside set {rank < rank(v)}) and keeps up to RCK
+// checkpoints at a power-of-two stride, so the fill pass re-walks short
+// segments in parallel.  meta[ev][q] = {length, stride, checkpoints, offset
+// of the loop's entries}; cnt[ev] = 3 * total length.
+#define RCK 64
+__global__ void k_reeb_count(DMesh m, DState s, int n_events, int64_t *cnt, int32_t *ck, int64_t *meta) {
+    const int ev = blockIdx.x;
+    if (ev >= n_events) return;
+    const int lane = threadIdx.x;
     const int64_t *rec = s.ev + 16 * (int64_t)ev;
     const int32_t v = (int32_t)rec[1];
     const int sN = (int)rec[4];
     const uint64_t kv = s.key[v];
     const int32_t b = m.rp[v];
     int64_t n = 0;
-    for (int q = 0; q < sN; ++q) {
-        const int32_t e0 = m.rev[b + s.ev_rep[16 * (int64_t)ev + q]];
+    if (lane < sN && lane < 16) {
+        int32_t *cq = ck + ((int64_t)ev * 16 + lane) * RCK;
+        const int32_t e0 = m.rev[b + s.ev_rep[16 * (int64_t)ev + lane]];
         int32_t e = e0;
-        int64_t guard = 0;
+        long long K = 1;
+        int nck = 0;
         do {
-            if (out) {
-                out[3 * n] = ldg(m.src + e);
-                out[3 * n + 1] = ldg(m.cyc + e);
-                out[3 * n + 2] = ldg(m.cyc + ldg(m.succ + e));
+            if ((n & (K - 1)) == 0) {
+                if (nck == RCK) {
+                    for (int c = 0; c < RCK / 2; ++c) cq[c] = cq[2 * c];
+                    nck = RCK / 2;
+                    K *= 2;
+                }
+                if ((n & (K - 1)) == 0) cq[nck++] = e;
             }
             n++;
             e = he_next(m, s.key, e, kv, v, false);
-        } while (e != e0 && ++guard <= m.nnz);
+        } while (e != e0 && n <= m.nnz);
+        int64_t *mq = meta + ((int64_t)ev * 16 + lane) * 4;
+        mq[0] = n;
+        mq[1] = K;
+        mq[2] = nck;
     }
-    return n;
+    // loop offsets: exclusive prefix of the lengths over the lanes
+    int64_t inc = n;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane < sN && lane < 16) meta[((int64_t)ev * 16 + lane) * 4 + 3] = inc - n;
+    if (lane == 63) cnt[ev] = 3 * inc;
 }
 
-__global__ void k_reeb_count(DMesh m, DState s, int n_events, int64_t *cnt) {
-    for (int ev = blockIdx.x * blockDim.x + threadIdx.x; ev < n_events; ev += gridDim.x * blockDim.x)
-        cnt[ev] = 3 * walk_event_loops(m, s, ev, nullptr);
-}
-
-// segment ev of buf spans [off[ev], off[ev+1]) (a power of two), its first
-// cnt[ev] entries are vertex ids, the rest is padding above every id
+// Fill pass: a workgroup per event; every (loop, checkpoint) segment is
+// re-walked by one thread, writing the three vertices of each front
+// triangle; then the segment's padding up to its power of two.  The order
+// of the entries does not matter (they are sorted before the mean).
 __global__ void k_reeb_fill(DMesh m, DState s, int n_events, const int64_t *off, const int64_t *cnt,
-                            int32_t *buf) {
-    for (int ev = blockIdx.x * blockDim.x + threadIdx.x; ev < n_events; ev += gridDim.x * blockDim.x) {
-        walk_event_loops(m, s, ev, buf + off[ev]);
-        for (int64_t i = off[ev] + cnt[ev]; i < off[ev + 1]; ++i) buf[i] = 0x7fffffff;
+                            const int32_t *ck, const int64_t *meta, int32_t *buf) {
+    const int ev = blockIdx.x;
+    if (ev >= n_events) return;
+    const int64_t *rec = s.ev + 16 * (int64_t)ev;
+    const int32_t v = (int32_t)rec[1];
+    const int sN = (int)rec[4] < 16 ? (int)rec[4] : 16;
+    const uint64_t kv = s.key[v];
+    int32_t *out = buf + off[ev];
+    for (int sg = threadIdx.x; sg < sN * RCK; sg += blockDim.x) {
+        const int q = sg / RCK, c = sg % RCK;
+        const int64_t *mq = meta + ((int64_t)ev * 16 + q) * 4;
+        if (c >= (int)mq[2]) continue;
+        const int64_t nq = mq[0], Kq = mq[1], base = mq[3];
+        int32_t e = ck[((int64_t)ev * 16 + q) * RCK + c];
+        const int64_t i0 = (int64_t)c * Kq;
+        const int64_t i1 = i0 + Kq < nq ? i0 + Kq : nq;
+        for (int64_t i = i0; i < i1; ++i) {
+            const v4i r = *(const GLOBAL_AS v4i *)(m.hrec + 4 * (int64_t)e);
+            const int64_t o = 3 * (base + i);
+            out[o] = ldg(m.src + e);
+            out[o + 1] = r.w;
+            out[o + 2] = r.z;
+            const uint64_t ky = ldg(s.key + r.z);
+            e = rank_lt(ky, r.z, kv, v) ? r.y : r.x;
+        }
     }
+    for (int64_t i = off[ev] + cnt[ev] + threadIdx.x; i < off[ev + 1]; i += blockDim.x) buf[i] = 0x7fffffff;
 }
 
 template <typename K>
@@ -2204,17 +2248,17 @@ __global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const i
     }
 }
 
-hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt,
-                             hipStream_t st) {
+hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt, int32_t *ck,
+                             int64_t *meta, hipStream_t st) {
     if (n_events <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reeb_count, dim3((n_events + 63) / 64), dim3(64), 0, st, m, s, n_events, cnt);
+    hipLaunchKernelGGL(k_reeb_count, dim3(n_events), dim3(64), 0, st, m, s, n_events, cnt, ck, meta);
     return hipGetLastError();
 }
 hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int n_events, const int64_t *off,
-                            const int64_t *cnt, int32_t *buf, hipStream_t st) {
+                            const int64_t *cnt, const int32_t *ck, const int64_t *meta, int32_t *buf,
+                            hipStream_t st) {
     if (n_events <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reeb_fill, dim3((n_events + 63) / 64), dim3(64), 0, st, m, s, n_events, off,
-                       cnt, buf);
+    hipLaunchKernelGGL(k_reeb_fill, dim3(n_events), dim3(NT), 0, st, m, s, n_events, off, cnt, ck, meta, buf);
     return hipGetLastError();
 }
 hipError_t launch_reeb_mean(const DMesh &m, int n_events, const int64_t *off, const int64_t *cnt,
