@@ -92,6 +92,58 @@ def copy_calibration(nbytes=1 << 30):
     log(f"copy calibration: {nbytes} bytes read and written")
 
 
+def dense_alg_bytes(updates, degsum):
+    # per vertex of a dense step: read rho(v) 8 + write rho(v) 8 + two row
+    # offsets 8, plus 4 bytes per neighbour id (no update list)
+    return 24 * updates + 4 * degsum
+
+
+def dense_leg(ctx, workload, steps):
+    """The dense field step (every vertex each step) on a mesh whose working
+    set is far beyond the caches, run for a fixed number of diffusion steps
+    with the topology beside it, against the band-stepped default for the
+    same steps; HBM share from the algorithmic bytes of a dense step."""
+    import ctypes as C
+    import paper_2105_13168_amd as vls
+    t0 = time.time()
+    m, desc = make_workload(workload)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    log(f"dense leg: {workload} V={m.nv} ({time.time() - t0:.1f}s)")
+
+    def run(flags, k):
+        p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_DEFER_RESULTS | flags, max_steps=k)
+        h = C.c_void_p()
+        st = vls.vls_run(ctx.h, M.h, C.byref(p), C.byref(h))
+        if st not in (0, vls.VLS_E_STALLED) or not h:
+            raise vls.VLSError(st, ctx.last_error())
+        s = vls.vls_summary()
+        vls.vls_result_summary(h, C.byref(s))
+        vls.vls_result_destroy(h)
+        out = {f: getattr(s, f) for f, _ in vls.vls_summary._fields_}
+        assert out["steps"] == k, (out["steps"], k)
+        return out
+
+    run(vls.VLS_DENSE_FIELD, min(steps, 20))
+    d = run(vls.VLS_DENSE_FIELD, steps)
+    b = run(0, steps)
+    assert d["n_inside"] == b["n_inside"] and d["n_events"] == b["n_events"]
+    ab = dense_alg_bytes(d["active_vertex_updates"], d["active_degree_sum"])
+    achieved = ab / (d["kernel_ms"] * 1e-3) / 1e9
+    res = {
+        "workload": desc, "nv": m.nv, "nf": m.nf, "diffusion_steps": steps,
+        "grid": d["grid"], "ms_per_dense_step": d["kernel_ms"] / steps,
+        "vertex_steps_per_s": m.nv * steps / (d["kernel_ms"] * 1e-3),
+        "algorithmic_bytes_per_step": ab / steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "kernel": "k_steps_dec (dense field)"},
+        "band_ms_per_step": b["kernel_ms"] / steps,
+        "band_updates_per_step": b["active_vertex_updates"] / steps,
+        "same_front": True,
+    }
+    M.close()
+    return res
+
+
 def batch_leg(ctx, n, seq_sample):
     """Batch of n uneven meshes in one launch (one workgroup per mesh)
     against the same meshes run one at a time (default launch) on a sample,
@@ -315,6 +367,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-lattice-share", type=float, default=0.05)
     ap.add_argument("--serve-slice-us", type=int, default=2000)
+    ap.add_argument("--dense-workload", default="lattice10_512",
+                    help="mesh of the dense-step leg ('none': skip)")
+    ap.add_argument("--dense-steps", type=int, default=400)
+    ap.add_argument("--dense", action="store_true", help="time the whole pass with the dense field step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -334,7 +390,8 @@ def main():
     log(f"mesh validated, adjacency built and uploaded ({time.time() - t1:.1f}s)")
 
     def one_pass():
-        p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_DEFER_RESULTS, grid=args.grid)
+        p = vls.default_params(seed_vertex=m.seed, grid=args.grid,
+                               flags=vls.VLS_DEFER_RESULTS | (vls.VLS_DENSE_FIELD if args.dense else 0))
         h = C.c_void_p()
         st = vls.vls_run(ctx.h, M.h, C.byref(p), C.byref(h))
         if st != 0:
@@ -407,6 +464,15 @@ def main():
                      "dense_equivalent_frac": value * dense_bytes / (HBM_PEAK_GBPS * 1e9),
                      "kernel_source_hash": kernel_source_hash()},
     }
+    if args.dense:
+        ab = dense_alg_bytes(upd, deg)
+        out["roofline"]["achieved"] = ab / (kernel_ms * 1e-3) / 1e9
+        out["roofline"]["frac"] = out["roofline"]["achieved"] / HBM_PEAK_GBPS
+        out["roofline"]["algorithmic_bytes"] = ab
+        out["roofline"]["traffic"] = None
+        out["config"]["field_step"] = "dense"
+    if args.dense_workload != "none" and args.dense_steps > 0:
+        out["dense_step"] = dense_leg(ctx, args.dense_workload, args.dense_steps)
     if args.batch > 0:
         out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample)
     if args.serve > 0:

@@ -20,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvls.so")
 
 VLS_OK = 0
+VLS_E_STALLED = -7
 VLS_E_BUFFER_TOO_SMALL = -10
 VLS_E_PENDING = -14
 VLS_E_CANCELLED = -15
@@ -29,6 +30,7 @@ VLS_TOPO_GLOBAL_PATH = 4
 VLS_COHERENT_SHARING = 8
 VLS_LOCKSTEP = 16
 VLS_BATCH_TWO_PER_CU = 32
+VLS_DENSE_FIELD = 64
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 

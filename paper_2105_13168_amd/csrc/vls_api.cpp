@@ -651,6 +651,7 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     dp.topo_global = (p->flags & VLS_TOPO_GLOBAL_PATH) ? 1 : 0;
     dp.coherent = (p->flags & VLS_COHERENT_SHARING) ? 1 : 0;
     dp.lockstep = (p->flags & VLS_LOCKSTEP) ? 1 : 0;
+    dp.dense = (p->flags & VLS_DENSE_FIELD) ? 1 : 0;
     HIPCHK(ctx, hipEventCreate(&rp.e0));
     HIPCHK(ctx, hipEventCreate(&rp.e1));
     HIPCHK(ctx, hipEventCreate(&rp.e2));
@@ -849,6 +850,7 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     // default launch: about one workgroup per 22k vertices (the field's share
     // of a step grows with the band; the topology workgroup does not), 16..128
     int grid = p->grid > 0 ? p->grid : (int)std::min<int64_t>(128, std::max<int64_t>(16, m->nv / 22000));
+    if (p->grid <= 0 && (p->flags & VLS_DENSE_FIELD)) grid = maxg;   // the dense step streams the whole mesh
     if (grid > maxg) grid = maxg;
     hipError_t le = launch_steps(m->d, rp.s, rp.dp, grid, block, ctx->stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le));

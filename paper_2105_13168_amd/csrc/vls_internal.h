@@ -138,7 +138,7 @@ struct DParams {
     int32_t topo_global;     // 1: always use the global-memory topology path
     int32_t coherent;        // 1: coherent atomic shared accesses, release-only barrier
     int32_t lockstep;        // 1: one grid barrier per step instead of the decoupled kernel
-    int32_t pad2;
+    int32_t dense;           // 1: the field step updates every vertex (no update list)
 };
 
 // host launchers (vls_kernels.hip)

@@ -35,6 +35,13 @@ namespace vls {
 #define WCK 64               // walk checkpoints per involved loop
 #define MAXBP 256            // rank-order breakpoints per event step kept in LDS
 #define GLOBAL_AS __attribute__((address_space(1)))   // global memory (avoids flat accesses)
+// Sub-phase clocks of the topology and event paths (diagnostics in the run
+// summary); each read waits for the scalar memory counter, so they can be
+// compiled out with -DVLS_DETAIL_CLOCKS=0.
+#ifndef VLS_DETAIL_CLOCKS
+#define VLS_DETAIL_CLOCKS 1
+#endif
+#define DCLK() (VLS_DETAIL_CLOCKS ? __builtin_amdgcn_s_memrealtime() : 0ull)
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 enum { NODE_SEED = 0, NODE_SPLIT = 1, NODE_MERGE = 2, NODE_VANISH = 3, NODE_DEGENERATE = 4 };
@@ -473,7 +480,9 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
             stx<CM>(rout + vk, x);
             upd += 1;
             degsum += dk;
-            cand[k] = x > p.tau && kv[k] == KEY_OUT;
+            // new crossers only: a vertex above tau at step t-1 and still
+            // outside was a candidate then and waits on the pending list
+            cand[k] = rk <= p.tau && x > p.tau && kv[k] == KEY_OUT;
         }
         (void)nbig;
         // appends: members of C_t and claimed vertices to the next list,
@@ -513,6 +522,112 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
         }
     }
     // wave reduction of the counters, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        upd += __shfl_down(upd, off);
+        degsum += __shfl_down(degsum, off);
+    }
+    if (lane == 0 && upd) {
+        atomicAdd((unsigned long long *)&ctl->active_updates, (unsigned long long)upd);
+        atomicAdd((unsigned long long *)&ctl->active_deg, (unsigned long long)degsum);
+    }
+}
+
+// Dense field step t: every vertex, in id order (coalesced padded rows and
+// value writes), split into one contiguous range per field workgroup.  The
+// update list is not used; vertices the list would skip are exact fixed
+// points of the step, so the field is bit-identical to the list's.  Crossers
+// (value above tau, key hint outside) go to the candidate list as there.
+template <int CM>
+__device__ __forceinline__ void phase_field_dense(const DMesh &m, const DState &s, const DParams &p, int64_t t,
+                                                  int worker, int nworkers) {
+    Ctl *ctl = s.ctl;
+    const double *__restrict__ rin = ((t - 1) & 1) ? s.rho1 : s.rho0;
+    double *__restrict__ rout = (t & 1) ? s.rho1 : s.rho0;
+    int32_t *__restrict__ cl = s.cand[t & 1];
+    int *clc = &ctl->cnt_cand[t & 3];
+    const int lane = __lane_id();
+    const int64_t nv = m.nv;
+    const int64_t per = (nv + nworkers - 1) / nworkers;
+    const int64_t beg = (int64_t)worker * per;
+    const int64_t end = beg + per < nv ? beg + per : nv;
+    long long upd = 0, degsum = 0;
+    for (int64_t base = beg; base < end; base += 2 * NT) {
+        int32_t v[2], nb[2][GB];
+        double r[2], xs[2][GB];
+        bool big[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t i = base + k * NT + threadIdx.x;
+            v[k] = i < end ? (int32_t)i : -1;
+            big[k] = false;
+            if (v[k] >= 0) {
+                const GLOBAL_AS v4i *row = (const GLOBAL_AS v4i *)(m.ell + (int64_t)v[k] * GB);
+#pragma unroll
+                for (int q = 0; q < GB / 4; ++q) {
+                    const v4i w = row[q];
+                    nb[k][4 * q] = w.x; nb[k][4 * q + 1] = w.y; nb[k][4 * q + 2] = w.z; nb[k][4 * q + 3] = w.w;
+                }
+                r[k] = ldx<CM>(rin + v[k]);
+                big[k] = nb[k][0] < 0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (v[k] >= 0 && !big[k]) {
+#pragma unroll
+                for (int j = 0; j < GB; ++j) xs[k][j] = ldx<CM>(rin + nb[k][j]);
+            }
+        bool cand[2] = {false, false};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (v[k] < 0) continue;
+            const int32_t vk = v[k];
+            const double rk = r[k];
+            double sum;
+            int dk;
+            if (!big[k]) {
+                dk = 0;
+#pragma unroll
+                for (int j = 0; j < GB; ++j) dk += nb[k][j] != vk;
+                sum = xs[k][0];
+#pragma unroll
+                for (int j = 1; j < GB; ++j)
+                    if (j < dk) sum = sum + xs[k][j];
+            } else {
+                const int32_t b = ldg(m.rp + vk), e = ldg(m.rp + vk + 1);
+                dk = e - b;
+                sum = ldx<CM>(rin + m.adj[b]);
+                for (int32_t j = b + 1; j < e; ++j) sum = sum + ldx<CM>(rin + m.adj[j]);
+            }
+            const double lap = sum - (double)dk * rk;
+            const double dd = (p.a * lap + p.w * (2.0 * rk - 1.0)) + p.e * sqrt(rk * (1.0 - rk));
+            double x = rk + p.c * dd;
+            if (x < 0.0) x = 0.0;
+            if (x > 1.0) x = 1.0;
+            stx<CM>(rout + vk, x);
+            upd += 1;
+            degsum += dk;
+            // new crossers only (see the list step); their key is read then
+            cand[k] = rk <= p.tau && x > p.tau && ldx<CM>(s.key + vk) == KEY_OUT;
+        }
+        const int nc = (int)cand[0] + (int)cand[1];
+        int inc = nc;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int y = __shfl_up(inc, off);
+            if (lane >= off) inc += y;
+        }
+        const int tot = __shfl(inc, WAVE - 1);
+        if (tot) {
+            int cb = 0;
+            if (lane == WAVE - 1) cb = atomicAdd(clc, tot);
+            cb = __shfl(cb, WAVE - 1);
+            int co = cb + inc - nc;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (cand[k]) stx<CM>(cl + co++, v[k]);
+        }
+    }
     for (int off = 32; off > 0; off >>= 1) {
         upd += __shfl_down(upd, off);
         degsum += __shfl_down(degsum, off);
@@ -653,7 +768,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
                               int32_t v, KSh *sh, const double *rho) {
     Ctl *ctl = s.ctl;
     const int lane = __lane_id();
-    if (lane == 0) ctl->clk_ev0 = __builtin_amdgcn_s_memrealtime();
+    if (lane == 0) ctl->clk_ev0 = DCLK();
     const int32_t b = m.rp[v];
     const int d = m.rp[v + 1] - b;
     const uint64_t kv = s.key[v];
@@ -731,7 +846,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
     __threadfence_block();
     // ---- merge: the involved loops before v joins (handle loops) ----------
     int keep_loop0 = 0;
-    const unsigned long long q0 = __builtin_amdgcn_s_memrealtime();
+    const unsigned long long q0 = DCLK();
     if (!full && sN >= 2) {
         if (sN > MAXDEG / 2) { if (lane == 0) fail(s, ST_CAPACITY, 3); return; }
         long long n = 0, best = LLONG_MAX, bestidx = 0;
@@ -830,7 +945,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
             __threadfence_block();
         }
     }
-    const unsigned long long q1 = __builtin_amdgcn_s_memrealtime();
+    const unsigned long long q1 = DCLK();
     unsigned long long q2 = q1, q3 = q1;
     // ---- the loops after v joins: walkers from the end of each new arc ----
     int mN = 0;
@@ -890,7 +1005,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
             sh->lpk[lane] = K;
             sh->lpnck[lane] = nck;
         }
-        q2 = __builtin_amdgcn_s_memrealtime();
+        q2 = DCLK();
         __builtin_amdgcn_wave_barrier();
         __threadfence_block();
         if (__shfl(ld_relaxed(&ctl->status), 0) != 0) return;
@@ -966,7 +1081,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
         if (mN < 0) return;
         const int big = __shfl(sh->maxround, 0);
         // tags of the new arcs, and relabel of every loop but the big one
-        q3 = __builtin_amdgcn_s_memrealtime();
+        q3 = DCLK();
         if (lane < d && !low) s.lid[b + lane] = sh->newtag[sh->cyc_of[sh->runid[lane]]];
         // the arcs walked to completion: edges 1 .. steps-1 of each walk,
         // replayed in K-step segments from its checkpoints, one lane each
@@ -991,7 +1106,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
     }
     // ---- bookkeeping: h, x, node, records ----------------------------------
     if (lane == 0) {
-        const unsigned long long q4 = __builtin_amdgcn_s_memrealtime();
+        const unsigned long long q4 = DCLK();
         ctl->clk_evp[0] += q1 - q0;          // merge walks and loop output
         ctl->clk_evp[1] += q2 - q1;          // split walkers
         ctl->clk_evp[2] += q4 - q3;          // relabel walks
@@ -1349,7 +1464,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
     const int tid = threadIdx.x;
     const uint64_t tk = (uint64_t)t << 32;
-    const unsigned long long k0 = __builtin_amdgcn_s_memrealtime();
+    const unsigned long long k0 = DCLK();
     unsigned long long k1 = k0, k2 = k0, k3 = k0;
     for (int i = tid; i < HCAP; i += NT) kl->hk[i] = -1;
     if (tid == 0) { sh->nL = 0; sh->nN = 0; sh->nnew = 0; sh->event = 0; sh->npend = 0; }
@@ -1378,7 +1493,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     }
     __syncthreads();
     const int nL = sh->nL;
-    k1 = __builtin_amdgcn_s_memrealtime();
+    k1 = DCLK();
     if (nL == 0) {
         if (tid == 0) ctl->clk_t[0] += k1 - k0;
         return;
@@ -1426,7 +1541,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     int nrounds = sh->nN ? 1 : 0;
     // later rounds (rare): touch the previous round, found through the hash
     if (sh->nN && sh->nN < nL) {
-        const unsigned long long kr = __builtin_amdgcn_s_memrealtime();
+        const unsigned long long kr = DCLK();
         for (int round = 1;; ++round) {
             for (int i = tid; i < nL; i += NT) {
                 int flag = 0;
@@ -1464,12 +1579,12 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
             if (sh->nN == nL) break;
         }
         if (tid == 0) {
-            ctl->clk_rounds += __builtin_amdgcn_s_memrealtime() - kr;
+            ctl->clk_rounds += DCLK() - kr;
             ctl->n_round_steps += 1;
         }
     }
     __syncthreads();
-    k2 = __builtin_amdgcn_s_memrealtime();
+    k2 = DCLK();
     // 3. lower-link classification: a neighbour is lower if it was inside
     //    before step t, or joined in this step with a smaller (round, id)
     for (int i = tid; i < nL; i += NT) {
@@ -1536,7 +1651,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         if (nlow == 0 || d > MAXDEG) atomicOr(&sh->event, 2);
     }
     __syncthreads();
-    k3 = __builtin_amdgcn_s_memrealtime();
+    k3 = DCLK();
     if (sh->event & 2) {
         if (tid == 0) fail(s, ST_INVARIANT, 12);
     } else if (!sh->event) {
@@ -1663,7 +1778,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         }
         if (tid == 0) {
             ctl->event_steps += 1;
-            ctl->clk_ev += __builtin_amdgcn_s_memrealtime() - k3;
+            ctl->clk_ev += DCLK() - k3;
         }
     }
     // 5. crossers not connected this step wait for the next
@@ -1671,7 +1786,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         if (kl->Lr[i] < 0) s.pend[t & 1][atomicAdd(&sh->npend, 1)] = kl->Lv[i];
     __syncthreads();
     if (tid == 0) {
-        const unsigned long long k4 = __builtin_amdgcn_s_memrealtime();
+        const unsigned long long k4 = DCLK();
         ctl->clk_t[0] += k1 - k0;
         ctl->clk_t[1] += k2 - k1;
         ctl->clk_t[2] += k3 - k2;
@@ -1737,10 +1852,12 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->stop[j & 1] = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (G == 1) {
                 __syncthreads();
-                phase_field<CM>(m, s, p, j + 1, 0, 1);
+                if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, 0, 1);
+                else phase_field<CM>(m, s, p, j + 1, 0, 1);
             }
         } else {
-            phase_field<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
+            if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
+            else phase_field<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
         }
         // field snapshots of step j (its buffer is not written in this iteration)
         for (int q = 0; q < s.n_ckpt; ++q) {
@@ -1861,10 +1978,10 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
                 go = 0;
             } else {
                 // field step t-1 complete on every field workgroup
-                const unsigned long long cb = __builtin_amdgcn_s_memrealtime();
+                const unsigned long long cb = DCLK();
                 ok = spin_ge(&ctl->fbar, (unsigned long long)(t - 1 - j0) * W, s);
                 __threadfence();
-                c_bar += __builtin_amdgcn_s_memrealtime() - cb;
+                c_bar += DCLK() - cb;
                 go = ok;
             }
             if (go && worker == 0) {
@@ -1875,7 +1992,8 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         __syncthreads();
         const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
         if (!go) break;
-        phase_field<CM, FK>(m, s, p, t, worker, (int)W);
+        if (p.dense) phase_field_dense<CM>(m, s, p, t, worker, (int)W);
+        else phase_field<CM, FK>(m, s, p, t, worker, (int)W);
         // field snapshot of step t-1 (its buffer is not written by step t)
         for (int q = 0; q < s.n_ckpt; ++q) {
             if (s.ckpt_steps[q] != t - 1 || t == 1) continue;
@@ -2028,7 +2146,8 @@ __global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState
                 const int stop = ctl->done;
                 __syncthreads();
                 if (stop) break;
-                phase_field<0, FKB>(m, s, p, j + 1, 0, 1);
+                if (p.dense) phase_field_dense<0>(m, s, p, j + 1, 0, 1);
+                else phase_field<0, FKB>(m, s, p, j + 1, 0, 1);
                 for (int q = 0; q < s.n_ckpt; ++q) {
                     if (s.ckpt_steps[q] != j || j == 0) continue;
                     const double *src = (j & 1) ? s.rho1 : s.rho0;

@@ -59,21 +59,28 @@ def test_batch_repeat_is_deterministic():
     ctx.close()
 
 
+_GANG_ORACLE = {}
+
+
+@pytest.mark.parametrize("dense", [False, True])
 @pytest.mark.parametrize("two_per_cu", [False, True])
 @pytest.mark.parametrize("pool", [0, 6])
-def test_batch_gangs_match_oracle(oracle_mod, pool, two_per_cu):
+def test_batch_gangs_match_oracle(oracle_mod, pool, two_per_cu, dense):
     """Meshes of >= 2^17 vertices get gangs of workgroups (one topology
     workgroup, the rest field) inside the batched launch; with a pool of 6
-    the gangs are scaled down to fit.  Results equal the oracle's."""
+    the gangs are scaled down to fit.  Results equal the oracle's, with the
+    band-limited and with the dense field step."""
     import paper_2105_13168_amd as vls
     ctx = vls.Context(0)
     ms = [mg.pretzel(96, rng_seed=2), mg.lattice(3, 96, rng_seed=3), mg.pretzel(72, rng_seed=1),
           mg.torus_grid(rng_seed=4), mg.multi_torus(2, 28, rng_seed=5)]
     M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
-    res = vls.batch_run(ctx, M, [m.seed for m in ms], grid=pool,
-                        flags=vls.VLS_BATCH_TWO_PER_CU if two_per_cu else 0)
+    flags = (vls.VLS_BATCH_TWO_PER_CU if two_per_cu else 0) | (vls.VLS_DENSE_FIELD if dense else 0)
+    res = vls.batch_run(ctx, M, [m.seed for m in ms], grid=pool, flags=flags)
     for m, g in zip(ms, res):
-        o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
+        if m.name not in _GANG_ORACLE:
+            _GANG_ORACLE[m.name] = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
+        o = _GANG_ORACLE[m.name]
         bad = compare(g, o, m.nv)
         assert not bad, (m.name, bad)
     for x in M:

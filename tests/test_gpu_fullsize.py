@@ -3,7 +3,8 @@ times (default grid of vls_run).
 
 * 256^3 pretzel (V = 2,188,952): every output's digest equals the oracle's
   (recorded by tests/golden/make_golden.py from the oracle alone), and the
-  sampled per-vertex values match one by one.
+  sampled per-vertex values match one by one; with the band-limited field
+  step (the default) and with the dense one.
 * 10^3-cell strut lattice on a 256^3 grid (V = 5,845,474, genus 2300): the
   oracle is not run at this size; properties that hold at any size are
   checked: every vertex inside, handle loops = tunnel loops = swept genus =
@@ -22,15 +23,17 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_pretzel256_digests_match_oracle():
+@pytest.mark.parametrize("field_step", ["band", "dense"])
+def test_pretzel256_digests_match_oracle(field_step):
     import paper_2105_13168_amd as vls
+    flags = vls.VLS_DENSE_FIELD if field_step == "dense" else 0
     gold = json.load(open(os.path.join(HERE, "golden", "oracle_full.json")))["pretzel256_s0"]
     m = mg.pretzel(256, rng_seed=0)
     assert m.nv == gold["nv"] and m.seed == gold["seed_vertex"]
     ctx = vls.Context(0)
     M = vls.Mesh(ctx, m.xyz, m.tri)
     try:
-        g = M.run(seed_vertex=m.seed)
+        g = M.run(seed_vertex=m.seed, flags=flags)
         d = digests(canon_gpu(g))
     finally:
         M.close()

@@ -90,19 +90,23 @@ def test_parity_coherent_sharing_variant(ctx, oracle_mod, name, make, ck):
     assert not bad, bad
 
 
-@pytest.mark.parametrize("flags", ["lockstep", "lockstep+coherent", "coherent"])
+@pytest.mark.parametrize("flags", ["lockstep", "lockstep+coherent", "coherent", "dense", "lockstep+dense",
+                                   "dense+coherent"])
 @pytest.mark.parametrize("name,make,ck", [SMALL[0], SMALL[6]], ids=["torus", "pretzel48"])
 def test_parity_step_kernel_variants(ctx, oracle_mod, name, make, ck, flags):
     """The lockstep step kernel (one grid barrier per step, topology of step
     t beside the field of step t+1) and the decoupled default (the field
     runs ahead up to two steps, the topology follows each completed field
-    step) give the same results, with either sharing mode."""
+    step) give the same results, with either sharing mode, and so does the
+    dense field step (every vertex each step instead of the update set)."""
     import paper_2105_13168_amd as vls
     f = 0
     if "lockstep" in flags:
         f |= vls.VLS_LOCKSTEP
     if "coherent" in flags:
         f |= vls.VLS_COHERENT_SHARING
+    if "dense" in flags:
+        f |= vls.VLS_DENSE_FIELD
     m = make()
     g, o = _run_both(ctx, oracle_mod, m, ck, flags=f)
     bad = compare(g, o, m.nv)
