@@ -75,9 +75,10 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
                                     full agent-scope fences; identical results, for testing */
 #define VLS_LOCKSTEP 16u         /* one grid barrier per step (topology of t beside field of t+1)
                                     instead of the decoupled kernel; identical results, for testing */
-#define VLS_DENSE_FIELD 64u      /* vls_run: the field step updates every vertex in id order instead of the
-                                    update list (streams the whole mesh each step; the default grid is
-                                    then every co-resident workgroup); identical results */
+#define VLS_DENSE_FIELD 64u      /* the field step updates every vertex in id order instead of the
+                                    update list (streams the whole mesh each step; vls_run's default
+                                    grid is then every co-resident workgroup); identical results;
+                                    meshes below 2^29 vertices (else VLS_E_INVALID_ARG) */
 #define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]): two workgroups per CU, each
                                     with a 1024-candidate LDS topology path and one list entry per
                                     field thread (the server always runs this way); default: one per

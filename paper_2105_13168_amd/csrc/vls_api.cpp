@@ -336,7 +336,9 @@ template <typename T>
 vls_status upload(vls_mesh *m, const std::vector<T> &h, const T **out) {
     void *p = nullptr;
     const size_t bytes = h.size() * sizeof(T);
-    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) return set_err(m->ctx, VLS_E_OUT_OF_MEMORY, "hipMalloc %zu bytes", bytes);
+    // 16 bytes of tail padding: aligned 16-byte loads of a row array's last
+    // partial chunk stay inside the allocation
+    if (hipMalloc(&p, bytes + 16) != hipSuccess) return set_err(m->ctx, VLS_E_OUT_OF_MEMORY, "hipMalloc %zu bytes", bytes);
     m->allocs.push_back(p);
     if (bytes && hipMemcpyAsync(p, h.data(), bytes, hipMemcpyHostToDevice, m->ctx->stream) != hipSuccess)
         return set_err(m->ctx, VLS_E_DEVICE, "upload failed");
@@ -362,7 +364,9 @@ struct RunBuffers {
 template <typename T>
 static hipError_t dalloc(RunBuffers *rb, T **p, size_t n) {
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T));
+    // 64 bytes of tail padding: aligned vector loads of a buffer's last
+    // partial chunk stay inside the allocation
+    hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T) + 64);
     if (e == hipSuccess) rb->allocs.push_back(q);
     *p = (T *)q;
     return e;
@@ -608,6 +612,8 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     if (p->max_steps < 1 || p->max_steps >= INT32_MAX) return set_err(ctx, VLS_E_INVALID_ARG, "max_steps");
     if (p->stall_steps < 1) return set_err(ctx, VLS_E_INVALID_ARG, "stall_steps");
     if (p->block != 0 && p->block != 256) return set_err(ctx, VLS_E_INVALID_ARG, "block must be 256");
+    if ((p->flags & VLS_DENSE_FIELD) && nv >= (int64_t)1 << 29)
+        return set_err(ctx, VLS_E_INVALID_ARG, "VLS_DENSE_FIELD needs fewer than 2^29 vertices");
     rp.m = m;
     rp.seed = seed;
     rp.rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;

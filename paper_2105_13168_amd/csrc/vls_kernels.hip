@@ -151,6 +151,12 @@ __global__ void k_init(DState s, int32_t nv, int64_t nnz) {
             s.mark[1][i] = 0;
             s.cstamp[i] = -1;
         }
+        // +0.0 at index nv of both field buffers (inside their tail
+        // padding): the dense step's padding slots gather it
+        if (i == nv) {
+            s.rho0[i] = 0.0;
+            s.rho1[i] = 0.0;
+        }
     }
 }
 
@@ -532,100 +538,282 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
     }
 }
 
-// Dense field step t: every vertex, in id order (coalesced padded rows and
-// value writes), split into one contiguous range per field workgroup.  The
-// update list is not used; vertices the list would skip are exact fixed
-// points of the step, so the field is bit-identical to the list's.  Crossers
-// (value above tau, key hint outside) go to the candidate list as there.
+// Dense field step t: every vertex each step.  The update set is not used;
+// the vertices it would skip are exact fixed points of the step, so the
+// field is bit-identical to the update-set step's.  Crossers (value above
+// tau for the first time, key hint outside) go to the candidate list as
+// there.
+//
+// The step is a stream over the compressed rows: per vertex its value (8 B
+// read, 8 B written), its row offset (4 B) and its neighbour ids (4 B
+// each), plus gathers of neighbour values that mostly hit the caches.  Work
+// is cut into tiles of DT consecutive vertices, four consecutive vertices
+// per lane, so a lane's ids are one contiguous run of the row array.  Tile
+// q belongs to wave q mod (all field waves): at any moment the waves work
+// on one window of ids and the gathers hit L2.  A wave stages its tile's id
+// segment in its own LDS slice.  Per tile it issues the gathers first and
+// then the loads of the next tile (its id segment in 16-byte chunks, its
+// values, and the row offsets of the tile after it); memory counters
+// retire in order, so consuming the gathers leaves the next tile's loads
+// in flight under this tile's arithmetic.  Every streamed load is issued
+// unconditionally at a clamped in-bounds address (the mesh and field
+// buffers carry tail padding), so no loaded register outlives its tile.
+#define DT 256                 // vertices per wave tile (4 per lane)
+#define DACAP 2048             // ids of one tile that fit the wave's LDS slice
+#define DSL (DACAP + 16)       // slice length: reads up to DW - 1 past a segment stay inside
+#define DCH (DACAP / 4 / WAVE) // 16-byte id chunks per lane
+#define LDS_AS __attribute__((address_space(3)))
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+struct DRows {
+    int32_t r[5];    // row offsets of the lane's vertices 4 lane + 0..4 (nnz past nv)
+};
+
+// row offsets of the tile at base, as loaded (read-only mesh data; the row
+// array has 16 bytes of tail padding, so a 16-byte load at an index <= nv
+// stays inside); dense_rows_fix clamps them once they have arrived
+__device__ __forceinline__ void dense_load_rp(const DMesh &m, int64_t base, int lane, DRows &t) {
+    const int64_t nv = m.nv;
+    const GLOBAL_AS int32_t *rp = (const GLOBAL_AS int32_t *)m.rp;
+    const int64_t i0 = base + 4 * lane;
+    const int64_t ic = i0 <= nv ? i0 : (nv & ~3ll);
+    const v4i w = *(const GLOBAL_AS v4i *)(rp + ic);
+    t.r[0] = w.x; t.r[1] = w.y; t.r[2] = w.z; t.r[3] = w.w;
+    t.r[4] = rp[ic + 4 <= nv ? ic + 4 : nv];
+}
+__device__ __forceinline__ void dense_rows_fix(const DMesh &m, int64_t base, int lane, DRows &t) {
+    const int64_t nv = m.nv;
+    const int64_t i0 = base + 4 * lane;
+    const int32_t nnz = (int32_t)m.nnz;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) t.r[k] = i0 + k <= nv ? t.r[k] : nnz;
+}
+
+// own values of the lane's four vertices (field buffers have 64 bytes of
+// tail padding; values past nv are not used); coherent loads one by one
+// when the field is shared that way
+template <int CM>
+__device__ __forceinline__ void dense_load_own(const double *rin, int64_t base, int64_t nv, int lane, dbl2 (&x)[2]) {
+    int64_t i0 = base + 4 * lane;
+    i0 = i0 < nv ? i0 : 0;
+    if constexpr (CM == 0) {
+        x[0] = *(const GLOBAL_AS dbl2 *)(rin + i0);
+        x[1] = *(const GLOBAL_AS dbl2 *)(rin + i0 + 2);
+    } else {
+        x[0].x = ldx<CM>(rin + i0);
+        x[0].y = ldx<CM>(rin + i0 + 1);
+        x[1].x = ldx<CM>(rin + i0 + 2);
+        x[1].y = ldx<CM>(rin + i0 + 3);
+    }
+}
+
+// id chunks of a segment [lo, hi) (lo < hi <= lo + DACAP - 3): chunk c
+// covers ids from (lo & ~3) + 4c; chunks past the segment reload its last
+// one
+__device__ __forceinline__ void dense_load_ids(const DMesh &m, int32_t lo, int32_t hi, int lane, v4i (&a)[DCH]) {
+    const int32_t a0 = lo & ~3;
+    const int n4 = (hi - a0 + 3) >> 2;
+    const GLOBAL_AS v4i *src = (const GLOBAL_AS v4i *)(m.adj + a0);
+#pragma unroll
+    for (int j = 0; j < DCH; ++j) {
+        const int c = lane + WAVE * j;
+        a[j] = src[c < n4 ? c : n4 - 1];
+    }
+}
+
+// field value at a vertex id through a 32-bit byte offset from the buffer
+// (scalar base + vector offset addressing; the dense step requires
+// nv < 2^29)
+template <int CM> __device__ __forceinline__ double ld_field(const double *base, int32_t i) {
+    const GLOBAL_AS double *a = (const GLOBAL_AS double *)((const GLOBAL_AS char *)base + ((uint32_t)i << 3));
+    if constexpr (CM) return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *a;
+}
+
+__device__ __forceinline__ void dense_store_ids(LDS_AS int32_t *ids, int lane, const v4i (&a)[DCH]) {
+#pragma unroll
+    for (int j = 0; j < DCH; ++j) *(LDS_AS v4i *)(ids + 4 * (lane + WAVE * j)) = a[j];
+}
+
+// One tile of the dense step with its ids from the wave's LDS slice
+// (IDS_LDS) or from the row array (a segment too long for the slice).
+// Straight-line code: each of the lane's four vertices gathers DW slots,
+// issued unconditionally, and sums them in slot (ascending id) order; slots
+// past its degree gather the +0.0 kept at index nv of the field buffers,
+// which leaves a sum of non-negative values unchanged.  Degrees above DW (none on
+// marching-tetrahedra surfaces, whose degrees are 4..9) add their further
+// neighbours one by one.  Between the gathers and their use it issues the
+// next tile's loads.
+#define DW 9
+struct DCoef {
+    double a, w, e, c, tau;
+};
+template <int CM, bool IDS_LDS>
+__device__ __forceinline__ void dense_tile(const DMesh &m, const DState &s, const DCoef &cf, const double *rin,
+                                           double *rout, const LDS_AS int32_t *ids, const DRows &rc, int32_t a0,
+                                           const dbl2 (&own)[2], int64_t base, int lane, int32_t plo,
+                                           int32_t phi, int64_t pq, int64_t pqq, v4i (&ac)[DCH],
+                                           dbl2 (&ownn)[2], DRows &rnn, bool (&cand)[4], long long &upd,
+                                           long long &degsum) {
+    const int64_t nv = m.nv;
+    const GLOBAL_AS int32_t *adj = (const GLOBAL_AS int32_t *)m.adj;
+    const int64_t v0 = base + 4 * lane;
+    const int32_t zero_slot = (int32_t)nv;
+    int32_t u[4][DW];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int32_t dk = rc.r[k + 1] - rc.r[k];
+#pragma unroll
+        for (int j = 0; j < DW; ++j) {
+            int32_t w;
+            if constexpr (IDS_LDS) {
+                w = ids[rc.r[k] - a0 + j];
+            } else {
+                int64_t ix = (int64_t)rc.r[k] + j;
+                ix = ix < m.nnz ? ix : m.nnz - 1;
+                w = adj[ix];
+            }
+            u[k][j] = j < dk ? w : zero_slot;
+        }
+    }
+    double xs[4][DW];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < DW; ++j) xs[k][j] = ld_field<CM>(rin, u[k][j]);
+    __builtin_amdgcn_sched_barrier(0);
+    // the next tile's loads: ids of segment [plo, phi), values of tile pq,
+    // row offsets of tile pqq (in-bounds stand-ins when there is none)
+    dense_load_ids(m, plo, phi, lane, ac);
+    dense_load_own<CM>(rin, pq * DT, nv, lane, ownn);
+    dense_load_rp(m, pqq * DT, lane, rnn);
+    __builtin_amdgcn_sched_barrier(0);
+    const double xr[4] = {own[0].x, own[0].y, own[1].x, own[1].y};
+    double xo[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int32_t dk = rc.r[k + 1] - rc.r[k];
+        double sum = xs[k][0];
+#pragma unroll
+        for (int j = 1; j < DW; ++j) sum = sum + xs[k][j];
+        for (int32_t j = DW; j < dk; ++j) {
+            const int32_t w = IDS_LDS ? ids[rc.r[k] - a0 + j] : adj[rc.r[k] + j];
+            sum = sum + ldx<CM>(rin + w);
+        }
+        const double rk = xr[k];
+        const double lap = sum - (double)dk * rk;
+        const double dd = (cf.a * lap + cf.w * (2.0 * rk - 1.0)) + cf.e * sqrt(rk * (1.0 - rk));
+        double x = rk + cf.c * dd;
+        if (x < 0.0) x = 0.0;
+        if (x > 1.0) x = 1.0;
+        xo[k] = x;
+        cand[k] = v0 + k < nv && rk <= cf.tau && x > cf.tau;
+        if (v0 + k < nv) {
+            upd += 1;
+            degsum += dk;
+        }
+    }
+    if (CM == 0 && v0 + 4 <= nv) {
+        dbl2 a, b;
+        a.x = xo[0]; a.y = xo[1]; b.x = xo[2]; b.y = xo[3];
+        *(GLOBAL_AS dbl2 *)(rout + v0) = a;
+        *(GLOBAL_AS dbl2 *)(rout + v0 + 2) = b;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (v0 + k < nv) stx<CM>(rout + v0 + k, xo[k]);
+    }
+    // new crossers only: a vertex above tau at step t-1 and still outside
+    // was a candidate then and is pending; the key is read for crossers only
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (cand[k]) cand[k] = ldx<CM>(s.key + v0 + k) == KEY_OUT;
+}
+
 template <int CM>
 __device__ __forceinline__ void phase_field_dense(const DMesh &m, const DState &s, const DParams &p, int64_t t,
-                                                  int worker, int nworkers) {
+                                                  int worker, int nworkers, LDS_AS int32_t *lds_all) {
     Ctl *ctl = s.ctl;
     const double *__restrict__ rin = ((t - 1) & 1) ? s.rho1 : s.rho0;
     double *__restrict__ rout = (t & 1) ? s.rho1 : s.rho0;
     int32_t *__restrict__ cl = s.cand[t & 1];
     int *clc = &ctl->cnt_cand[t & 3];
     const int lane = __lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    LDS_AS int32_t *ids = lds_all + wv * DSL;
+    const DCoef cf = {p.a, p.w, p.e, p.c, p.tau};
     const int64_t nv = m.nv;
-    const int64_t per = (nv + nworkers - 1) / nworkers;
-    const int64_t beg = (int64_t)worker * per;
-    const int64_t end = beg + per < nv ? beg + per : nv;
+    const int64_t nw = (int64_t)nworkers * (NT / WAVE);
+    const int64_t ntiles = (nv + DT - 1) / DT;
     long long upd = 0, degsum = 0;
-    for (int64_t base = beg; base < end; base += 2 * NT) {
-        int32_t v[2], nb[2][GB];
-        double r[2], xs[2][GB];
-        bool big[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int64_t i = base + k * NT + threadIdx.x;
-            v[k] = i < end ? (int32_t)i : -1;
-            big[k] = false;
-            if (v[k] >= 0) {
-                const GLOBAL_AS v4i *row = (const GLOBAL_AS v4i *)(m.ell + (int64_t)v[k] * GB);
-#pragma unroll
-                for (int q = 0; q < GB / 4; ++q) {
-                    const v4i w = row[q];
-                    nb[k][4 * q] = w.x; nb[k][4 * q + 1] = w.y; nb[k][4 * q + 2] = w.z; nb[k][4 * q + 3] = w.w;
-                }
-                r[k] = ldx<CM>(rin + v[k]);
-                big[k] = nb[k][0] < 0;
+    int64_t q = (int64_t)worker * (NT / WAVE) + wv;
+    if (q < ntiles) {
+        // prologue: tile q staged, row offsets of tile q+nw loading
+        DRows rc, rn;
+        dbl2 own[2], ownn[2];
+        v4i ac[DCH];
+        dense_load_rp(m, q * DT, lane, rc);
+        dense_load_rp(m, (q + nw < ntiles ? q + nw : q) * DT, lane, rn);
+        dense_rows_fix(m, q * DT, lane, rc);
+        int32_t lo = __builtin_amdgcn_readfirstlane(rc.r[0]);
+        int32_t hi = __builtin_amdgcn_readlane(rc.r[4], WAVE - 1);
+        bool fits = hi - (lo & ~3) <= DACAP;
+        // a vertex has at least three neighbours, so [lo, lo + 1) is a
+        // valid stand-in segment
+        dense_load_ids(m, lo, fits ? hi : lo + 1, lane, ac);
+        dense_load_own<CM>(rin, q * DT, nv, lane, own);
+        if (fits) dense_store_ids(ids, lane, ac);
+        for (;;) {
+            const int64_t base = q * DT;
+            const int64_t qn = q + nw, qnn = qn + nw;
+            const bool hn = qn < ntiles, hnn = qnn < ntiles;
+            int32_t lon = lo, hin = lo + 1;
+            bool fitn = false;
+            if (hn) {
+                dense_rows_fix(m, qn * DT, lane, rn);
+                lon = __builtin_amdgcn_readfirstlane(rn.r[0]);
+                hin = __builtin_amdgcn_readlane(rn.r[4], WAVE - 1);
+                fitn = hin - (lon & ~3) <= DACAP;
             }
-        }
+            const int32_t plo = fitn ? lon : lo, phi = fitn ? hin : lo + 1;
+            const int64_t pq = hn ? qn : q, pqq = hnn ? qnn : q;
+            bool cand[4];
+            DRows rnn;
+            if (fits)
+                dense_tile<CM, true>(m, s, cf, rin, rout, ids, rc, lo & ~3, own, base, lane, plo, phi, pq, pqq, ac,
+                                     ownn, rnn, cand, upd, degsum);
+            else
+                dense_tile<CM, false>(m, s, cf, rin, rout, ids, rc, lo & ~3, own, base, lane, plo, phi, pq, pqq, ac,
+                                      ownn, rnn, cand, upd, degsum);
+            const int nc = (int)cand[0] + (int)cand[1] + (int)cand[2] + (int)cand[3];
+            int inc = nc;
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (v[k] >= 0 && !big[k]) {
-#pragma unroll
-                for (int j = 0; j < GB; ++j) xs[k][j] = ldx<CM>(rin + nb[k][j]);
+            for (int off = 1; off < WAVE; off <<= 1) {
+                const int y = __shfl_up(inc, off);
+                if (lane >= off) inc += y;
             }
-        bool cand[2] = {false, false};
+            const int tot = __builtin_amdgcn_readlane(inc, WAVE - 1);
+            if (tot) {
+                int cb = 0;
+                if (lane == WAVE - 1) cb = atomicAdd(clc, tot);
+                cb = __shfl(cb, WAVE - 1);
+                int co = cb + inc - nc;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            if (v[k] < 0) continue;
-            const int32_t vk = v[k];
-            const double rk = r[k];
-            double sum;
-            int dk;
-            if (!big[k]) {
-                dk = 0;
-#pragma unroll
-                for (int j = 0; j < GB; ++j) dk += nb[k][j] != vk;
-                sum = xs[k][0];
-#pragma unroll
-                for (int j = 1; j < GB; ++j)
-                    if (j < dk) sum = sum + xs[k][j];
-            } else {
-                const int32_t b = ldg(m.rp + vk), e = ldg(m.rp + vk + 1);
-                dk = e - b;
-                sum = ldx<CM>(rin + m.adj[b]);
-                for (int32_t j = b + 1; j < e; ++j) sum = sum + ldx<CM>(rin + m.adj[j]);
+                for (int k = 0; k < 4; ++k)
+                    if (cand[k]) stx<CM>(cl + co++, (int32_t)(base + 4 * lane + k));
             }
-            const double lap = sum - (double)dk * rk;
-            const double dd = (p.a * lap + p.w * (2.0 * rk - 1.0)) + p.e * sqrt(rk * (1.0 - rk));
-            double x = rk + p.c * dd;
-            if (x < 0.0) x = 0.0;
-            if (x > 1.0) x = 1.0;
-            stx<CM>(rout + vk, x);
-            upd += 1;
-            degsum += dk;
-            // new crossers only (see the list step); their key is read then
-            cand[k] = rk <= p.tau && x > p.tau && ldx<CM>(s.key + vk) == KEY_OUT;
-        }
-        const int nc = (int)cand[0] + (int)cand[1];
-        int inc = nc;
-#pragma unroll
-        for (int off = 1; off < WAVE; off <<= 1) {
-            const int y = __shfl_up(inc, off);
-            if (lane >= off) inc += y;
-        }
-        const int tot = __shfl(inc, WAVE - 1);
-        if (tot) {
-            int cb = 0;
-            if (lane == WAVE - 1) cb = atomicAdd(clc, tot);
-            cb = __shfl(cb, WAVE - 1);
-            int co = cb + inc - nc;
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (cand[k]) stx<CM>(cl + co++, v[k]);
+            if (!hn) break;
+            // the next tile's ids into the slice (every read of this tile's
+            // ids is above, in program order)
+            if (fitn) dense_store_ids(ids, lane, ac);
+            q = qn;
+            rc = rn;
+            rn = rnn;
+            lo = lon;
+            fits = fitn;
+            own[0] = ownn[0];
+            own[1] = ownn[1];
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -1402,6 +1590,12 @@ struct KL {
     int32_t hv[HCAP];       // hash: entry index
 };
 
+// the dense field step borrows the LDS of the topology's sort buffer and
+// tables (contiguous) for its wave slices
+static_assert(LCAP_BATCH * sizeof(uint64_t) + sizeof(KL<LCAP_BATCH>) >= (NT / WAVE) * DSL * sizeof(int32_t),
+              "dense field LDS slices");
+static_assert((DSL * sizeof(int32_t)) % 16 == 0, "dense slices stay 16-byte aligned");
+
 __host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
 template <int CAP>
@@ -1852,11 +2046,11 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->stop[j & 1] = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (G == 1) {
                 __syncthreads();
-                if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, 0, 1);
+                if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, 0, 1, (LDS_AS int32_t *)lsort);
                 else phase_field<CM>(m, s, p, j + 1, 0, 1);
             }
         } else {
-            if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
+            if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1, (LDS_AS int32_t *)lsort);
             else phase_field<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
         }
         // field snapshots of step j (its buffer is not written in this iteration)
@@ -1992,7 +2186,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         __syncthreads();
         const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
         if (!go) break;
-        if (p.dense) phase_field_dense<CM>(m, s, p, t, worker, (int)W);
+        if (p.dense) phase_field_dense<CM>(m, s, p, t, worker, (int)W, (LDS_AS int32_t *)lsort);
         else phase_field<CM, FK>(m, s, p, t, worker, (int)W);
         // field snapshot of step t-1 (its buffer is not written by step t)
         for (int q = 0; q < s.n_ckpt; ++q) {
@@ -2146,7 +2340,7 @@ __global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState
                 const int stop = ctl->done;
                 __syncthreads();
                 if (stop) break;
-                if (p.dense) phase_field_dense<0>(m, s, p, j + 1, 0, 1);
+                if (p.dense) phase_field_dense<0>(m, s, p, j + 1, 0, 1, (LDS_AS int32_t *)lsort);
                 else phase_field<0, FKB>(m, s, p, j + 1, 0, 1);
                 for (int q = 0; q < s.n_ckpt; ++q) {
                     if (s.ckpt_steps[q] != j || j == 0) continue;
