@@ -731,6 +731,20 @@ __device__ __forceinline__ void dense_tile(const DMesh &m, const DState &s, cons
         if (cand[k]) cand[k] = ldx<CM>(s.key + v0 + k) == KEY_OUT;
 }
 
+// Position of field workgroup `worker` (block worker + 1; block 0 runs the
+// topology) in XCD-major order.  Workgroups are dispatched to the NXCD
+// XCDs round-robin by block index, so in this order consecutive positions
+// share an XCD: the tiles of one round that an XCD works on are then one
+// contiguous range, and its L2 holds their neighbourhoods instead of every
+// XCD touching the whole round.  Any other dispatch only changes speed.
+#define NXCD 8
+__device__ __forceinline__ int dense_worker_pos(int worker, int nworkers) {
+    const int b = worker + 1, x = b % NXCD;
+    int pos = 0;
+    for (int y = 0; y < x; ++y) pos += y == 0 ? nworkers / NXCD : (y <= nworkers ? (nworkers - y) / NXCD + 1 : 0);
+    return pos + (x == 0 ? b / NXCD - 1 : (b - x) / NXCD);
+}
+
 template <int CM>
 __device__ __forceinline__ void phase_field_dense(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                                                   int worker, int nworkers, LDS_AS int32_t *lds_all) {
@@ -747,7 +761,7 @@ __device__ __forceinline__ void phase_field_dense(const DMesh &m, const DState &
     const int64_t nw = (int64_t)nworkers * (NT / WAVE);
     const int64_t ntiles = (nv + DT - 1) / DT;
     long long upd = 0, degsum = 0;
-    int64_t q = (int64_t)worker * (NT / WAVE) + wv;
+    int64_t q = (int64_t)dense_worker_pos(worker, nworkers) * (NT / WAVE) + wv;
     if (q < ntiles) {
         // prologue: tile q staged, row offsets of tile q+nw loading
         DRows rc, rn;
