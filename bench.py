@@ -65,17 +65,20 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_ms, workload):
+def measured_traffic(kernel_ms, workload, steps=None):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     runs (FETCH_SIZE, WRITE_SIZE scaled by a copy of known size), as GB/s over
     the live kernel time; None when the counters were taken on another
-    workload or on other kernel sources."""
+    workload, another number of steps or other kernel sources.  `workload`
+    names the record (k_steps_<workload>_traffic.json)."""
     path = os.path.join(ROOT, "profiles", f"k_steps_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if steps is not None and t.get("diffusion_steps") != steps:
         return None
     return t["hbm_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9
 
@@ -135,7 +138,9 @@ def dense_leg(ctx, workload, steps):
         "vertex_steps_per_s": m.nv * steps / (d["kernel_ms"] * 1e-3),
         "algorithmic_bytes_per_step": ab / steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "kernel": "k_steps_dec (dense field)"},
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(d["kernel_ms"], f"dense_{workload}", steps),
+                     "kernel": "k_steps_dec (dense field)"},
         "band_ms_per_step": b["kernel_ms"] / steps,
         "band_updates_per_step": b["active_vertex_updates"] / steps,
         "same_front": True,
