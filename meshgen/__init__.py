@@ -20,6 +20,8 @@ synthetic surfaces of known genus stand in for them):
                          N(0,1e-4) jitter
 * ``sdf_surface``     -- any signed-distance function at any grid size
                          (small spheres, tori, multi-tori for tests)
+* ``uv_sphere``       -- latitude-longitude sphere whose poles have high
+                         degree (tests of wide vertices)
 """
 from __future__ import annotations
 
@@ -31,7 +33,7 @@ import numpy as np
 __all__ = [
     "Mesh", "torus_grid", "marching_tets", "sdf_surface", "pretzel", "batch_workload",
     "sdf_sphere", "sdf_torus", "sdf_union_tori", "sdf_box", "jittered",
-    "pick_seed", "euler_characteristic", "pretzel_sdf", "multi_torus",
+    "pick_seed", "euler_characteristic", "pretzel_sdf", "multi_torus", "uv_sphere",
 ]
 
 
@@ -99,6 +101,42 @@ def torus_grid(n_major: int = 64, n_minor: int = 32, R: float = 1.0,
     xyz = xyz + rng.normal(0.0, jitter, size=xyz.shape)
     seed = int(rng.integers(xyz.shape[0]))
     return Mesh(xyz, tri, seed, f"torus{n_major}x{n_minor}")
+
+
+def uv_sphere(n_lat: int = 30, n_lon: int = 40, jitter: float = 1e-3, rng_seed: int = 0) -> Mesh:
+    """Latitude-longitude unit sphere: the north pole (id 0), n_lat rings of
+    n_lon vertices (ring r, column c -> id 1 + n_lon*r + c, colatitude
+    pi (r+1)/(n_lat+1), longitude 2 pi c/n_lon), the south pole (last id).
+    The poles have degree n_lon, the vertices of the two rings next to them
+    5, all others 6; genus 0.  One PRNG stream draws the N(0, jitter^2)
+    coordinate noise, then the seed."""
+    r = np.arange(n_lat)
+    c = np.arange(n_lon)
+    th = np.pi * (r + 1) / (n_lat + 1)
+    ph = 2.0 * np.pi * c / n_lon
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    ring = np.stack([(np.sin(TH) * np.cos(PH)).ravel(), (np.sin(TH) * np.sin(PH)).ravel(),
+                     np.cos(TH).ravel()], axis=1)
+    xyz = np.concatenate([[[0.0, 0.0, 1.0]], ring, [[0.0, 0.0, -1.0]]]).astype(np.float64)
+    S = 1 + n_lat * n_lon
+
+    def vid(rr, cc):
+        return 1 + n_lon * rr + (cc % n_lon)
+
+    tris = []
+    for cc in range(n_lon):
+        tris.append((0, vid(0, cc), vid(0, cc + 1)))
+        tris.append((S, vid(n_lat - 1, cc + 1), vid(n_lat - 1, cc)))
+    for rr in range(n_lat - 1):
+        for cc in range(n_lon):
+            a, b, e, d = vid(rr, cc), vid(rr + 1, cc), vid(rr + 1, cc + 1), vid(rr, cc + 1)
+            tris.append((a, b, e))
+            tris.append((a, e, d))
+    tri = np.array(tris, dtype=np.int32)
+    rng = np.random.default_rng(rng_seed)
+    xyz = xyz + rng.normal(0.0, jitter, size=xyz.shape)
+    seed = int(rng.integers(xyz.shape[0]))
+    return Mesh(xyz, tri, seed, f"uvsphere{n_lat}x{n_lon}")
 
 
 # ---------------------------------------------------------------------------

@@ -46,6 +46,9 @@ SMALL = [
     ("thin_strip400x6", lambda: mg.torus_grid(400, 6, R=10.0, r=0.2, jitter=1e-3, rng_seed=0), [1, 1000]),
     ("lattice2_40", lambda: mg.lattice(2, 40, rng_seed=1), [1, 700, 1500]),
     ("lattice3_48", lambda: mg.lattice(3, 48, rng_seed=0), [1, 1000, 2500]),
+    # poles of degree 40: wide padded rows, wide link rows, the event path at
+    # a large full link, and the one-tile-deep dense step
+    ("uvsphere30x40", lambda: mg.uv_sphere(30, 40, rng_seed=0), [1, 60]),
 ]
 
 
@@ -67,7 +70,8 @@ def test_parity_independent_of_launch_shape(ctx, oracle_mod, grid):
     assert not bad, bad
 
 
-@pytest.mark.parametrize("name,make,ck", SMALL[:1] + SMALL[5:7], ids=["torus", "double_torus", "pretzel48"])
+@pytest.mark.parametrize("name,make,ck", SMALL[:1] + SMALL[5:7] + SMALL[10:11],
+                         ids=["torus", "double_torus", "pretzel48", "uvsphere"])
 def test_parity_global_topology_path(ctx, oracle_mod, name, make, ck):
     """The global-memory topology path (taken by steps with more than 1024
     crossers) forced on every step gives the same results."""
@@ -92,7 +96,7 @@ def test_parity_coherent_sharing_variant(ctx, oracle_mod, name, make, ck):
 
 @pytest.mark.parametrize("flags", ["lockstep", "lockstep+coherent", "coherent", "dense", "lockstep+dense",
                                    "dense+coherent"])
-@pytest.mark.parametrize("name,make,ck", [SMALL[0], SMALL[6]], ids=["torus", "pretzel48"])
+@pytest.mark.parametrize("name,make,ck", [SMALL[0], SMALL[6], SMALL[10]], ids=["torus", "pretzel48", "uvsphere"])
 def test_parity_step_kernel_variants(ctx, oracle_mod, name, make, ck, flags):
     """The lockstep step kernel (one grid barrier per step, topology of step
     t beside the field of step t+1) and the decoupled default (the field

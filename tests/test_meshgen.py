@@ -37,3 +37,18 @@ def test_lattice_genus(n, grid):
 def test_lattice_genus_formula():
     # the config's 10^3-cell lattice: 3630 struts on 1331 nodes
     assert mg.lattice_genus(10) == 3630 - 1331 + 1 == 2300
+
+
+def test_uv_sphere_is_closed_outward_with_wide_poles():
+    m = mg.uv_sphere(30, 40, rng_seed=0)
+    assert mg.euler_characteristic(m.tri, m.nv) == 2
+    t = m.tri.astype(np.int64)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    k = e[:, 0] * m.nv + e[:, 1]
+    assert np.unique(k).size == k.size
+    assert np.array_equal(np.sort(k), np.sort(e[:, 1] * m.nv + e[:, 0]))
+    deg = np.bincount(e[:, 0], minlength=m.nv)
+    assert deg[0] == 40 and deg[-1] == 40 and set(deg[1:-1].tolist()) == {5, 6}
+    p = m.xyz[t]
+    n = np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0])
+    assert (np.einsum("ij,ij->i", n, p.mean(axis=1)) > 0).all()
