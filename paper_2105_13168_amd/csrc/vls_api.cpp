@@ -928,7 +928,7 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
     HIPCHK(ctx, hipEventRecord(b0, stream));
     hipError_t le = launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dpp, (const int32_t *)dord,
                                  (const int32_t *)dtg, (const int32_t *)dsl, bp.nslots, (int *)dnext, grid, lds, ~0ull,
-                                 nullptr, ++g_epoch, occ, stream);
+                                 nullptr, ++g_epoch, occ, (per_mesh[0].flags & VLS_COHERENT_SHARING) ? 1 : 0, stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "batch kernel launch: %s", hipGetErrorString(le));
     HIPCHK(ctx, hipEventRecord(b1, stream));
     HIPCHK(ctx, hipEventSynchronize(b1));
@@ -1159,6 +1159,7 @@ struct vls_server {
     size_t budget = 0;
     int max_slots = 0;
     int occ = 2;                     // workgroups per CU of the step launches
+    int cm = 0;                      // 1: gangs share through coherent atomics
     int64_t gang_verts = 0;          // vertices per gang workgroup (0 = default)
     unsigned long long slice_ticks = 0;
     std::mutex mu;
@@ -1275,7 +1276,7 @@ bool vls_server::launch_slice() {
         return false;
     if (launch_batch((const DMesh *)dm, (const DState *)ds, (const DParams *)dp, (const int32_t *)dord,
                      (const int32_t *)dtg, (const int32_t *)dsl, bp.nslots, (int *)dnext, bp.grid, lds, slice_ticks,
-                     (int32_t *)ddone, ++g_epoch, occ, st) != hipSuccess)
+                     (int32_t *)ddone, ++g_epoch, occ, cm, st) != hipSuccess)
         return false;
     hdone.assign(n, 0);
     if (hipMemcpyAsync(hdone.data(), ddone, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) ||

@@ -149,7 +149,7 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
 int max_coresident_blocks(int block, size_t lds_bytes);
 hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order,
                         const int32_t *task_g, const int32_t *slots, int nslots, int *next_slot, int grid, size_t lds,
-                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, int occ,
+                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, int occ, int cm,
                         hipStream_t st);
 int max_coresident_batch(size_t lds_bytes, int occ);
 size_t batch_lds_bytes(int occ);

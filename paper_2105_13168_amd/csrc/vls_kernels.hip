@@ -2120,6 +2120,22 @@ __device__ __forceinline__ bool spin_ge64(const long long *p, long long target, 
     return true;
 }
 
+// Hand-off fences between a gang's workgroups.  CM = 0: plain accesses to
+// shared data, so full agent-scope fences (release writes back the L2,
+// acquire invalidates it: the XCDs' L2s are not coherent with each other).
+// CM = 1: shared data moves through agent-scope atomics, so the release only
+// writes back the topology's plain stores and the acquire is an ordering
+// point; no L2 is invalidated, which keeps the caches of every other
+// workgroup on the XCD warm.
+template <int CM> __device__ __forceinline__ void hand_off_acquire() {
+    if constexpr (CM) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    else __threadfence();
+}
+template <int CM> __device__ __forceinline__ void hand_off_release() {
+    if constexpr (CM) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else __threadfence();
+}
+
 // One mesh advanced by a gang of G >= 2 co-resident workgroups: rank 0 runs
 // the topology, ranks 1..G-1 the field.  Entry state: iterations below j0
 // complete (topology j0-1 and field j0 done), fbar = 0, kdone <= j0-1,
@@ -2144,7 +2160,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
             const unsigned long long c0 = __builtin_amdgcn_s_memrealtime();
             if (threadIdx.x == 0) {
                 go = spin_ge(&ctl->fbar, (unsigned long long)(t - j0) * W, s) ? 1 : 0;
-                __threadfence();
+                hand_off_acquire<CM>();
             }
             __syncthreads();
             const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
@@ -2153,11 +2169,11 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
             if (threadIdx.x == 0) {
                 const int d = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || !go;
                 const int y = !d && __builtin_amdgcn_s_memrealtime() - v0 >= budget;
-                __threadfence();
+                hand_off_release<CM>();
                 if (d || y) {
                     // the stop step becomes visible before the jump of kdone
                     __hip_atomic_store(&ctl->stop_step, (long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __threadfence();
+                    hand_off_release<CM>();
                     __hip_atomic_store(&ctl->kdone, KDONE_STOP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     __hip_atomic_store(&ctl->kdone, (long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2180,7 +2196,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         if (threadIdx.x == 0) {
             // topology t-2 done (its field buffer and crosser list are free)
             int ok = spin_ge64(&ctl->kdone, t - 2, s);
-            __threadfence();
+            hand_off_acquire<CM>();
             const long long stop = __hip_atomic_load(&ctl->stop_step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!ok || stop <= t - 2) {
                 go = 0;
@@ -2188,7 +2204,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
                 // field step t-1 complete on every field workgroup
                 const unsigned long long cb = DCLK();
                 ok = spin_ge(&ctl->fbar, (unsigned long long)(t - 1 - j0) * W, s);
-                __threadfence();
+                hand_off_acquire<CM>();
                 c_bar += DCLK() - cb;
                 go = ok;
             }
@@ -2211,7 +2227,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();
+            hand_off_release<CM>();
             atomicAdd(&ctl->fbar, 1ull);
         }
         const unsigned long long c2 = __builtin_amdgcn_s_memrealtime();
@@ -2263,7 +2279,7 @@ __device__ __forceinline__ void zero_dead_counters(Ctl *ctl, int64_t j0) {
 // OCC workgroups per CU: OCC = 1 keeps the solo kernel's LDS topology path
 // (LCAP candidates) and two list entries per field thread; OCC = 2 halves
 // both (LCAP_BATCH, one entry) so that two workgroups overlap on each CU.
-template <int OCC>
+template <int OCC, int CM>
 __global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState *ss, const DParams *ps,
                                               const int32_t *order, const int32_t *task_g, const int32_t *slots,
                                               int nslots, int *next_slot, unsigned long long budget_ticks,
@@ -2314,7 +2330,7 @@ __global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState
                     }
                     __threadfence();
                     jstart = __hip_atomic_load(&ctl->gang_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch
-                                 ? (long long)ctl->vbase : -1;
+                                 ? __hip_atomic_load(&ctl->vbase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
                 }
             }
             __syncthreads();
@@ -2324,7 +2340,7 @@ __global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState
             } else if (rank != 0 && j0 < 0) {
                 // the visit never opened (error already recorded) or the mesh is done
             } else {
-                const int64_t nx = gang_advance<0, CAP, FKB>(m, s, p, rank, g, j0, budget_ticks, ksh, kl, lsort, go);
+                const int64_t nx = gang_advance<CM, CAP, FKB>(m, s, p, rank, g, j0, budget_ticks, ksh, kl, lsort, go);
                 if (rank == 0 && threadIdx.x == 0) {
                     ctl->biter = nx;
                     if (done_out) done_out[w] = ctl->done;
@@ -2375,16 +2391,24 @@ __global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState
 
 hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, const int32_t *order,
                         const int32_t *task_g, const int32_t *slots, int nslots, int *next_slot, int grid, size_t lds,
-                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, int occ, hipStream_t st) {
+                        unsigned long long budget_ticks, int32_t *done_out, unsigned int epoch, int occ, int cm,
+                        hipStream_t st) {
     void *args[] = {&ms, &ss, &ps, &order, &task_g, &slots, &nslots, &next_slot, &budget_ticks, &done_out, &epoch};
-    const void *fn = occ == 2 ? (const void *)k_batch<2> : (const void *)k_batch<1>;
+    const void *fn = occ == 2 ? (cm ? (const void *)k_batch<2, 1> : (const void *)k_batch<2, 0>)
+                              : (cm ? (const void *)k_batch<1, 1> : (const void *)k_batch<1, 0>);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, (unsigned)lds, st);
 }
 
 int max_coresident_batch(size_t lds_bytes, int occ) {
-    int per_cu = 0;
-    const void *fn = occ == 2 ? (const void *)k_batch<2> : (const void *)k_batch<1>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds_bytes) != hipSuccess) return 0;
+    // the smaller residency of the two sharing modes
+    int per_cu = 1 << 30;
+    const void *fns[2] = {occ == 2 ? (const void *)k_batch<2, 0> : (const void *)k_batch<1, 0>,
+                          occ == 2 ? (const void *)k_batch<2, 1> : (const void *)k_batch<1, 1>};
+    for (const void *fn : fns) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NT, lds_bytes) != hipSuccess) return 0;
+        per_cu = n < per_cu ? n : per_cu;
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     int cus = 0;

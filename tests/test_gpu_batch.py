@@ -88,6 +88,28 @@ def test_batch_gangs_match_oracle(oracle_mod, pool, two_per_cu, dense):
     ctx.close()
 
 
+@pytest.mark.parametrize("two_per_cu", [False, True])
+def test_batch_gangs_coherent_sharing_match_oracle(oracle_mod, two_per_cu):
+    """Gangs whose workgroups share the field through coherent atomics
+    (ordering-point fences instead of L2 invalidation at each hand-off)
+    give the oracle's results, next to one-workgroup meshes."""
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    ms = [mg.pretzel(96, rng_seed=2), mg.lattice(3, 96, rng_seed=3), mg.pretzel(72, rng_seed=1),
+          mg.torus_grid(rng_seed=4), mg.multi_torus(2, 28, rng_seed=5)]
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    flags = vls.VLS_COHERENT_SHARING | (vls.VLS_BATCH_TWO_PER_CU if two_per_cu else 0)
+    res = vls.batch_run(ctx, M, [m.seed for m in ms], flags=flags)
+    for m, g in zip(ms, res):
+        if m.name not in _GANG_ORACLE:
+            _GANG_ORACLE[m.name] = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
+        bad = compare(g, _GANG_ORACLE[m.name], m.nv)
+        assert not bad, (m.name, bad)
+    for x in M:
+        x.close()
+    ctx.close()
+
+
 def test_batch_schedule_changes_no_result():
     """Every schedule the tuner may pick (pool shape, vertices per gang
     workgroup) gives bit-identical results; the tuner returns one of them."""
