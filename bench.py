@@ -241,7 +241,7 @@ def batch_leg(ctx, n, seq_sample):
     }
 
 
-def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0):
+def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=False):
     """Serving: Poisson arrivals at ``rate``/s, each request an initial pass
     of a mesh drawn from the uneven batch distribution or, with probability
     ``lattice_share``, from two strut lattices of 2-8M triangles; meshes are
@@ -268,7 +268,8 @@ def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0):
     pick = np.where(rng.random(n_req) < lattice_share, len(pool) + rng.integers(0, len(lat), size=n_req),
                     rng.integers(0, len(pool), size=n_req))
     free, _total = torch.cuda.mem_get_info()
-    srv = vls.Server(ctx, hbm_budget_bytes=free // 2, max_slots=1024, slice_us=slice_us)
+    srv = vls.Server(ctx, hbm_budget_bytes=free // 2, max_slots=1024, slice_us=slice_us,
+                     flags=vls.VLS_BATCH_TWO_PER_CU if two_per_cu else 0)
     # warm-up request (first launch, allocations)
     t = srv.submit(M[0], seed_vertex=meshes[0].seed)
     while srv.poll(t) is None:
@@ -372,6 +373,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-lattice-share", type=float, default=0.05)
     ap.add_argument("--serve-slice-us", type=int, default=2000)
+    ap.add_argument("--serve-two-per-cu", action="store_true", help="server step launches at two workgroups per CU")
     ap.add_argument("--dense-workload", default="lattice10_512",
                     help="mesh of the dense-step leg ('none': skip)")
     ap.add_argument("--dense-steps", type=int, default=400)
@@ -482,7 +484,8 @@ def main():
         out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample)
     if args.serve > 0:
         out["serving"] = serve_leg(ctx, args.serve, args.serve_rate, args.serve_lattice_share,
-                                   args.serve_slice_us)
+                                   args.serve_slice_us, two_per_cu=args.serve_two_per_cu)
+        out["serving"]["workgroups_per_cu"] = 2 if args.serve_two_per_cu else 1
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:

@@ -264,7 +264,10 @@ vls_status vls_batch_run(struct vls_context *ctx, int32_t n, const struct vls_me
  *   requests (per request: the per-vertex and per-half-edge run arrays,
  *   event/loop buffers and checkpoints; the mesh itself is the caller's);
  *   max_slots caps how many run at once.  A request larger than the budget
- *   is admitted only when nothing else runs.
+ *   is admitted only when nothing else runs.  flags: VLS_BATCH_TWO_PER_CU
+ *   (two workgroups per CU in the step launches; default one) and
+ *   VLS_COHERENT_SHARING (gangs share through coherent atomics); any other
+ *   bit is VLS_E_INVALID_ARG.
  * vls_server_submit: queues an initial pass of mesh m with parameters p
  *   (copied, checkpoint list included); thread-safe; *ticket identifies it.
  *   The mesh must stay alive until the request is polled; one mesh may be
@@ -284,7 +287,7 @@ vls_status vls_batch_run(struct vls_context *ctx, int32_t n, const struct vls_me
  */
 struct vls_server;
 vls_status vls_server_create(struct vls_context *ctx, size_t hbm_budget_bytes, int32_t max_slots,
-                             int64_t slice_us, struct vls_server **out);
+                             int64_t slice_us, uint32_t flags, struct vls_server **out);
 vls_status vls_server_submit(struct vls_server *srv, const struct vls_mesh *m, const vls_params *p,
                              uint64_t *ticket);
 vls_status vls_server_poll(struct vls_server *srv, uint64_t ticket, struct vls_result **out);

@@ -99,7 +99,7 @@ _sig = {
     "vls_result_vertices": (C.c_int32, [_P, _P, _P, _P]),
     "vls_result_fetch": (C.c_int32, [_P]),
     "vls_result_destroy": (C.c_int32, [_P]),
-    "vls_server_create": (C.c_int32, [_P, C.c_size_t, C.c_int32, C.c_int64, _PP]),
+    "vls_server_create": (C.c_int32, [_P, C.c_size_t, C.c_int32, C.c_int64, C.c_uint32, _PP]),
     "vls_server_submit": (C.c_int32, [_P, _P, C.POINTER(vls_params), C.POINTER(C.c_uint64)]),
     "vls_server_poll": (C.c_int32, [_P, C.c_uint64, _PP]),
     "vls_server_stats": (C.c_int32, [_P, _I64P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -306,9 +306,10 @@ class Server:
     returns a ticket, poll() returns None while the request runs and its
     Result once done.  A mesh must stay open until its requests are polled."""
 
-    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 1024, slice_us: int = 2000):
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 1024, slice_us: int = 2000,
+                 flags: int = 0):
         h = C.c_void_p()
-        st = vls_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), int(slice_us), C.byref(h))
+        st = vls_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), int(slice_us), int(flags), C.byref(h))
         if st != VLS_OK:
             raise VLSError(st, ctx.last_error())
         self.h = h

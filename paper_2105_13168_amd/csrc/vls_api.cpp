@@ -1158,7 +1158,7 @@ struct vls_server {
     vls_context ctx;                 // private stream on the caller's device
     size_t budget = 0;
     int max_slots = 0;
-    int occ = 2;                     // workgroups per CU of the step launches
+    int occ = 1;                     // workgroups per CU of the step launches
     int cm = 0;                      // 1: gangs share through coherent atomics
     int64_t gang_verts = 0;          // vertices per gang workgroup (0 = default)
     unsigned long long slice_ticks = 0;
@@ -1324,8 +1324,9 @@ void vls_server::loop() {
 extern "C" {
 
 vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t max_slots, int64_t slice_us,
-                             vls_server **out) {
-    if (!ctx || !out || max_slots < 1 || slice_us < 1 || hbm_budget_bytes == 0)
+                             uint32_t flags, vls_server **out) {
+    if (!ctx || !out || max_slots < 1 || slice_us < 1 || hbm_budget_bytes == 0 ||
+        (flags & ~(VLS_BATCH_TWO_PER_CU | VLS_COHERENT_SHARING)))
         return set_err(ctx, VLS_E_INVALID_ARG, "bad server arguments");
     *out = nullptr;
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
@@ -1337,6 +1338,8 @@ vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t 
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     s->slice_ticks = (unsigned long long)slice_us * 100ull;    // s_memrealtime runs at 100 MHz
+    s->occ = (flags & VLS_BATCH_TWO_PER_CU) ? 2 : 1;
+    s->cm = (flags & VLS_COHERENT_SHARING) ? 1 : 0;
     vls_server *raw = s.get();
     try {
         s->th = std::thread([raw] { raw->loop(); });

@@ -414,12 +414,19 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
 #pragma unroll
         for (int k = 0; k < FK; ++k) {
             if (keep[k] && !big[k]) {
+                // padding slots (the vertex itself) read index nv instead, in
+                // the buffers' tail padding: the same address on every lane,
+                // so a padded slot costs one request rather than one per
+                // lane; those slots are never used
+                int32_t g[GB];
 #pragma unroll
-                for (int j = 0; j < GB; ++j) xs[k][j] = ldx<CM>(rin + nb[k][j]);
+                for (int j = 0; j < GB; ++j) g[j] = nb[k][j] != v[k] ? nb[k][j] : (int32_t)m.nv;
 #pragma unroll
-                for (int j = 0; j < GB; ++j) mu[k][j] = ldx<CM>(mk_cur + nb[k][j]);
+                for (int j = 0; j < GB; ++j) xs[k][j] = ldx<CM>(rin + g[j]);
 #pragma unroll
-                for (int j = 0; j < GB; ++j) st[k][j] = *(const GLOBAL_AS int32_t *)(s.stamp + nb[k][j]);
+                for (int j = 0; j < GB; ++j) mu[k][j] = ldx<CM>(mk_cur + g[j]);
+#pragma unroll
+                for (int j = 0; j < GB; ++j) st[k][j] = *(const GLOBAL_AS int32_t *)(s.stamp + g[j]);
             }
         }
 #pragma unroll

@@ -52,13 +52,15 @@ def _same(a, b):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("shape", ["one_per_cu", "two_per_cu", "coherent"])
 @pytest.mark.parametrize("slice_us", [150, 5000])
-def test_server_mix_matches_oracle_and_solo(oracle_mod, slice_us):
+def test_server_mix_matches_oracle_and_solo(oracle_mod, slice_us, shape):
     import paper_2105_13168_amd as vls
+    flags = {"one_per_cu": 0, "two_per_cu": vls.VLS_BATCH_TWO_PER_CU, "coherent": vls.VLS_COHERENT_SHARING}[shape]
     ctx = vls.Context(0)
     ms = _meshes()
     M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
-    srv = vls.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=64, slice_us=slice_us)
+    srv = vls.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=64, slice_us=slice_us, flags=flags)
     try:
         # staggered arrivals; the first torus twice at once (own run state
         # per request); checkpoints on one request
@@ -138,18 +140,20 @@ def test_server_destroy_with_work_in_flight():
     ctx.close()
 
 
-def test_server_gangs_resize_and_switch(oracle_mod):
+@pytest.mark.parametrize("two_per_cu", [False, True])
+def test_server_gangs_resize_and_switch(oracle_mod, two_per_cu):
     """Many large requests at once: the planner grants meshes of >= 2^17
     vertices gangs of workgroups, largest first, within three quarters of
-    the pool (512 workgroups at two per CU); the requests that no longer fit
-    run on one workgroup.  As requests finish the rest are re-planned, so a
-    request's visits switch from one workgroup to a gang.  Every result
-    equals the oracle's."""
+    the pool (256 or 512 workgroups at one or two per CU); the requests that
+    no longer fit run on one workgroup.  As requests finish the rest are
+    re-planned, so a request's visits switch from one workgroup to a gang.
+    Every result equals the oracle's."""
     import paper_2105_13168_amd as vls
     ctx = vls.Context(0)
     big = [mg.pretzel(72, rng_seed=s) for s in (0, 1)] + [mg.pretzel(96, rng_seed=2), mg.lattice(3, 96, rng_seed=3)]
     M = [vls.Mesh(ctx, m.xyz, m.tri) for m in big]
-    srv = vls.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=512, slice_us=300)
+    srv = vls.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=512, slice_us=300,
+                     flags=vls.VLS_BATCH_TWO_PER_CU if two_per_cu else 0)
     try:
         reqs = [(k % 2, srv.submit(M[k % 2], seed_vertex=big[k % 2].seed)) for k in range(200)]
         reqs += [(2, srv.submit(M[2], seed_vertex=big[2].seed)), (3, srv.submit(M[3], seed_vertex=big[3].seed))]
