@@ -65,12 +65,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_ms, workload, steps=None):
+def measured_traffic(kernel_ms, workload, steps=None, grid=None):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     runs (FETCH_SIZE, WRITE_SIZE scaled by a copy of known size), as GB/s over
     the live kernel time; None when the counters were taken on another
-    workload, another number of steps or other kernel sources.  `workload`
-    names the record (k_steps_<workload>_traffic.json)."""
+    workload, another number of steps, another grid or other kernel
+    sources.  `workload` names the record (k_steps_<workload>_traffic.json)."""
     path = os.path.join(ROOT, "profiles", f"k_steps_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -79,6 +79,8 @@ def measured_traffic(kernel_ms, workload, steps=None):
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     if steps is not None and t.get("diffusion_steps") != steps:
+        return None
+    if grid is not None and t.get("grid") != grid:
         return None
     return t["hbm_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9
 
@@ -139,7 +141,7 @@ def dense_leg(ctx, workload, steps):
         "algorithmic_bytes_per_step": ab / steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic(d["kernel_ms"], f"dense_{workload}", steps),
+                     "traffic": measured_traffic(d["kernel_ms"], f"dense_{workload}", steps, grid=d["grid"]),
                      "kernel": "k_steps_dec (dense field)"},
         "band_ms_per_step": b["kernel_ms"] / steps,
         "band_updates_per_step": b["active_vertex_updates"] / steps,
@@ -464,7 +466,7 @@ def main():
             "event_steps": last["event_steps"],
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms, args.workload),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms, args.workload, grid=last["grid"]),
                      "kernel": "k_steps_dec", "algorithmic_bytes": ab,
                      # a dense step (every vertex, 32 + 4 deg bytes) at this
                      # vertex-steps/s would need this share of HBM peak
