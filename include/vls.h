@@ -71,18 +71,20 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
                                     LDS tables hold: 2048 solo, 1024 in two-per-CU launches);
                                     results are identical, the flag exists for testing */
 #define VLS_COHERENT_SHARING 8u  /* share data between workgroups through coherent atomic accesses
-                                    and a release-only step barrier instead of plain accesses and
-                                    full agent-scope fences; identical results, for testing */
+                                    and release-only hand-offs instead of plain accesses and full
+                                    agent-scope fences (vls_run; vls_batch_run through the flags of
+                                    per_mesh[0]; the server through its creation flags); identical
+                                    results */
 #define VLS_LOCKSTEP 16u         /* one grid barrier per step (topology of t beside field of t+1)
                                     instead of the decoupled kernel; identical results, for testing */
 #define VLS_DENSE_FIELD 64u      /* the field step updates every vertex in id order instead of the
                                     update list (streams the whole mesh each step; vls_run's default
                                     grid is then every co-resident workgroup); identical results;
                                     meshes below 2^29 vertices (else VLS_E_INVALID_ARG) */
-#define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]): two workgroups per CU, each
-                                    with a 1024-candidate LDS topology path and one list entry per
-                                    field thread (the server always runs this way); default: one per
-                                    CU with the solo kernel's 2048 candidates and two entries */
+#define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]) and the server (creation
+                                    flags): two workgroups per CU, each with a 1024-candidate LDS
+                                    topology path and one list entry per field thread; default: one
+                                    per CU with the solo kernel's 2048 candidates and two entries */
 
 /*
  * Parameters.  Defaults (vls_params_default) are the paper's coefficients
