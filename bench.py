@@ -374,7 +374,7 @@ def main():
     ap.add_argument("--serve", type=int, default=1000, help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-lattice-share", type=float, default=0.05)
-    ap.add_argument("--serve-slice-us", type=int, default=2000)
+    ap.add_argument("--serve-slice-us", type=int, default=20000)
     ap.add_argument("--serve-two-per-cu", action="store_true", help="server step launches at two workgroups per CU")
     ap.add_argument("--dense-workload", default="lattice10_512",
                     help="mesh of the dense-step leg ('none': skip)")

@@ -306,7 +306,7 @@ class Server:
     returns a ticket, poll() returns None while the request runs and its
     Result once done.  A mesh must stay open until its requests are polled."""
 
-    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 1024, slice_us: int = 2000,
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 1024, slice_us: int = 20000,
                  flags: int = 0):
         h = C.c_void_p()
         st = vls_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), int(slice_us), int(flags), C.byref(h))
