@@ -20,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvls.so")
 
 VLS_OK = 0
+VLS_E_INVALID_ARG = -1
 VLS_E_STALLED = -7
 VLS_E_BUFFER_TOO_SMALL = -10
 VLS_E_PENDING = -14

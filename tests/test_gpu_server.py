@@ -123,6 +123,22 @@ def test_server_budget_admission_one_at_a_time(oracle_mod):
         ctx.close()
 
 
+def test_server_rejects_bad_arguments():
+    """Unknown flag bits, no slots, a zero slice or a zero budget are
+    VLS_E_INVALID_ARG at creation; no server is made."""
+    import ctypes as C
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    try:
+        for budget, slots, slice_us, flags in ((1 << 30, 8, 1000, 1 << 10), (1 << 30, 8, 1000, vls.VLS_DENSE_FIELD),
+                                               (1 << 30, 0, 1000, 0), (1 << 30, 8, 0, 0), (0, 8, 1000, 0)):
+            h = C.c_void_p()
+            st = vls.vls_server_create(ctx.h, budget, slots, slice_us, flags, C.byref(h))
+            assert st == vls.VLS_E_INVALID_ARG and not h.value, (budget, slots, slice_us, flags, st)
+    finally:
+        ctx.close()
+
+
 def test_server_destroy_with_work_in_flight():
     import paper_2105_13168_amd as vls
     ctx = vls.Context(0)
