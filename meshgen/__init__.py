@@ -22,10 +22,19 @@ synthetic surfaces of known genus stand in for them):
                          (small spheres, tori, multi-tori for tests)
 * ``uv_sphere``       -- latitude-longitude sphere whose poles have high
                          degree (tests of wide vertices)
+* ``voxel_surface``   -- unjittered boundary of a set of unit voxels; the
+                         exact symmetry of such surfaces makes fronts meet
+                         in ties (3-way merges, 1-to-3 splits, monkey
+                         saddles)
+* ``csaszar_torus``   -- the 7-vertex torus (every vertex adjacent to every
+                         other one)
 """
 from __future__ import annotations
 
+import ctypes
 import itertools
+import os
+import subprocess
 from dataclasses import dataclass
 
 import numpy as np
@@ -34,6 +43,7 @@ __all__ = [
     "Mesh", "torus_grid", "marching_tets", "sdf_surface", "pretzel", "batch_workload",
     "sdf_sphere", "sdf_torus", "sdf_union_tori", "sdf_box", "jittered",
     "pick_seed", "euler_characteristic", "pretzel_sdf", "multi_torus", "uv_sphere",
+    "voxel_surface", "voxel_frame", "csaszar_torus",
 ]
 
 
@@ -547,15 +557,153 @@ def lattice_genus(n_cells: int) -> int:
     return 3 * n * (n + 1) ** 2 - (n + 1) ** 3 + 1
 
 
+_MT_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mt_lattice.c")
+_MT_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_mt_lattice.so")
+_mt = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C twin of the lattice extraction (gcc, OpenMP, no
+    contraction)."""
+    if force or not os.path.exists(_MT_LIB) or os.path.getmtime(_MT_LIB) < os.path.getmtime(_MT_SRC):
+        tmp = _MT_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c99",
+                               "-shared", "-fPIC", "-o", tmp, _MT_SRC, "-lm"])
+        os.replace(tmp, _MT_LIB)
+    return _MT_LIB
+
+
+def _mt_load():
+    global _mt
+    if _mt is None:
+        build(force=False)
+        lib = ctypes.CDLL(_MT_LIB)
+        P = ctypes.c_void_p
+        lib.mt_lattice.restype = ctypes.c_int
+        lib.mt_lattice.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                   P, P, P, P, P, P, P, ctypes.POINTER(P), ctypes.POINTER(P)]
+        lib.mt_free.restype = None
+        lib.mt_free.argtypes = [P]
+        _mt = lib
+    return _mt
+
+
+def lattice_mt_compiled(n_cells: int, radius: float, lo, hi, shape) -> Mesh:
+    """The same extraction as ``marching_tets_slabs(lattice_plane_sdf(...))``
+    run by the compiled twin in mt_lattice.c: bit-identical vertex positions
+    and numbering, the same triangles (in another order), in parallel."""
+    lib = _mt_load()
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    tets = np.ascontiguousarray(_TETS, dtype=np.int64)
+    cases = np.ascontiguousarray(_CASES, dtype=np.int64)
+    ntri = np.ascontiguousarray(_NTRI, dtype=np.int64)
+    nv, nf = ctypes.c_int64(), ctypes.c_int64()
+    px, pt = ctypes.c_void_p(), ctypes.c_void_p()
+    rc = lib.mt_lattice(int(n_cells), float(radius), int(shape[0]), int(shape[1]), int(shape[2]),
+                        lo.ctypes.data, hi.ctypes.data, tets.ctypes.data, cases.ctypes.data, ntri.ctypes.data,
+                        ctypes.byref(nv), ctypes.byref(nf), ctypes.byref(px), ctypes.byref(pt))
+    if rc != 0:
+        raise MemoryError("mt_lattice: out of memory")
+    try:
+        xyz = np.ctypeslib.as_array((ctypes.c_double * (3 * nv.value)).from_address(px.value)).reshape(-1, 3).copy()
+        tri = np.ctypeslib.as_array((ctypes.c_int32 * (3 * nf.value)).from_address(pt.value)).reshape(-1, 3).copy()
+    finally:
+        lib.mt_free(px)
+        lib.mt_free(pt)
+    return Mesh(xyz, tri, 0, "mt_lattice")
+
+
 def lattice(n_cells: int = 10, grid: int = 1024, radius: float = 0.15, sigma: float = 0.0,
-            rng_seed: int = 0, slab: int = 16, progress=None) -> Mesh:
+            rng_seed: int = 0, slab: int = 16, progress=None, compiled: bool = True) -> Mesh:
     """Strut lattice surface: level 0 of ``lattice_plane_sdf`` on grid^3
     samples over [-0.5, n + 0.5]^3, optional N(0, sigma^2) jitter, then a
-    random seed vertex from rng_seed.  Genus ``lattice_genus(n_cells)``."""
+    random seed vertex from rng_seed.  Genus ``lattice_genus(n_cells)``.
+    compiled=True extracts with the C twin (same vertices and triangles,
+    triangles in another order), else with the numpy slab extraction."""
     lo = (-0.5, -0.5, -0.5)
     hi = (n_cells + 0.5,) * 3
-    m = marching_tets_slabs(lattice_plane_sdf(n_cells, radius), lo, hi, (grid, grid, grid), slab,
-                            progress=progress)
+    if compiled:
+        m = lattice_mt_compiled(n_cells, radius, lo, hi, (grid, grid, grid))
+    else:
+        m = marching_tets_slabs(lattice_plane_sdf(n_cells, radius), lo, hi, (grid, grid, grid), slab,
+                                progress=progress)
     m = jittered(m, sigma, rng_seed, f"lattice{n_cells}_{grid}") if sigma > 0 else \
         Mesh(m.xyz, m.tri, 0, f"lattice{n_cells}_{grid}")
     return m if sigma > 0 else pick_seed(m, rng_seed)
+
+
+# ---------------------------------------------------------------------------
+# unjittered voxel surfaces and the 7-vertex torus
+# ---------------------------------------------------------------------------
+def voxel_surface(occ, center: bool = True, name: str = "voxel") -> Mesh:
+    """Boundary of a set of unit voxels: occ[i, j, k] True fills the cube
+    [i, i+1] x [j, j+1] x [k, k+1].  Each exposed unit face becomes four
+    triangles around its centre (center=True: the face's full symmetry is
+    kept) or two triangles split along the diagonal on which both in-plane
+    coordinates increase (a choice every permutation of the axes maps to
+    itself).  Triangles are counter-clockwise seen from outside; vertices are
+    welded by their doubled integer coordinates and numbered in ascending
+    (x, y, z) order.  No jitter; seed vertex 0.  Voxels that touch only along
+    an edge or at a corner make a non-manifold surface: the shapes used here
+    have none."""
+    occ = np.asarray(occ, dtype=bool)
+    P = np.pad(occ, 1)
+    quads = []
+    for ax in range(3):
+        a1, a2 = (ax + 1) % 3, (ax + 2) % 3
+        e1 = np.zeros(3, np.int64)
+        e1[a1] = 1
+        e2 = np.zeros(3, np.int64)
+        e2[a2] = 1
+        for sgn in (1, -1):
+            face = P & ~np.roll(P, -sgn, axis=ax)       # filled voxel, empty neighbour
+            idx = np.argwhere(face).astype(np.int64) - 1
+            if idx.size == 0:
+                continue
+            base = idx.copy()
+            if sgn == 1:
+                base[:, ax] += 1
+            p0, p1, p2, p3 = base, base + e1, base + e1 + e2, base + e2
+            # (e1, e2, e_ax) is right-handed: p0 p1 p2 p3 is counter-clockwise seen from +ax
+            quads.append(np.stack([p0, p1, p2, p3] if sgn == 1 else [p0, p3, p2, p1], axis=1))
+    Q = 2 * np.concatenate(quads)                        # [nq, 4, 3] doubled coordinates
+    if center:
+        cen = Q.sum(axis=1) // 4
+        T = np.concatenate([np.stack([Q[:, k], Q[:, (k + 1) % 4], cen], axis=1) for k in range(4)])
+    else:
+        lo = np.argmin(Q.sum(axis=2), axis=1)            # corner with the smallest coordinate sum
+        r = np.arange(Q.shape[0])
+        c = [Q[r, (lo + k) % 4] for k in range(4)]
+        T = np.concatenate([np.stack([c[0], c[1], c[2]], axis=1), np.stack([c[0], c[2], c[3]], axis=1)])
+    flat = T.reshape(-1, 3)
+    M = int(flat.max()) + 1
+    key = (flat[:, 0] * M + flat[:, 1]) * M + flat[:, 2]
+    uk, inv = np.unique(key, return_inverse=True)
+    xyz = np.stack([uk // (M * M), (uk // M) % M, uk % M], axis=1).astype(np.float64) / 2.0
+    return Mesh(xyz, inv.reshape(-1, 3).astype(np.int32), 0, name)
+
+
+def voxel_frame(n_cells: int = 1, length: int = 2, bar: int = 1, center: bool = True) -> Mesh:
+    """Voxel jungle gym: bars of bar x bar voxels along every edge of an
+    n_cells^3 cubic lattice with `length` empty voxels between bars (a voxel
+    is filled when at least two of its three coordinates fall in a bar
+    interval).  Genus = struts - nodes + 1, as for the strut lattice."""
+    N = n_cells * (length + bar) + bar
+    r = (np.arange(N) % (length + bar)) < bar
+    I, J, K = np.meshgrid(r, r, r, indexing="ij")
+    occ = (I.astype(np.int64) + J + K) >= 2
+    return voxel_surface(occ, center, f"voxel_frame{n_cells}_{length}_{bar}{'c' if center else 'd'}")
+
+
+def csaszar_torus() -> Mesh:
+    """The 7-vertex torus: triangles (i, i+1, i+3) and (i, i+3, i+2) mod 7,
+    vertices on a twisted ring (the coordinates only matter for lengths and
+    positions; the triangulation is what the method sees)."""
+    t = []
+    for i in range(7):
+        t.append((i, (i + 1) % 7, (i + 3) % 7))
+        t.append((i, (i + 3) % 7, (i + 2) % 7))
+    ang = np.arange(7) * 2.0 * np.pi / 7.0
+    xyz = np.stack([np.cos(ang), np.sin(ang), 0.3 * np.cos(3.0 * ang)], axis=1)
+    return Mesh(xyz.astype(np.float64), np.array(t, dtype=np.int32), 0, "csaszar7")

@@ -97,3 +97,52 @@ def hop_ball(tri, nv, s, r0):
         hop[nb] = h
         frontier = nb
     return hop
+
+
+def events_bruteforce(m, r):
+    """Every event's s (fronts on the lower link), m (loops through the new
+    crossed edges) and h (from the Euler characteristic and loop count
+    before and after the insertion) recomputed from the insertion order."""
+    topo = MeshTopo(m.tri, m.nv)
+    order = rank_key(r.T, r.rnd)
+    pos = np.empty(m.nv, dtype=np.int64)
+    pos[order] = np.arange(m.nv)
+    # neighbours
+    t = m.tri.astype(np.int64)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    nbr = [[] for _ in range(m.nv)]
+    for u, x in e:
+        nbr[u].append(x)
+    # counter-clockwise link edges a -> b of each vertex (triangle (v, a, b))
+    link = [[] for _ in range(m.nv)]
+    for a_, b_, c_ in t:
+        link[a_].append((b_, c_))
+        link[b_].append((c_, a_))
+        link[c_].append((a_, b_))
+    for ev in r.events:
+        step, v, typ, k, s, mm, h, x = (int(q) for q in ev[:8])
+        pre = pos < pos[v]
+        post = pre.copy()
+        post[v] = True
+        # lower arcs of v's link: a link edge leaving the upper part into the
+        # lower part starts one; a full lower link is recorded as k = 0
+        full = all(pre[a_] for a_, _ in link[v])
+        k_bf = 0 if full else sum(1 for a_, b_ in link[v] if not pre[a_] and pre[b_])
+        assert k_bf == k, (ev, k_bf)
+        nb, lab, ce = topo.loops(pre)
+        na, laba, cea = topo.loops(post)
+        # loops through v's star before: labels of crossed edges (u, v)
+        lab_of = dict(zip(ce.tolist(), lab.tolist()))
+        s_bf = len({lab_of[topo.edge_id(u, v)] for u in nbr[v] if pre[u]})
+        laba_of = dict(zip(cea.tolist(), laba.tolist()))
+        m_bf = len({laba_of[topo.edge_id(u, v)] for u in nbr[v] if not post[u]})
+        assert s_bf == s, (ev, s_bf)
+        assert m_bf == mm, (ev, m_bf)
+        dchi = topo.euler_char(post) - topo.euler_char(pre)
+        db = na - nb
+        assert dchi + db == -2 * h
+        # node type and extra cycles from (full link, s, h)
+        x_bf = 0 if full else h - (s - 1)
+        assert x_bf == x, (ev, x_bf)
+        typ_bf = 3 if full else (4 if x_bf > 0 else (2 if s >= 2 else 1))
+        assert typ_bf == typ, (ev, typ_bf)

@@ -27,7 +27,7 @@ import pytest
 
 import meshgen as mg
 
-from _topo import MeshTopo, hop_ball, rank_key
+from _topo import MeshTopo, events_bruteforce, hop_ball
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -159,41 +159,11 @@ def test_genus_counts_over_seeds(oracle_mod, name, make, g):
         assert len(edges) - len(nodes) + 1 + extra == g
 
 
-def _events_bruteforce(m, r):
-    topo = MeshTopo(m.tri, m.nv)
-    order = rank_key(r.T, r.rnd)
-    pos = np.empty(m.nv, dtype=np.int64)
-    pos[order] = np.arange(m.nv)
-    # neighbours
-    t = m.tri.astype(np.int64)
-    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
-    nbr = [[] for _ in range(m.nv)]
-    for u, x in e:
-        nbr[u].append(x)
-    for ev in r.events:
-        step, v, typ, k, s, mm, h, x = (int(q) for q in ev[:8])
-        pre = pos < pos[v]
-        post = pre.copy()
-        post[v] = True
-        nb, lab, ce = topo.loops(pre)
-        na, laba, cea = topo.loops(post)
-        # loops through v's star before: labels of crossed edges (u, v)
-        lab_of = dict(zip(ce.tolist(), lab.tolist()))
-        s_bf = len({lab_of[topo.edge_id(u, v)] for u in nbr[v] if pre[u]})
-        laba_of = dict(zip(cea.tolist(), laba.tolist()))
-        m_bf = len({laba_of[topo.edge_id(u, v)] for u in nbr[v] if not post[u]})
-        assert s_bf == s, (ev, s_bf)
-        assert m_bf == mm, (ev, m_bf)
-        dchi = topo.euler_char(post) - topo.euler_char(pre)
-        db = na - nb
-        assert dchi + db == -2 * h
-
-
 def test_event_semantics_bruteforce(oracle_mod):
     for m in (_torus(), mg.multi_torus(2, 24, rng_seed=1), mg.pretzel(32, rng_seed=2)):
         r = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
         assert r.status == 0
-        _events_bruteforce(m, r)
+        events_bruteforce(m, r)
 
 
 def test_euler_identity_every_step_bruteforce(oracle_mod):
