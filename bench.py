@@ -98,9 +98,11 @@ def copy_calibration(nbytes=1 << 30):
 
 
 def dense_alg_bytes(updates, degsum):
-    # per vertex of a dense step: read rho(v) 8 + write rho(v) 8 + two row
-    # offsets 8, plus 4 bytes per neighbour id (no update list)
-    return 24 * updates + 4 * degsum
+    # per vertex of a dense step: read rho(v) 8 + write rho(v) 8 + one row
+    # offset 4 (consecutive vertices share their row bounds: a tile of n
+    # vertices reads n+1 offsets), plus 4 bytes per neighbour id (no update
+    # list)
+    return 20 * updates + 4 * degsum
 
 
 def dense_leg(ctx, workload, steps):

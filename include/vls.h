@@ -50,11 +50,11 @@ enum {
     VLS_E_OUT_OF_MEMORY = -8,
     VLS_E_DEVICE = -9,                /* a HIP runtime call failed                               */
     VLS_E_BUFFER_TOO_SMALL = -10,
-    VLS_E_CAPACITY = -11,             /* an internal device buffer bound was exceeded            */
-    VLS_E_TOO_LARGE = -12,            /* mesh beyond the 32-bit index range                      */
+    VLS_E_PENDING = -11,              /* server request / async run not finished yet             */
+    VLS_E_CANCELLED = -12,            /* server request dropped by vls_server_shutdown / _destroy */
     VLS_E_INVARIANT = -13,            /* a topological invariant failed (see vls_last_error)     */
-    VLS_E_PENDING = -14,              /* server request not finished yet                         */
-    VLS_E_CANCELLED = -15             /* server request dropped by vls_server_destroy            */
+    VLS_E_CAPACITY = -14,             /* an internal device buffer bound was exceeded            */
+    VLS_E_TOO_LARGE = -15             /* mesh beyond the index range or the degree limit (64)    */
 };
 
 /* Reeb node types (Section "Initial Pass": branching and collision;
@@ -107,7 +107,7 @@ typedef struct vls_params {
     int32_t n_ckpt;            /* number of entries in ckpt_steps                         */
     const int64_t *ckpt_steps; /* (host) steps whose field is kept (with VLS_RECORD_FIELD) */
     int32_t grid;              /* persistent workgroups; 0 = chosen by the library: about
-                                  one per 22k vertices, 16..128, at most what is co-resident;
+                                  one per 34k vertices, 16..128, at most what is co-resident;
                                   vls_batch_run: pool size of per_mesh[0]                 */
     int32_t block;             /* threads per workgroup: 256 (0 = default)                */
     int64_t gang_vertices;     /* vls_batch_run / server (per_mesh[0] for a batch): a mesh
@@ -139,8 +139,9 @@ vls_status vls_context_destroy(struct vls_context *ctx);
  *        oriented (counter-clockwise seen from outside)
  * Copies, validates, builds the adjacency (ascending and counter-clockwise
  * vertex links, reverse and successor half-edge maps) and uploads it.
+ * Limits: every vertex degree is 3..64, nv < 2^31 - 1 and 3*nf < 2^31.
  * Errors: VLS_E_MESH_* when the mesh is not a closed connected orientable
- * manifold; VLS_E_TOO_LARGE when 3*nf >= 2^31.
+ * manifold; VLS_E_TOO_LARGE when 3*nf >= 2^31 or a vertex has degree > 64.
  */
 vls_status vls_mesh_create(struct vls_context *ctx, int64_t nv, const double *xyz,
                            int64_t nf, const int32_t *tri, struct vls_mesh **out);
@@ -159,6 +160,42 @@ vls_status vls_mesh_destroy(struct vls_mesh *m);
  */
 vls_status vls_run(struct vls_context *ctx, const struct vls_mesh *m, const vls_params *p,
                    struct vls_result **out);
+
+/*
+ * The same pass on caller-owned device memory and a caller stream: PyTorch
+ * (or any caller) allocates the workspace and owns the stream; the library
+ * allocates no device memory for the run (Introduction: mesh in, loops and
+ * Reeb graph out; the memory-budgeted concurrency of Section "Performance
+ * Considerations" is the caller's to plan with vls_workspace_size).
+ *
+ * vls_workspace_size: bytes of device workspace a vls_run_async of mesh m
+ *   with parameters p needs: the run state (per vertex and per half-edge
+ *   arrays, event and loop buffers), the field checkpoints of p, and the
+ *   post-pass scratch (Reeb positions and tunnel paths, processed in chunks
+ *   that always fit it).  Depends on the mesh and on p's checkpoint count
+ *   only.
+ * vls_run_async: enqueues the seed initialisation and the persistent step
+ *   kernel on hip_stream (a hipStream_t; NULL = the context's stream) and
+ *   returns at once with *out in the launched state.  d_workspace (device,
+ *   256-byte aligned, at least vls_workspace_size bytes) is borrowed: it
+ *   must stay allocated and untouched by other work until vls_result_wait
+ *   (or the first accessor, or vls_result_destroy) has returned; its
+ *   initial contents do not matter.  p and its checkpoint list are copied.
+ *   The mesh's own cached run state is not used, so several async runs of
+ *   one mesh may be in flight, each with its own workspace.
+ * vls_result_wait: waits for the step kernel, runs the post-passes on the
+ *   same stream in the workspace, copies every result to host memory owned
+ *   by the result, and returns the run status (as vls_run would).  Every
+ *   accessor waits implicitly; a stream synchronisation alone does not run
+ *   the post-passes.  For a result of vls_run it returns its run status.
+ * Errors: VLS_E_BUFFER_TOO_SMALL (workspace too small), VLS_E_INVALID_ARG
+ *   (misaligned or NULL workspace, bad parameters), VLS_E_DEVICE.
+ */
+vls_status vls_workspace_size(const struct vls_mesh *m, const vls_params *p, size_t *bytes);
+vls_status vls_run_async(struct vls_context *ctx, const struct vls_mesh *m, const vls_params *p,
+                         void *d_workspace, size_t bytes, void *hip_stream, struct vls_result **out);
+vls_status vls_result_wait(struct vls_result *r);
+
 
 typedef struct {
     int32_t n_handles;         /* handle loops emitted (merges: fronts involved minus one)   */
@@ -283,8 +320,13 @@ vls_status vls_batch_run(struct vls_context *ctx, int32_t n, const struct vls_me
  * vls_server_poll: VLS_E_PENDING until the request is done; then *out
  *   receives its result (owned by the caller) and the call returns the run
  *   status; the ticket is then forgotten.  Thread-safe.
- * vls_server_destroy: stops the scheduler; queued and running requests are
- *   dropped (their polls can no longer happen), unpolled results freed.
+ * vls_server_shutdown: stops the scheduler after its current launch; every
+ *   request still queued or running is cancelled: its poll returns
+ *   VLS_E_CANCELLED with *out = NULL.  Finished requests keep their results
+ *   until polled; later submits return VLS_E_CANCELLED.  Idempotent.
+ * vls_server_destroy: vls_server_shutdown, then frees the server and every
+ *   result that was never polled; the handle and its tickets are invalid
+ *   afterwards.
  * Errors: VLS_E_INVALID_ARG (bad handle/ticket), VLS_E_DEVICE.
  */
 struct vls_server;
@@ -297,6 +339,7 @@ vls_status vls_server_poll(struct vls_server *srv, uint64_t ticket, struct vls_r
    state currently admitted (bytes), requests queued and running */
 vls_status vls_server_stats(const struct vls_server *srv, int64_t *launches, int64_t *completed,
                             int64_t *admitted_bytes, int32_t *queued, int32_t *running);
+vls_status vls_server_shutdown(struct vls_server *srv);
 vls_status vls_server_destroy(struct vls_server *srv);
 
 /* Copies the bulk results of a VLS_DEFER_RESULTS run to the host (no-op

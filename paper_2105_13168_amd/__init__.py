@@ -23,8 +23,11 @@ VLS_OK = 0
 VLS_E_INVALID_ARG = -1
 VLS_E_STALLED = -7
 VLS_E_BUFFER_TOO_SMALL = -10
-VLS_E_PENDING = -14
-VLS_E_CANCELLED = -15
+VLS_E_PENDING = -11
+VLS_E_CANCELLED = -12
+VLS_E_INVARIANT = -13
+VLS_E_CAPACITY = -14
+VLS_E_TOO_LARGE = -15
 VLS_RECORD_FIELD = 1
 VLS_DEFER_RESULTS = 2
 VLS_TOPO_GLOBAL_PATH = 4
@@ -74,6 +77,15 @@ class vls_reeb_edge(C.Structure):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2105_13168_amd/build.py`")
+# PyTorch ships its own HIP runtime under the same soname as the system one
+# the library links against.  Loaded after PyTorch, the library binds to
+# that runtime (one runtime per process: PyTorch's streams and memory are
+# valid here); loaded first, it would pull in the system runtime and
+# PyTorch's would then fail to find the device.  So PyTorch goes first.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 _PP = C.POINTER(C.c_void_p)
@@ -88,6 +100,9 @@ _sig = {
     "vls_mesh_info": (C.c_int32, [_P, _I64P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vls_mesh_destroy": (C.c_int32, [_P]),
     "vls_run": (C.c_int32, [_P, _P, C.POINTER(vls_params), _PP]),
+    "vls_workspace_size": (C.c_int32, [_P, C.POINTER(vls_params), C.POINTER(C.c_size_t)]),
+    "vls_run_async": (C.c_int32, [_P, _P, C.POINTER(vls_params), _P, C.c_size_t, _P, _PP]),
+    "vls_result_wait": (C.c_int32, [_P]),
     "vls_batch_run": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "vls_result_summary": (C.c_int32, [_P, C.POINTER(vls_summary)]),
     "vls_result_events": (C.c_int32, [_P, C.c_int64, _P, _I64P]),
@@ -104,6 +119,7 @@ _sig = {
     "vls_server_submit": (C.c_int32, [_P, _P, C.POINTER(vls_params), C.POINTER(C.c_uint64)]),
     "vls_server_poll": (C.c_int32, [_P, C.c_uint64, _PP]),
     "vls_server_stats": (C.c_int32, [_P, _I64P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "vls_server_shutdown": (C.c_int32, [_P]),
     "vls_server_destroy": (C.c_int32, [_P]),
 }
 for _n, (_rt, _at) in _sig.items():
@@ -277,14 +293,25 @@ class Result:
         return [l for l in self.loops if l["kept"]]
 
 
-def batch_run(ctx: Context, meshes, seeds, raise_on_error: bool = True, **kw):
+def batch_run(ctx: Context, meshes, seeds, raise_on_error: bool = True, per_mesh=None, **kw):
     """Many meshes in one launch (one workgroup per mesh); returns one
-    Result per mesh, in input order."""
+    Result per mesh, in input order.  ``kw`` applies to every mesh,
+    ``per_mesh`` (a list of dicts, ckpt_steps allowed) to one mesh each."""
     n = len(meshes)
     hm = (C.c_void_p * n)(*[m.h.value for m in meshes])
     ps = (vls_params * n)()
+    cks = []
     for i in range(n):
-        ps[i] = default_params(seed_vertex=int(seeds[i]), **kw)
+        d = dict(kw)
+        if per_mesh is not None:
+            d.update(per_mesh[i])
+        ck = np.ascontiguousarray(np.asarray(d.pop("ckpt_steps", ()), dtype=np.int64).reshape(-1))
+        cks.append(ck)
+        ps[i] = default_params(seed_vertex=int(seeds[i]), **d)
+        if ck.size:
+            ps[i].flags |= VLS_RECORD_FIELD
+            ps[i].n_ckpt = ck.size
+            ps[i].ckpt_steps = ck.ctypes.data_as(_I64P)
     outs = (C.c_void_p * n)()
     st = vls_batch_run(ctx.h, n, hm, ps, outs)
     if st != VLS_OK and (raise_on_error and st != -7 or not outs[0]):
@@ -293,9 +320,8 @@ def batch_run(ctx: Context, meshes, seeds, raise_on_error: bool = True, **kw):
                 vls_result_destroy(C.c_void_p(outs[i]))
         raise VLSError(st, ctx.last_error())
     res = []
-    empty = np.zeros(0, dtype=np.int64)
     for i in range(n):
-        r = Result(C.c_void_p(outs[i]), meshes[i], empty)
+        r = Result(C.c_void_p(outs[i]), meshes[i], cks[i])
         r.status = r.summary["run_status"]
         r.error = ""
         res.append(r)
@@ -346,6 +372,12 @@ class Server:
         r.status = int(st)
         r.error = ""
         return r
+
+    def shutdown(self):
+        """Stops scheduling; unfinished requests then poll as cancelled."""
+        st = vls_server_shutdown(self.h)
+        if st != VLS_OK:
+            raise VLSError(st, "shutdown")
 
     def stats(self) -> dict:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()

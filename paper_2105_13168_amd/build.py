@@ -19,7 +19,11 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # the field must be evaluated exactly as written: no FMA contraction
     "-ffp-contract=off", "-fno-fast-math",
-    # no packed FP32 instructions anywhere in device code
+    # no packed FP32 instructions (v_pk_*_f32) anywhere in device code: the
+    # feature is known to the gfx950 device pass, which then emits none (a
+    # float2 multiply-add that compiles to v_pk_fma_f32 without the flag
+    # compiles to scalar v_fma_f32 with it; tests/test_build_flags.py checks
+    # this); the host pass, which has no such feature, warns and ignores it
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

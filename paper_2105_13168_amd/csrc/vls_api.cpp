@@ -54,19 +54,24 @@ struct vls_mesh {
     vls_result *pending = nullptr;       // run whose results still sit in rb
 };
 
+struct RunPrep;   // one run in flight (defined with the run sequence)
+
 struct Pending {
-    bool active = false;
+    bool active = false;                 // bulk results still on the device
     vls_context *ctx = nullptr;
-    vls_mesh *mesh = nullptr;
+    vls_mesh *mesh = nullptr;            // mesh whose cached run state holds them
+    hipStream_t stream = nullptr;
     DState s{};
     Ctl c{};
-    void *dpos = nullptr, *dtn = nullptr, *dtlen = nullptr;
-    std::vector<void *> tmp_allocs;
+    std::vector<void *> tmp_allocs;      // checkpoint buffers of hipMalloc'ed runs
     bool rec_field = false;
 };
 
 struct vls_result {
     Pending pend;
+    RunPrep *launched = nullptr;         // vls_run_async: enqueued, not yet waited for
+    vls_status launch_status = VLS_OK;   // status vls_result_wait returns once done
+    bool failed = false;                 // the post-passes or copies failed: no outputs
     vls_summary sum{};
     int64_t nv = 0;
     std::vector<int64_t> ev;             // [n][16]
@@ -80,8 +85,8 @@ struct vls_result {
     std::vector<int32_t> tn;             // [n_tunnels][4]
     std::vector<int64_t> tn_off;         // [n_tunnels+1]
     std::vector<int32_t> tn_v;
+    std::vector<double> tn_pts;          // [*][3] positions of the tunnel vertices
     std::vector<double> tn_len;          // [n_tunnels] vertex polyline lengths
-    std::vector<double> mesh_xyz;        // for tunnel polylines
     std::vector<int32_t> step, round, parent;
     std::vector<double> rho_final;
     std::vector<int64_t> ckpt_steps;
@@ -146,11 +151,11 @@ const char *vls_status_string(vls_status s) {
     case VLS_E_OUT_OF_MEMORY: return "VLS_E_OUT_OF_MEMORY";
     case VLS_E_DEVICE: return "VLS_E_DEVICE";
     case VLS_E_BUFFER_TOO_SMALL: return "VLS_E_BUFFER_TOO_SMALL";
-    case VLS_E_CAPACITY: return "VLS_E_CAPACITY";
-    case VLS_E_TOO_LARGE: return "VLS_E_TOO_LARGE";
-    case VLS_E_INVARIANT: return "VLS_E_INVARIANT";
     case VLS_E_PENDING: return "VLS_E_PENDING";
     case VLS_E_CANCELLED: return "VLS_E_CANCELLED";
+    case VLS_E_INVARIANT: return "VLS_E_INVARIANT";
+    case VLS_E_CAPACITY: return "VLS_E_CAPACITY";
+    case VLS_E_TOO_LARGE: return "VLS_E_TOO_LARGE";
     default: return "VLS_E_UNKNOWN";
     }
 }
@@ -349,57 +354,51 @@ vls_status upload(vls_mesh *m, const std::vector<T> &h, const T **out) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// per-mesh device run state (allocated at the first run, reused)
+// device memory of a run: either carved from one caller-provided block (a
+// workspace: nothing is allocated) or one hipMalloc per buffer; a counting
+// mode sizes a workspace with the same sequence of requests
 // ---------------------------------------------------------------------------
-struct RunBuffers {
-    std::vector<void *> allocs;
-    DState s{};
-    int64_t ord_cap = 0;
-    int32_t n_ckpt_cap = 0;
-    ~RunBuffers() {
-        for (void *p : allocs) (void)hipFree(p);
+struct DevArena {
+    enum Mode { MALLOC, CARVE, COUNT } mode = MALLOC;
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    std::vector<void *> owned;        // MALLOC mode: freed by release()
+    static size_t padded(size_t bytes) {
+        // 64 bytes of tail padding (aligned vector loads of a buffer's last
+        // partial chunk stay inside it), 256-byte aligned starts
+        return (bytes + 64 + 255) & ~(size_t)255;
+    }
+    size_t left() const { return used <= cap ? cap - used : 0; }
+    template <typename T> hipError_t get(T **p, size_t n) {
+        const size_t b = padded((n ? n : 1) * sizeof(T));
+        if (mode == MALLOC) {
+            void *q = nullptr;
+            hipError_t e = hipMalloc(&q, b);
+            if (e == hipSuccess) owned.push_back(q);
+            *p = (T *)q;
+            used += b;
+            return e;
+        }
+        if (mode == COUNT) {
+            *p = (T *)(uintptr_t)(256 + used);   // never dereferenced
+            used += b;
+            return hipSuccess;
+        }
+        if (used + b > cap) { *p = nullptr; return hipErrorOutOfMemory; }
+        *p = (T *)(base + used);
+        used += b;
+        return hipSuccess;
+    }
+    void release() {
+        for (void *q : owned) (void)hipFree(q);
+        owned.clear();
+        used = 0;
     }
 };
 
-template <typename T>
-static hipError_t dalloc(RunBuffers *rb, T **p, size_t n) {
-    void *q = nullptr;
-    // 64 bytes of tail padding: aligned vector loads of a buffer's last
-    // partial chunk stay inside the allocation
-    hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T) + 64);
-    if (e == hipSuccess) rb->allocs.push_back(q);
-    *p = (T *)q;
-    return e;
-}
-
-// device bytes make_run_buffers allocates for mesh m (the server's HBM
-// admission charges a request this much plus its checkpoints)
-static size_t run_buffer_bytes(const vls_mesh *m) {
-    const size_t nv = (size_t)m->nv, nnz = (size_t)m->nnz;
-    size_t npow = 1;
-    while (npow < nv) npow <<= 1;
-    const int64_t g = std::max<int64_t>(0, m->euler_genus);
-    const size_t tag_cap = (size_t)std::min<int64_t>((int64_t)nv + 4096, INT32_MAX);
-    const size_t ev_cap = (size_t)std::min<int64_t>((int64_t)nv, 65536 + (int64_t)nv / 16);
-    const size_t ev_ids_cap = 4 * ev_cap + 64;
-    const size_t lp_cap = (size_t)(2 * g + 64);
-    const size_t lp_he_cap = nnz / 4 + 65536;
-    size_t b = 0;
-    b += nv * (8 + 8 + 8 + 4 + 4);                 // rho0, rho1, key, parent, depth
-    b += nnz * 4;                                  // lid
-    b += nv * 4 * 13;                              // stamp .. Lcls (13 int32 arrays)
-    b += npow * 8;                                 // ord
-    b += tag_cap * 4 * 2 + tag_cap * 4 * 2;        // tag_parent, tag_fid, front_birth, front_death
-    b += ev_cap * 16 * 8 + ev_cap * 16 * 4 + ev_ids_cap * 8;
-    b += lp_cap * 8 * 8 + lp_he_cap * 2 * 4 + lp_he_cap * 3 * 8 + lp_cap * 4 * 4;
-    b += 64 * 64 * 4 + lp_he_cap * 8;              // walk checkpoints, segment lengths
-    b += sizeof(Ctl);
-    return b;
-}
-
-static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
-    auto rb = std::make_unique<RunBuffers>();
-    DState &s = rb->s;
+// run state of one pass on mesh m (the arrays of DState), from arena A
+static hipError_t alloc_state(const vls_mesh *m, DevArena &A, DState &s) {
+    s = DState{};
     const size_t nv = (size_t)m->nv, nnz = (size_t)m->nnz;
     size_t npow = 1;
     while (npow < nv) npow <<= 1;
@@ -413,23 +412,64 @@ static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
     s.lp_cap = (int32_t)(2 * g + 64);
     s.lp_he_cap = (int64_t)nnz / 4 + 65536;
     hipError_t e = hipSuccess;
-#define A(ptr, n) if (e == hipSuccess) e = dalloc(rb.get(), &(ptr), (n))
-    A(s.rho0, nv); A(s.rho1, nv); A(s.key, nv); A(s.parent, nv); A(s.depth, nv);
-    A(s.lid, nnz); A(s.stamp, nv); A(s.cstamp, nv); A(s.mark[0], nv); A(s.mark[1], nv);
-    A(s.act[0], nv); A(s.act[1], nv); A(s.cand[0], nv); A(s.cand[1], nv);
-    A(s.pend[0], nv); A(s.pend[1], nv); A(s.L, nv); A(s.Lrnd, nv); A(s.Lcls, nv);
-    A(s.ord, npow);
-    A(s.tag_parent, (size_t)s.tag_cap); A(s.tag_fid, (size_t)s.tag_cap);
-    A(s.ev, (size_t)s.ev_cap * 16); A(s.ev_rep, (size_t)s.ev_cap * 16); A(s.ev_ids, (size_t)s.ev_ids_cap);
-    A(s.front_birth, (size_t)s.front_cap); A(s.front_death, (size_t)s.front_cap);
-    A(s.lp, (size_t)s.lp_cap * 8); A(s.lp_he, (size_t)s.lp_he_cap * 2); A(s.lp_pts, (size_t)s.lp_he_cap * 3);
-    A(s.tn, (size_t)s.lp_cap * 4);
-    A(s.wck, 64 * 64);
-    A(s.wseg, (size_t)s.lp_he_cap);
-    A(s.ctl, 1);
-#undef A
+#define A_(ptr, n) if (e == hipSuccess) e = A.get(&(ptr), (n))
+    A_(s.rho0, nv); A_(s.rho1, nv); A_(s.key, nv); A_(s.parent, nv); A_(s.depth, nv);
+    A_(s.lid, nnz); A_(s.stamp, nv); A_(s.cstamp, nv); A_(s.mark[0], nv); A_(s.mark[1], nv);
+    A_(s.act[0], nv); A_(s.act[1], nv); A_(s.cand[0], nv); A_(s.cand[1], nv);
+    A_(s.pend[0], nv); A_(s.pend[1], nv); A_(s.L, nv); A_(s.Lrnd, nv); A_(s.Lcls, nv);
+    A_(s.ord, npow);
+    A_(s.tag_parent, (size_t)s.tag_cap); A_(s.tag_fid, (size_t)s.tag_cap);
+    A_(s.ev, (size_t)s.ev_cap * 16); A_(s.ev_rep, (size_t)s.ev_cap * 16); A_(s.ev_ids, (size_t)s.ev_ids_cap);
+    A_(s.front_birth, (size_t)s.front_cap); A_(s.front_death, (size_t)s.front_cap);
+    A_(s.lp, (size_t)s.lp_cap * 8); A_(s.lp_he, (size_t)s.lp_he_cap * 2); A_(s.lp_pts, (size_t)s.lp_he_cap * 3);
+    A_(s.tn, (size_t)s.lp_cap * 4);
+    A_(s.wck, 64 * 64);
+    A_(s.wseg, (size_t)s.lp_he_cap);
+    A_(s.ctl, 1);
+#undef A_
+    return e;
+}
+
+// Post-pass scratch: event chunks of kPostChunk events (walk checkpoints and
+// counts), the fill buffer of the Reeb positions and the tunnel paths.  One
+// event's fill needs the next power of two of 3 x (its loops' total length)
+// entries; the loops are disjoint sets of crossed edges, so that is below
+// 3 * nnz; a tunnel path has at most 2 * nv + 1 vertices.  A workspace of
+// post_bytes() therefore always completes the post-passes, chunk by chunk.
+constexpr int kPostChunk = 256;
+static size_t post_fill_entries(const vls_mesh *m) {
+    return (size_t)std::max<int64_t>(3 * m->nnz, 2 * m->nv + 2) + 16;
+}
+static size_t post_bytes(const vls_mesh *m) {
+    const size_t C = kPostChunk;
+    const size_t ntn = (size_t)(2 * std::max<int64_t>(0, m->euler_genus) + 64);
+    return DevArena::padded((C + 1) * 8) * 2 + DevArena::padded(C * 16 * 64 * 4) + DevArena::padded(C * 16 * 4 * 8) +
+           DevArena::padded(C * 3 * 8) + DevArena::padded((ntn + 1) * 8) * 2 + DevArena::padded(ntn * 8) +
+           DevArena::padded(post_fill_entries(m) * 4);
+}
+
+// per-mesh device run state of vls_run / vls_batch_run (allocated at the
+// first run, reused)
+struct RunBuffers {
+    DevArena arena;
+    DState s{};
+    ~RunBuffers() { arena.release(); }
+};
+
+// device bytes of one run's state on mesh m (the server's HBM admission
+// charges a request this much plus its checkpoints)
+static size_t run_buffer_bytes(const vls_mesh *m) {
+    DevArena A;
+    A.mode = DevArena::COUNT;
+    DState s;
+    (void)alloc_state(m, A, s);
+    return A.used;
+}
+
+static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
+    auto rb = std::make_unique<RunBuffers>();
+    hipError_t e = alloc_state(m, rb->arena, rb->s);
     if (e != hipSuccess) return set_err(m->ctx, VLS_E_OUT_OF_MEMORY, "device allocation failed: %s", hipGetErrorString(e));
-    rb->ord_cap = (int64_t)npow;
     *out = rb.release();
     return VLS_OK;
 }
@@ -445,21 +485,17 @@ static vls_status fetch_results(vls_result *r) {
     if (pd.mesh && pd.mesh->pending == r) pd.mesh->pending = nullptr;
     const DState &s = pd.s;
     const Ctl &c = pd.c;
-    hipStream_t stream = ctx->stream;
+    hipStream_t stream = pd.stream;
     const int64_t nv = r->nv;
-    const int nev = c.n_events, ntn = c.n_tunnels;
+    const int nev = c.n_events;
     (void)hipSetDevice(ctx->device);
     r->ev.resize((size_t)nev * 16);
     r->ev_ids.resize((size_t)c.ev_ids_used);
-    r->node_pos.resize((size_t)nev * 3);
     r->front_birth.resize(c.next_front);
     r->front_death.resize(c.next_front);
     r->lp.resize((size_t)c.n_loops * 8);
     r->lp_he.resize((size_t)c.lp_he_used * 2);
     r->lp_pts.resize((size_t)c.lp_he_used * 3);
-    r->tn.resize((size_t)ntn * 4);
-    r->tn_v.resize(ntn ? (size_t)r->tn_off[ntn] : 0);
-    r->tn_len.resize(ntn);
     std::vector<uint64_t> key(nv);
     r->parent.resize(nv);
     r->rho_final.resize(nv);
@@ -468,15 +504,11 @@ static vls_status fetch_results(vls_result *r) {
     };
     HIPCHK(ctx, cp(r->ev.data(), s.ev, r->ev.size() * 8));
     HIPCHK(ctx, cp(r->ev_ids.data(), s.ev_ids, r->ev_ids.size() * 8));
-    if (nev) HIPCHK(ctx, cp(r->node_pos.data(), pd.dpos, r->node_pos.size() * 8));
     HIPCHK(ctx, cp(r->front_birth.data(), s.front_birth, r->front_birth.size() * 4));
     HIPCHK(ctx, cp(r->front_death.data(), s.front_death, r->front_death.size() * 4));
     HIPCHK(ctx, cp(r->lp.data(), s.lp, r->lp.size() * 8));
     HIPCHK(ctx, cp(r->lp_he.data(), s.lp_he, r->lp_he.size() * 4));
     HIPCHK(ctx, cp(r->lp_pts.data(), s.lp_pts, r->lp_pts.size() * 8));
-    HIPCHK(ctx, cp(r->tn.data(), s.tn, r->tn.size() * 4));
-    if (ntn) HIPCHK(ctx, cp(r->tn_v.data(), pd.dtn, r->tn_v.size() * 4));
-    if (ntn) HIPCHK(ctx, cp(r->tn_len.data(), pd.dtlen, ntn * 8));
     HIPCHK(ctx, cp(key.data(), s.key, nv * 8));
     HIPCHK(ctx, cp(r->parent.data(), s.parent, nv * 4));
     const int64_t fin = c.steps;
@@ -487,7 +519,6 @@ static vls_status fetch_results(vls_result *r) {
         HIPCHK(ctx, cp(r->ckpt.data(), s.ckpt, r->ckpt.size() * 8));
     }
     HIPCHK(ctx, hipStreamSynchronize(stream));
-    for (void *q : {pd.dpos, pd.dtn, pd.dtlen}) if (q) (void)hipFree(q);
     for (void *q : pd.tmp_allocs) (void)hipFree(q);
     pd.tmp_allocs.clear();
     r->step.resize(nv);
@@ -506,7 +537,22 @@ static vls_status fetch_results(vls_result *r) {
     return VLS_OK;
 }
 
-static vls_status ensure(const vls_result *r) { return fetch_results(const_cast<vls_result *>(r)); }
+static vls_status wait_launched(vls_result *r);
+
+// statuses with which a run still produces a result (partial for a stall)
+static bool is_run_status(vls_status st) {
+    return st == VLS_E_STALLED || st == VLS_E_SEED_INVALID || st == VLS_E_INVARIANT || st == VLS_E_CAPACITY;
+}
+
+static vls_status ensure(const vls_result *r) {
+    vls_result *q = const_cast<vls_result *>(r);
+    if (q->failed) return q->launch_status;
+    if (q->launched) {
+        vls_status st = wait_launched(q);
+        if (st != VLS_OK && !is_run_status(st)) return st;
+    }
+    return fetch_results(q);
+}
 
 extern "C" {
 
@@ -584,23 +630,33 @@ static uint64_t splitmix64(uint64_t x) {
 struct RunPrep {
     vls_mesh *m = nullptr;
     bool priv = false;          // device state owned by the caller (server request), not by the mesh
+    bool ws = false;            // run state carved from a caller workspace: nothing allocated
+    hipStream_t stream = nullptr;
     DState s{};
     DParams dp{};
     int64_t seed = 0;
     bool rec_field = false;
     std::vector<void *> tmp_allocs;
+    DevArena post;              // post-pass scratch: the workspace's tail (ws) or hipMalloc
+    vls_params params{};        // vls_run_async: parameters kept for the wait
+    std::vector<int64_t> ckpt;  // vls_run_async: checkpoint list kept for the wait
+    int grid = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
     ~RunPrep() {
         for (void *q : tmp_allocs) (void)hipFree(q);
+        post.release();
         for (hipEvent_t e : {e0, e1, e2, e3}) if (e) (void)hipEventDestroy(e);
     }
 };
 
-// checks, device buffers, parameters; enqueues init + seed on the stream
+// checks, device buffers, parameters; enqueues init + seed on rp.stream.
+// priv: the caller's run state (server request); ws: a workspace arena the
+// run state, checkpoints and post-pass scratch are carved from (no
+// allocation, no events).
 static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p, RunPrep &rp,
-                              RunBuffers *priv = nullptr) {
+                              RunBuffers *priv = nullptr, DevArena *ws = nullptr) {
     if (p->struct_size != sizeof(vls_params)) return set_err(ctx, VLS_E_INVALID_ARG, "vls_params.struct_size mismatch");
-    if (!priv && m->pending) {
+    if (!priv && !ws && m->pending) {
         vls_status fs = fetch_results(m->pending);
         if (fs) return fs;
     }
@@ -614,10 +670,15 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     if (p->block != 0 && p->block != 256) return set_err(ctx, VLS_E_INVALID_ARG, "block must be 256");
     if ((p->flags & VLS_DENSE_FIELD) && nv >= (int64_t)1 << 29)
         return set_err(ctx, VLS_E_INVALID_ARG, "VLS_DENSE_FIELD needs fewer than 2^29 vertices");
+    if (p->n_ckpt < 0) return set_err(ctx, VLS_E_INVALID_ARG, "n_ckpt");
     rp.m = m;
     rp.seed = seed;
     rp.rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
-    if (priv) {
+    if (!rp.stream) rp.stream = ctx->stream;
+    if (ws) {
+        rp.ws = true;
+        if (alloc_state(m, *ws, rp.s) != hipSuccess) return set_err(ctx, VLS_E_BUFFER_TOO_SMALL, "workspace too small");
+    } else if (priv) {
         rp.priv = true;
         rp.s = priv->s;
     } else {
@@ -628,20 +689,33 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
         rp.s = m->rb->s;
     }
     DState &s = rp.s;
-    hipStream_t stream = ctx->stream;
+    hipStream_t stream = rp.stream;
     s.n_ckpt = 0;
     s.ckpt = nullptr;
     s.ckpt_steps = nullptr;
     if (rp.rec_field) {
-        void *a = nullptr, *b = nullptr;
-        if (hipMalloc(&a, (size_t)p->n_ckpt * nv * sizeof(double)) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
-        rp.tmp_allocs.push_back(a);
-        if (hipMalloc(&b, (size_t)p->n_ckpt * sizeof(int64_t)) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
-        rp.tmp_allocs.push_back(b);
-        s.ckpt = (double *)a;
-        s.ckpt_steps = (const int64_t *)b;
+        double *a = nullptr;
+        int64_t *b = nullptr;
+        if (ws) {
+            if (ws->get(&a, (size_t)p->n_ckpt * nv) != hipSuccess || ws->get(&b, (size_t)p->n_ckpt) != hipSuccess)
+                return set_err(ctx, VLS_E_BUFFER_TOO_SMALL, "workspace too small for the checkpoints");
+        } else {
+            if (hipMalloc(&a, (size_t)p->n_ckpt * nv * sizeof(double)) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
+            rp.tmp_allocs.push_back(a);
+            if (hipMalloc(&b, (size_t)p->n_ckpt * sizeof(int64_t)) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "checkpoint buffers");
+            rp.tmp_allocs.push_back(b);
+        }
+        s.ckpt = a;
+        s.ckpt_steps = b;
         s.n_ckpt = p->n_ckpt;
         HIPCHK(ctx, hipMemcpyAsync(b, p->ckpt_steps, (size_t)p->n_ckpt * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    }
+    if (ws) {
+        // the rest of the workspace is the post-pass scratch
+        rp.post.mode = DevArena::CARVE;
+        rp.post.base = ws->base + ws->used;
+        rp.post.cap = ws->left();
+        if (rp.post.cap < post_bytes(m)) return set_err(ctx, VLS_E_BUFFER_TOO_SMALL, "workspace too small for the post-passes");
     }
     DParams &dp = rp.dp;
     const double dt = p->dt_mode == 1 ? 0.25 / (double)m->dmax : 50.0 / (double)m->dmax;
@@ -658,106 +732,182 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     dp.coherent = (p->flags & VLS_COHERENT_SHARING) ? 1 : 0;
     dp.lockstep = (p->flags & VLS_LOCKSTEP) ? 1 : 0;
     dp.dense = (p->flags & VLS_DENSE_FIELD) ? 1 : 0;
-    HIPCHK(ctx, hipEventCreate(&rp.e0));
-    HIPCHK(ctx, hipEventCreate(&rp.e1));
-    HIPCHK(ctx, hipEventCreate(&rp.e2));
-    HIPCHK(ctx, hipEventCreate(&rp.e3));
-    HIPCHK(ctx, hipEventRecord(rp.e0, stream));
-    HIPCHK(ctx, hipMemsetAsync(s.ctl, 0, sizeof(Ctl), stream));
+    if (!ws) {
+        HIPCHK(ctx, hipEventCreate(&rp.e0));
+        HIPCHK(ctx, hipEventCreate(&rp.e1));
+        HIPCHK(ctx, hipEventCreate(&rp.e2));
+        HIPCHK(ctx, hipEventCreate(&rp.e3));
+        HIPCHK(ctx, hipEventRecord(rp.e0, stream));
+    }
     HIPCHK(ctx, launch_init(m->d, s, m->nnz, stream));
     HIPCHK(ctx, launch_seed(m->d, s, dp, stream));
-    HIPCHK(ctx, hipEventRecord(rp.e1, stream));
+    if (!ws) HIPCHK(ctx, hipEventRecord(rp.e1, stream));
     return VLS_OK;
 }
 
-// after the step kernel: post-passes, summary, result object (bulk results
-// deferred until fetched)
-static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p, int grid, int block,
-                             double kernel_ms_override, std::unique_ptr<vls_result> &rout) {
+// Reeb positions and tunnel paths of a finished run, into r (host), with
+// post-pass scratch from rp.post: one chunk of events / tunnels when the
+// scratch is hipMalloc'ed, as many chunks as the workspace needs otherwise.
+static vls_status post_passes(vls_context *ctx, RunPrep &rp, const Ctl &c, vls_result &r) {
     vls_mesh *m = rp.m;
     const DState &s = rp.s;
-    hipStream_t stream = ctx->stream;
+    hipStream_t stream = rp.stream;
+    DevArena &A = rp.post;
+    const bool carve = A.mode == DevArena::CARVE;
+    const int nev = c.n_events, ntn = c.n_tunnels;
+    r.node_pos.assign((size_t)nev * 3, 0.0);
+    r.tn.resize((size_t)ntn * 4);
+    r.tn_off.assign(ntn + 1, 0);
+    r.tn_len.assign(ntn, 0.0);
+    const size_t mark = A.used;
+    auto toolarge = [&](const char *what) {
+        return set_err(ctx, VLS_E_CAPACITY, "post-pass scratch too small for %s", what);
+    };
+    if (nev > 0) {
+        const int C = carve ? std::min(nev, kPostChunk) : nev;
+        int64_t *dcnt = nullptr, *doff = nullptr, *dmeta = nullptr;
+        int32_t *dck = nullptr;
+        double *dpos = nullptr;
+        if (A.get(&dcnt, C + 1) || A.get(&doff, C + 1) || A.get(&dck, (size_t)C * 16 * 64) ||
+            A.get(&dmeta, (size_t)C * 16 * 4) || A.get(&dpos, (size_t)C * 3))
+            return carve ? toolarge("event chunks") : set_err(ctx, VLS_E_OUT_OF_MEMORY, "post-pass buffers");
+        int32_t *dbuf = nullptr;
+        size_t fill_cap = 0;   // entries
+        if (carve) {
+            fill_cap = A.left() / 4 > 64 ? A.left() / 4 - 64 : 0;
+            dbuf = (int32_t *)(A.base + A.used);
+        }
+        std::vector<int64_t> cnt(C + 1, 0), off;
+        for (int c0 = 0; c0 < nev; c0 += C) {
+            const int nc = std::min(C, nev - c0);
+            HIPCHK(ctx, launch_reeb_count(m->d, s, c0, nc, dcnt, dck, dmeta, stream));
+            HIPCHK(ctx, hipMemcpyAsync(cnt.data(), dcnt, nc * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+            HIPCHK(ctx, hipStreamSynchronize(stream));
+            std::vector<int64_t> np(nc);
+            int64_t tot = 0;
+            for (int i = 0; i < nc; ++i) {
+                int64_t q = 1;
+                while (q < cnt[i]) q <<= 1;
+                np[i] = q;
+                tot += q;
+            }
+            if (!carve) {
+                // one fill over the whole chunk
+                if (A.get(&dbuf, (size_t)tot + 16)) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "post-pass fill buffer");
+                fill_cap = (size_t)tot + 16;
+            }
+            for (int a = 0; a < nc;) {
+                int b = a;
+                int64_t used = 0;
+                while (b < nc && used + np[b] <= (int64_t)fill_cap) used += np[b++];
+                if (b == a) return toolarge("one event's front triangles");
+                off.assign(b - a + 1, 0);
+                for (int i = a; i < b; ++i) off[i - a + 1] = off[i - a] + np[i];
+                HIPCHK(ctx, hipMemcpyAsync(doff, off.data(), (b - a + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+                HIPCHK(ctx, launch_reeb_fill(m->d, s, c0 + a, b - a, doff, dcnt + a, dck + (size_t)a * 16 * 64,
+                                             dmeta + (size_t)a * 16 * 4, dbuf, stream));
+                HIPCHK(ctx, launch_reeb_mean(m->d, b - a, doff, dcnt + a, dbuf, dpos + 3 * a, stream));
+                // the offsets are re-uploaded by the next sub-chunk: wait for this one
+                HIPCHK(ctx, hipStreamSynchronize(stream));
+                a = b;
+            }
+            HIPCHK(ctx, hipMemcpyAsync(r.node_pos.data() + 3 * (size_t)c0, dpos, (size_t)nc * 3 * sizeof(double),
+                                       hipMemcpyDeviceToHost, stream));
+        }
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+    }
+    if (!carve) A.release();
+    A.used = mark;
+    if (ntn > 0) {
+        HIPCHK(ctx, hipMemcpyAsync(r.tn.data(), s.tn, (size_t)ntn * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        int64_t *dtcnt = nullptr, *dtoff = nullptr;
+        double *dtlen = nullptr;
+        if (A.get(&dtcnt, ntn + 1) || A.get(&dtoff, ntn + 1) || A.get(&dtlen, ntn))
+            return carve ? toolarge("tunnel counts") : set_err(ctx, VLS_E_OUT_OF_MEMORY, "post-pass buffers");
+        std::vector<int64_t> tcnt(ntn + 1, 0);
+        HIPCHK(ctx, launch_tunnel_count(s, ntn, dtcnt, stream));
+        HIPCHK(ctx, hipMemcpyAsync(tcnt.data(), dtcnt, ntn * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        for (int i = 0; i < ntn; ++i) r.tn_off[i + 1] = r.tn_off[i] + tcnt[i];
+        r.tn_v.resize((size_t)r.tn_off[ntn]);
+        int32_t *dtn = nullptr;
+        size_t cap = 0;
+        if (carve) {
+            cap = A.left() / 4 > 64 ? A.left() / 4 - 64 : 0;
+            dtn = (int32_t *)(A.base + A.used);
+        } else {
+            if (A.get(&dtn, (size_t)r.tn_off[ntn] + 16)) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "tunnel buffer");
+            cap = (size_t)r.tn_off[ntn] + 16;
+        }
+        std::vector<int64_t> toff;
+        for (int a = 0; a < ntn;) {
+            int b = a;
+            while (b < ntn && r.tn_off[b + 1] - r.tn_off[a] <= (int64_t)cap) ++b;
+            if (b == a) return toolarge("one tunnel path");
+            toff.assign(b - a + 1, 0);
+            for (int i = a; i <= b; ++i) toff[i - a] = r.tn_off[i] - r.tn_off[a];
+            HIPCHK(ctx, hipMemcpyAsync(dtoff, toff.data(), (b - a + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+            HIPCHK(ctx, launch_tunnel_fill(m->d, s, a, b - a, dtoff, dtn, dtlen + a, stream));
+            HIPCHK(ctx, hipMemcpyAsync(r.tn_v.data() + r.tn_off[a], dtn, (size_t)(r.tn_off[b] - r.tn_off[a]) * 4,
+                                       hipMemcpyDeviceToHost, stream));
+            HIPCHK(ctx, hipStreamSynchronize(stream));
+            a = b;
+        }
+        HIPCHK(ctx, hipMemcpyAsync(r.tn_len.data(), dtlen, ntn * sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        r.tn_pts.resize(r.tn_v.size() * 3);
+        for (size_t q = 0; q < r.tn_v.size(); ++q)
+            std::memcpy(r.tn_pts.data() + 3 * q, m->xyz.data() + 3 * (size_t)r.tn_v[q], 3 * sizeof(double));
+    }
+    if (!carve) A.release();
+    A.used = mark;
+    return VLS_OK;
+}
+
+// after the step kernel: post-passes, summary, result object r (bulk
+// results deferred until fetched unless copied here)
+static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p, int grid, int block,
+                             double kernel_ms_override, vls_result &R) {
+    vls_mesh *m = rp.m;
+    const DState &s = rp.s;
+    hipStream_t stream = rp.stream;
     const int64_t nv = m->nv;
     Ctl c{};
     HIPCHK(ctx, hipMemcpyAsync(&c, s.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     HIPCHK(ctx, hipStreamSynchronize(stream));
-    const int nev = c.n_events, ntn = c.n_tunnels;
-    auto r = std::make_unique<vls_result>();
+    vls_result *r = &R;
     r->nv = nv;
-    std::vector<int64_t> cnt(std::max(nev, ntn) + 1, 0), off;
-    void *dcnt = nullptr, *doff = nullptr, *dbuf = nullptr, *dpos = nullptr, *dtn = nullptr;
-    void *dtcnt = nullptr, *dtoff = nullptr, *dtlen = nullptr, *dck = nullptr, *dmeta = nullptr;
-    struct Guard {
-        std::vector<void **> ptrs;
-        ~Guard() { for (void **q : ptrs) if (*q) (void)hipFree(*q); }
-    } guard{{&dcnt, &doff, &dbuf, &dtcnt, &dtoff, &dck, &dmeta}};
-    if (nev > 0) {
-        HIPCHK(ctx, hipMalloc(&dcnt, (nev + 1) * sizeof(int64_t)));
-        HIPCHK(ctx, hipMalloc(&doff, (nev + 1) * sizeof(int64_t)));
-        // per event and involved loop (at most 16): 64 walk checkpoints and
-        // {length, stride, checkpoints, offset}
-        HIPCHK(ctx, hipMalloc(&dck, (size_t)nev * 16 * 64 * sizeof(int32_t)));
-        HIPCHK(ctx, hipMalloc(&dmeta, (size_t)nev * 16 * 4 * sizeof(int64_t)));
-        HIPCHK(ctx, launch_reeb_count(m->d, s, nev, (int64_t *)dcnt, (int32_t *)dck, (int64_t *)dmeta, stream));
-        HIPCHK(ctx, hipMemcpyAsync(cnt.data(), dcnt, nev * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-        HIPCHK(ctx, hipStreamSynchronize(stream));
-        off.assign(nev + 1, 0);
-        for (int i = 0; i < nev; ++i) {
-            int64_t np = 1;
-            while (np < cnt[i]) np <<= 1;
-            off[i + 1] = off[i] + np;
-        }
-        HIPCHK(ctx, hipMemcpyAsync(doff, off.data(), (nev + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-        HIPCHK(ctx, hipMalloc(&dbuf, off[nev] * sizeof(int32_t) + 16));
-        HIPCHK(ctx, hipMalloc(&dpos, nev * 3 * sizeof(double)));
-        HIPCHK(ctx, launch_reeb_fill(m->d, s, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dck,
-                                     (int64_t *)dmeta, (int32_t *)dbuf, stream));
-        HIPCHK(ctx, launch_reeb_mean(m->d, nev, (int64_t *)doff, (int64_t *)dcnt, (int32_t *)dbuf, (double *)dpos, stream));
-    }
-    std::vector<int64_t> tcnt(ntn + 1, 0);
-    if (ntn > 0) {
-        HIPCHK(ctx, hipMalloc(&dtcnt, (ntn + 1) * sizeof(int64_t)));
-        HIPCHK(ctx, hipMalloc(&dtoff, (ntn + 1) * sizeof(int64_t)));
-        HIPCHK(ctx, launch_tunnel_count(s, ntn, (int64_t *)dtcnt, stream));
-        HIPCHK(ctx, hipMemcpyAsync(tcnt.data(), dtcnt, ntn * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-        HIPCHK(ctx, hipStreamSynchronize(stream));
-        r->tn_off.assign(ntn + 1, 0);
-        for (int i = 0; i < ntn; ++i) r->tn_off[i + 1] = r->tn_off[i] + tcnt[i];
-        HIPCHK(ctx, hipMemcpyAsync(dtoff, r->tn_off.data(), (ntn + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-        HIPCHK(ctx, hipMalloc(&dtn, r->tn_off[ntn] * sizeof(int32_t) + 16));
-        HIPCHK(ctx, hipMalloc(&dtlen, ntn * sizeof(double)));
-        HIPCHK(ctx, launch_tunnel_fill(m->d, s, ntn, (int64_t *)dtoff, (int32_t *)dtn, (double *)dtlen, stream));
-    }
-    HIPCHK(ctx, hipEventRecord(rp.e3, stream));
-    HIPCHK(ctx, hipStreamSynchronize(stream));
+    if (vls_status ps = post_passes(ctx, rp, c, *r)) return ps;
     float ms_k = 0.f, ms_t = 0.f;
-    (void)hipEventElapsedTime(&ms_k, rp.e1, rp.e2);
-    (void)hipEventElapsedTime(&ms_t, rp.e0, rp.e3);
+    if (!rp.ws) {
+        HIPCHK(ctx, hipEventRecord(rp.e3, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        (void)hipEventElapsedTime(&ms_k, rp.e1, rp.e2);
+        (void)hipEventElapsedTime(&ms_t, rp.e0, rp.e3);
+    }
     // bulk results stay on the device until fetched
     Pending &pd = r->pend;
     pd.active = true;
     pd.ctx = ctx;
-    pd.mesh = rp.priv ? nullptr : m;
+    pd.mesh = (rp.priv || rp.ws) ? nullptr : m;
+    pd.stream = stream;
     pd.s = s;
     pd.c = c;
-    pd.dpos = dpos;
-    pd.dtn = dtn;
-    pd.dtlen = dtlen;
     pd.tmp_allocs = rp.tmp_allocs;
     rp.tmp_allocs.clear();
     pd.rec_field = rp.rec_field;
     if (rp.rec_field) r->ckpt_steps.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
-    if (!rp.priv) m->pending = r.get();
+    if (pd.mesh) m->pending = r;
     r->seed_xyz.assign(m->xyz.begin() + 3 * rp.seed, m->xyz.begin() + 3 * rp.seed + 3);
     vls_summary &S = r->sum;
     S.n_handles = (int32_t)c.gsum_h;
-    S.n_tunnels = ntn;
+    S.n_tunnels = c.n_tunnels;
     S.euler_genus = m->euler_genus;
     S.swept_genus = (int32_t)((2 - c.chi - c.b) / 2);
-    S.reeb_nodes = nev + 1;
+    S.reeb_nodes = c.n_events + 1;
     S.reeb_edges = c.next_front;
     S.n_degenerate = c.n_degenerate;
-    S.n_events = nev;
+    S.n_events = c.n_events;
     S.steps = c.steps;
     S.active_vertex_updates = c.active_updates;
     S.active_degree_sum = c.active_deg;
@@ -788,11 +938,12 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
                 (long long)c.n_inside, (long long)nv);
     else if (rs == VLS_E_SEED_INVALID)
         set_err(ctx, rs, "seed region around vertex %lld is not a disk-like region", (long long)rp.seed);
-    if (rp.priv || !(p->flags & VLS_DEFER_RESULTS)) {
-        vls_status fs = fetch_results(r.get());
+    // results of caller-owned state (server requests, workspaces) are
+    // copied now: that state is not kept for a later fetch
+    if (rp.priv || rp.ws || !(p->flags & VLS_DEFER_RESULTS)) {
+        vls_status fs = fetch_results(r);
         if (fs) return fs;
     }
-    rout = std::move(r);
     return rs;
 }
 
@@ -841,6 +992,22 @@ void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp, int64_t
 
 extern "C" {
 
+// launch shape of a one-mesh run: p->grid if set, else about one workgroup
+// per 34k vertices, 16..128.  The field's share of a step grows with the
+// band, but every field workgroup also loads the memory system the
+// topology's dependent chains run through: on the 256^3 pretzel 64
+// workgroups beat 99 (456 against 491 ms per pass) although the field alone
+// runs faster at 99.  The dense step streams the whole mesh: every
+// co-resident workgroup.  0 when the occupancy query fails.
+static int solo_grid(const vls_mesh *m, const vls_params *p) {
+    const size_t lds = step_lds_bytes(256, m->dmax);
+    const int maxg = max_coresident_blocks(256, lds);
+    if (maxg <= 0) return 0;
+    int grid = p->grid > 0 ? p->grid : (int)std::min<int64_t>(128, std::max<int64_t>(16, m->nv / 34000));
+    if (p->grid <= 0 && (p->flags & VLS_DENSE_FIELD)) grid = maxg;
+    return std::min(grid, maxg);
+}
+
 vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vls_result **out) {
     if (!ctx || !mc || !p || !out) return set_err(ctx, VLS_E_INVALID_ARG, "null argument");
     *out = nullptr;
@@ -850,25 +1017,111 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     vls_status st = prepare_run(ctx, m, p, rp);
     if (st) return st;
     const int block = 256;
-    const size_t lds = step_lds_bytes(block, m->dmax);
-    const int maxg = max_coresident_blocks(block, lds);
-    if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
-    // default launch: about one workgroup per 34k vertices, 16..128.  The
-    // field's share of a step grows with the band, but every field
-    // workgroup also loads the memory system the topology's dependent
-    // chains run through: on the 256^3 pretzel 64 workgroups beat 99 (456
-    // against 491 ms per pass) although the field alone runs faster at 99.
-    int grid = p->grid > 0 ? p->grid : (int)std::min<int64_t>(128, std::max<int64_t>(16, m->nv / 34000));
-    if (p->grid <= 0 && (p->flags & VLS_DENSE_FIELD)) grid = maxg;   // the dense step streams the whole mesh
-    if (grid > maxg) grid = maxg;
+    const int grid = solo_grid(m, p);
+    if (grid <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
     hipError_t le = launch_steps(m->d, rp.s, rp.dp, grid, block, ctx->stream);
     if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le));
     HIPCHK(ctx, hipEventRecord(rp.e2, ctx->stream));
-    std::unique_ptr<vls_result> r;
-    vls_status rs = finish_run(ctx, rp, p, grid, block, -1.0, r);
-    if (!r) return rs;
+    auto r = std::make_unique<vls_result>();
+    vls_status rs = finish_run(ctx, rp, p, grid, block, -1.0, *r);
+    if (rs != VLS_OK && !is_run_status(rs)) {
+        if (m->pending == r.get()) m->pending = nullptr;
+        return rs;
+    }
     *out = r.release();
     return rs;
+}
+
+vls_status vls_workspace_size(const vls_mesh *m, const vls_params *p, size_t *bytes) {
+    if (!m || !p || !bytes) return VLS_E_INVALID_ARG;
+    if (p->struct_size != sizeof(vls_params)) return VLS_E_INVALID_ARG;
+    DevArena A;
+    A.mode = DevArena::COUNT;
+    DState s;
+    (void)alloc_state(m, A, s);
+    if ((p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps) {
+        double *a;
+        int64_t *b;
+        (void)A.get(&a, (size_t)p->n_ckpt * (size_t)m->nv);
+        (void)A.get(&b, (size_t)p->n_ckpt);
+    }
+    *bytes = A.used + post_bytes(m);
+    return VLS_OK;
+}
+
+}  // extern "C"
+
+// enqueues a whole pass on `stream` with every device buffer carved from
+// [base, base + bytes); the result waits for it on first use
+static vls_status run_in_workspace(vls_context *ctx, const vls_mesh *mc, const vls_params *p, void *base,
+                                   size_t bytes, hipStream_t stream, vls_result **out) {
+    if (!ctx || !mc || !p || !out || !base) return set_err(ctx, VLS_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (((uintptr_t)base & 255) != 0) return set_err(ctx, VLS_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    vls_mesh *m = const_cast<vls_mesh *>(mc);
+    if (p->struct_size != sizeof(vls_params)) return set_err(ctx, VLS_E_INVALID_ARG, "vls_params.struct_size mismatch");
+    size_t need = 0;
+    (void)vls_workspace_size(m, p, &need);
+    if (bytes < need)
+        return set_err(ctx, VLS_E_BUFFER_TOO_SMALL, "workspace of %zu bytes, %zu needed", bytes, need);
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    const int grid = solo_grid(m, p);
+    if (grid <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
+    auto rp = std::make_unique<RunPrep>();
+    rp->stream = stream ? stream : ctx->stream;
+    rp->params = *p;
+    const bool rec = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
+    if (rec) rp->ckpt.assign(p->ckpt_steps, p->ckpt_steps + p->n_ckpt);
+    rp->params.ckpt_steps = rec ? rp->ckpt.data() : nullptr;
+    rp->params.n_ckpt = rec ? p->n_ckpt : 0;
+    rp->grid = grid;
+    DevArena ws;
+    ws.mode = DevArena::CARVE;
+    ws.base = (char *)base;
+    ws.cap = bytes;
+    vls_status st = prepare_run(ctx, m, &rp->params, *rp, nullptr, &ws);
+    if (st) return st;
+    hipError_t le = launch_steps(m->d, rp->s, rp->dp, grid, 256, rp->stream);
+    if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le));
+    auto r = std::make_unique<vls_result>();
+    r->pend.ctx = ctx;
+    r->launched = rp.release();
+    *out = r.release();
+    return VLS_OK;
+}
+
+// the second half of a workspace run: the step kernel's end, post-passes,
+// every result copied to the host; the workspace is free afterwards
+static vls_status wait_launched(vls_result *r) {
+    RunPrep *rp = r->launched;
+    if (!rp) return r->launch_status;
+    r->launched = nullptr;
+    std::unique_ptr<RunPrep> own(rp);
+    vls_context *ctx = r->pend.ctx;
+    (void)hipSetDevice(ctx->device);
+    vls_status rs = finish_run(ctx, *rp, &rp->params, rp->grid, 256, -1.0, *r);
+    if (rs != VLS_OK && !is_run_status(rs)) {
+        // the device work may still be queued: let it end before the
+        // workspace is given back
+        (void)hipStreamSynchronize(rp->stream);
+        r->failed = true;
+    }
+    r->launch_status = rs;
+    return rs;
+}
+
+extern "C" {
+
+vls_status vls_run_async(vls_context *ctx, const vls_mesh *m, const vls_params *p, void *d_workspace,
+                         size_t bytes, void *hip_stream, vls_result **out) {
+    return run_in_workspace(ctx, m, p, d_workspace, bytes, (hipStream_t)hip_stream, out);
+}
+
+vls_status vls_result_wait(vls_result *r) {
+    if (!r) return VLS_E_INVALID_ARG;
+    if (r->failed) return r->launch_status;
+    if (r->launched) return wait_launched(r);
+    return r->sum.run_status;
 }
 
 vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *meshes, const vls_params *per_mesh,
@@ -942,9 +1195,11 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
     vls_status first = VLS_OK;
     for (int32_t i = 0; i < n; ++i) {
         HIPCHK(ctx, hipEventRecord(preps[i].e2, stream));
-        std::unique_ptr<vls_result> r;
-        vls_status rs = finish_run(ctx, preps[i], &per_mesh[i], grid, 256, ms_b, r);
-        if (!r) {
+        auto r = std::make_unique<vls_result>();
+        vls_status rs = finish_run(ctx, preps[i], &per_mesh[i], grid, 256, ms_b, *r);
+        if (rs != VLS_OK && !is_run_status(rs)) {
+            vls_mesh *mi = const_cast<vls_mesh *>(meshes[i]);
+            if (mi->pending == r.get()) mi->pending = nullptr;
             for (int32_t j = 0; j < i; ++j) { (void)vls_result_destroy(out[j]); out[j] = nullptr; }
             return rs;
         }
@@ -956,6 +1211,12 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
 
 vls_status vls_result_summary(const vls_result *r, vls_summary *s) {
     if (!r || !s) return VLS_E_INVALID_ARG;
+    vls_result *q = const_cast<vls_result *>(r);
+    if (q->launched) {
+        vls_status st = wait_launched(q);
+        if (st != VLS_OK && !is_run_status(st)) return st;
+    }
+    if (q->failed) return q->launch_status;
     *s = r->sum;
     return VLS_OK;
 }
@@ -1025,7 +1286,7 @@ vls_status vls_result_loop(const vls_result *r, int32_t kind, int32_t i, int64_t
         for (int64_t q = 0; q < n; ++q) {
             const int32_t a = r->tn_v[off + q], b = r->tn_v[off + (q + 1) % n];
             if (edges_uv) { edges_uv[2 * q] = a; edges_uv[2 * q + 1] = b; }
-            if (pts) std::memcpy(pts + 3 * q, r->mesh_xyz.data() + 3 * (int64_t)a, 3 * sizeof(double));
+            if (pts) std::memcpy(pts + 3 * q, r->tn_pts.data() + 3 * (off + q), 3 * sizeof(double));
         }
         return VLS_OK;
     }
@@ -1115,13 +1376,19 @@ vls_status vls_result_fetch(vls_result *r) {
 
 vls_status vls_result_destroy(vls_result *r) {
     if (!r) return VLS_E_INVALID_ARG;
+    if (r->launched) {
+        // enqueued and never waited for: let the device work end first (it
+        // uses the caller's workspace)
+        (void)hipStreamSynchronize(r->launched->stream);
+        delete r->launched;
+        r->launched = nullptr;
+    }
     Pending &pd = r->pend;
     if (pd.active) {
         // never fetched: drop the device copies without reading them
         pd.active = false;
         if (pd.mesh && pd.mesh->pending == r) pd.mesh->pending = nullptr;
         (void)hipSetDevice(pd.ctx->device);
-        for (void *q : {pd.dpos, pd.dtn, pd.dtlen}) if (q) (void)hipFree(q);
         for (void *q : pd.tmp_allocs) (void)hipFree(q);
     }
     delete r;
@@ -1212,10 +1479,11 @@ void vls_server::finish(SrvReq *q, vls_status st, vls_result *r) {
 
 // a request whose step kernel finished: post-passes, results to the host
 void vls_server::complete(SrvReq *q) {
-    std::unique_ptr<vls_result> r;
     if (hipEventRecord(q->prep->e2, ctx.stream) != hipSuccess) { finish(q, VLS_E_DEVICE, nullptr); return; }
-    vls_status rs = finish_run(&ctx, *q->prep, &q->p, 0, 256, -1.0, r);
-    finish(q, r ? rs : (rs ? rs : VLS_E_DEVICE), r.release());
+    auto r = std::make_unique<vls_result>();
+    vls_status rs = finish_run(&ctx, *q->prep, &q->p, 0, 256, -1.0, *r);
+    if (rs != VLS_OK && !is_run_status(rs)) { finish(q, rs, nullptr); return; }
+    finish(q, rs, r.release());
 }
 
 // device run state and seed initialisation of a newly admitted request
@@ -1241,6 +1509,7 @@ bool vls_server::launch_slice() {
     if (n > cap) {
         for (void *q : {dm, ds, dp, dord, dnext, ddone, dtg, dsl}) if (q) (void)hipFree(q);
         dm = ds = dp = dord = dnext = ddone = dtg = dsl = nullptr;
+        cap = 0;   // a failed allocation below is retried by the next slice
         int c = 64;
         while (c < n) c <<= 1;
         if (hipMalloc(&dm, c * sizeof(DMesh)) || hipMalloc(&ds, c * sizeof(DState)) ||
@@ -1408,19 +1677,43 @@ vls_status vls_server_stats(const vls_server *srv, int64_t *launches, int64_t *c
     return VLS_OK;
 }
 
-vls_status vls_server_destroy(vls_server *srv) {
+vls_status vls_server_shutdown(vls_server *srv) {
     if (!srv) return VLS_E_INVALID_ARG;
+    std::vector<SrvReq *> queued;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop && !srv->th.joinable()) return VLS_OK;
         srv->stop = true;
+        queued.assign(srv->queue.begin(), srv->queue.end());
         srv->queue.clear();
     }
     srv->cv.notify_all();
     if (srv->th.joinable()) srv->th.join();
+    // the scheduler has stopped after its last launch: the requests it was
+    // running and those still queued end as cancelled (their polls say so)
     (void)hipSetDevice(srv->ctx.device);
     (void)hipStreamSynchronize(srv->ctx.stream);
-    for (SrvReq *q : srv->active) { q->rb.reset(); q->prep.reset(); }
+    std::vector<SrvReq *> drop(srv->active.begin(), srv->active.end());
     srv->active.clear();
+    for (SrvReq *q : drop) { q->rb.reset(); q->prep.reset(); }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (SrvReq *q : drop) {
+        q->status = VLS_E_CANCELLED;
+        q->done = true;
+        q->t_done = Clock::now();
+        srv->used -= q->bytes;
+    }
+    for (SrvReq *q : queued) {
+        q->status = VLS_E_CANCELLED;
+        q->done = true;
+        q->t_done = Clock::now();
+    }
+    return VLS_OK;
+}
+
+vls_status vls_server_destroy(vls_server *srv) {
+    if (!srv) return VLS_E_INVALID_ARG;
+    (void)vls_server_shutdown(srv);
     for (auto &kv : srv->reqs)
         if (kv.second->res) (void)vls_result_destroy(kv.second->res);
     srv->reqs.clear();

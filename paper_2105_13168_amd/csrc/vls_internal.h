@@ -154,15 +154,15 @@ hipError_t launch_batch(const DMesh *ms, const DState *ss, const DParams *ps, co
 int max_coresident_batch(size_t lds_bytes, int occ);
 size_t batch_lds_bytes(int occ);
 size_t step_lds_bytes(int block, int dmax);
-hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt, int32_t *ck,
+hipError_t launch_reeb_count(const DMesh &m, const DState &s, int ev0, int n_events, int64_t *cnt, int32_t *ck,
                              int64_t *meta, hipStream_t st);
-hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int n_events, const int64_t *off,
+hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int ev0, int n_events, const int64_t *off,
                             const int64_t *cnt, const int32_t *ck, const int64_t *meta, int32_t *buf,
                             hipStream_t st);
 hipError_t launch_reeb_mean(const DMesh &m, int n_events, const int64_t *off, const int64_t *cnt,
                             int32_t *buf, double *pos, hipStream_t st);
 hipError_t launch_tunnel_count(const DState &s, int n_tunnels, int64_t *cnt, hipStream_t st);
-hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int n_tunnels, const int64_t *off, int32_t *out,
+hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int t0, int n_tunnels, const int64_t *off, int32_t *out,
                               double *len, hipStream_t st);
 
 }  // namespace vls

@@ -45,7 +45,7 @@ namespace vls {
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 enum { NODE_SEED = 0, NODE_SPLIT = 1, NODE_MERGE = 2, NODE_VANISH = 3, NODE_DEGENERATE = 4 };
-enum { ST_OK = 0, ST_SEED_INVALID = -6, ST_STALLED = -7, ST_CAPACITY = -11, ST_INVARIANT = -13 };
+enum { ST_OK = 0, ST_SEED_INVALID = -6, ST_STALLED = -7, ST_INVARIANT = -13, ST_CAPACITY = -14 };
 
 __device__ __forceinline__ bool rank_lt(uint64_t ka, int32_t a, uint64_t kb, int32_t b) {
     return ka < kb || (ka == kb && a < b);
@@ -138,6 +138,12 @@ __device__ __forceinline__ int32_t he_next(const DMesh &m, const uint64_t *__res
 // ---------------------------------------------------------------------------
 __global__ void k_init(DState s, int32_t nv, int64_t nnz) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // the control block starts at zero (a kernel rather than a memset node,
+    // so the run sequence holds no memset)
+    if (blockIdx.x == 0) {
+        unsigned long long *c = (unsigned long long *)s.ctl;
+        for (size_t i = threadIdx.x; i < sizeof(Ctl) / 8; i += blockDim.x) c[i] = 0ull;
+    }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride) {
         s.lid[i] = -1;
         if (i < nv) {
@@ -2373,18 +2379,21 @@ __global__ void __launch_bounds__(NT, OCC) k_batch(const DMesh *ms, const DState
                 }
                 __syncthreads();
                 if (j >= 1) phase_topo<0, CAP>(m, s, p, j, ksh, kl, lsort);
-                __syncthreads();
-                const int stop = ctl->done;
-                __syncthreads();
-                if (stop) break;
-                if (p.dense) phase_field_dense<0>(m, s, p, j + 1, 0, 1, (LDS_AS int32_t *)lsort);
-                else phase_field<0, FKB>(m, s, p, j + 1, 0, 1);
+                // field snapshot of step j (complete since the previous
+                // iteration; step j+1 writes the other buffer), taken before
+                // the stop test so that the last step's snapshot is kept too
                 for (int q = 0; q < s.n_ckpt; ++q) {
                     if (s.ckpt_steps[q] != j || j == 0) continue;
                     const double *src = (j & 1) ? s.rho1 : s.rho0;
                     double *dst = s.ckpt + (int64_t)q * m.nv;
                     for (int64_t i = threadIdx.x; i < m.nv; i += NT) dst[i] = src[i];
                 }
+                __syncthreads();
+                const int stop = ctl->done;
+                __syncthreads();
+                if (stop) break;
+                if (p.dense) phase_field_dense<0>(m, s, p, j + 1, 0, 1, (LDS_AS int32_t *)lsort);
+                else phase_field<0, FKB>(m, s, p, j + 1, 0, 1);
                 __syncthreads();
             }
         }
@@ -2478,9 +2487,11 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
 // segments in parallel.  meta[ev][q] = {length, stride, checkpoints, offset
 // of the loop's entries}; cnt[ev] = 3 * total length.
 #define RCK 64
-__global__ void k_reeb_count(DMesh m, DState s, int n_events, int64_t *cnt, int32_t *ck, int64_t *meta) {
-    const int ev = blockIdx.x;
-    if (ev >= n_events) return;
+__global__ void k_reeb_count(DMesh m, DState s, int ev0, int n_events, int64_t *cnt, int32_t *ck, int64_t *meta) {
+    // events ev0 .. ev0+n_events-1; cnt, ck, meta indexed from ev0
+    if ((int)blockIdx.x >= n_events) return;
+    const int ev = ev0 + (int)blockIdx.x;
+    const int64_t rel = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t *rec = s.ev + 16 * (int64_t)ev;
     const int32_t v = (int32_t)rec[1];
@@ -2489,7 +2500,7 @@ __global__ void k_reeb_count(DMesh m, DState s, int n_events, int64_t *cnt, int3
     const int32_t b = m.rp[v];
     int64_t n = 0;
     if (lane < sN && lane < 16) {
-        int32_t *cq = ck + ((int64_t)ev * 16 + lane) * RCK;
+        int32_t *cq = ck + (rel * 16 + lane) * RCK;
         const int32_t e0 = m.rev[b + s.ev_rep[16 * (int64_t)ev + lane]];
         int32_t e = e0;
         long long K = 1;
@@ -2506,7 +2517,7 @@ __global__ void k_reeb_count(DMesh m, DState s, int n_events, int64_t *cnt, int3
             n++;
             e = he_next(m, s.key, e, kv, v, false);
         } while (e != e0 && n <= m.nnz);
-        int64_t *mq = meta + ((int64_t)ev * 16 + lane) * 4;
+        int64_t *mq = meta + (rel * 16 + lane) * 4;
         mq[0] = n;
         mq[1] = K;
         mq[2] = nck;
@@ -2517,29 +2528,31 @@ __global__ void k_reeb_count(DMesh m, DState s, int n_events, int64_t *cnt, int3
         const int64_t y = __shfl_up(inc, off);
         if (lane >= off) inc += y;
     }
-    if (lane < sN && lane < 16) meta[((int64_t)ev * 16 + lane) * 4 + 3] = inc - n;
-    if (lane == 63) cnt[ev] = 3 * inc;
+    if (lane < sN && lane < 16) meta[(rel * 16 + lane) * 4 + 3] = inc - n;
+    if (lane == 63) cnt[rel] = 3 * inc;
 }
 
 // Fill pass: a workgroup per event; every (loop, checkpoint) segment is
 // re-walked by one thread, writing the three vertices of each front
 // triangle; then the segment's padding up to its power of two.  The order
 // of the entries does not matter (they are sorted before the mean).
-__global__ void k_reeb_fill(DMesh m, DState s, int n_events, const int64_t *off, const int64_t *cnt,
+// Events ev0 .. ev0+n_events-1: off[] (n_events+1 entries) is relative to
+// this launch, cnt/ck/meta are the count pass's arrays shifted to ev0.
+__global__ void k_reeb_fill(DMesh m, DState s, int ev0, int n_events, const int64_t *off, const int64_t *cnt,
                             const int32_t *ck, const int64_t *meta, int32_t *buf) {
-    const int ev = blockIdx.x;
-    if (ev >= n_events) return;
-    const int64_t *rec = s.ev + 16 * (int64_t)ev;
+    if ((int)blockIdx.x >= n_events) return;
+    const int64_t rel = blockIdx.x;
+    const int64_t *rec = s.ev + 16 * (int64_t)(ev0 + (int)rel);
     const int32_t v = (int32_t)rec[1];
     const int sN = (int)rec[4] < 16 ? (int)rec[4] : 16;
     const uint64_t kv = s.key[v];
-    int32_t *out = buf + off[ev];
+    int32_t *out = buf + off[rel];
     for (int sg = threadIdx.x; sg < sN * RCK; sg += blockDim.x) {
         const int q = sg / RCK, c = sg % RCK;
-        const int64_t *mq = meta + ((int64_t)ev * 16 + q) * 4;
+        const int64_t *mq = meta + (rel * 16 + q) * 4;
         if (c >= (int)mq[2]) continue;
         const int64_t nq = mq[0], Kq = mq[1], base = mq[3];
-        int32_t e = ck[((int64_t)ev * 16 + q) * RCK + c];
+        int32_t e = ck[(rel * 16 + q) * RCK + c];
         const int64_t i0 = (int64_t)c * Kq;
         const int64_t i1 = i0 + Kq < nq ? i0 + Kq : nq;
         for (int64_t i = i0; i < i1; ++i) {
@@ -2552,7 +2565,7 @@ __global__ void k_reeb_fill(DMesh m, DState s, int n_events, const int64_t *off,
             e = rank_lt(ky, r.z, kv, v) ? r.y : r.x;
         }
     }
-    for (int64_t i = off[ev] + cnt[ev] + threadIdx.x; i < off[ev + 1]; i += blockDim.x) buf[i] = 0x7fffffff;
+    for (int64_t i = off[rel] + cnt[rel] + threadIdx.x; i < off[rel + 1]; i += blockDim.x) buf[i] = 0x7fffffff;
 }
 
 template <typename K>
@@ -2606,17 +2619,17 @@ __global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const i
     }
 }
 
-hipError_t launch_reeb_count(const DMesh &m, const DState &s, int n_events, int64_t *cnt, int32_t *ck,
+hipError_t launch_reeb_count(const DMesh &m, const DState &s, int ev0, int n_events, int64_t *cnt, int32_t *ck,
                              int64_t *meta, hipStream_t st) {
     if (n_events <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reeb_count, dim3(n_events), dim3(64), 0, st, m, s, n_events, cnt, ck, meta);
+    hipLaunchKernelGGL(k_reeb_count, dim3(n_events), dim3(64), 0, st, m, s, ev0, n_events, cnt, ck, meta);
     return hipGetLastError();
 }
-hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int n_events, const int64_t *off,
+hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int ev0, int n_events, const int64_t *off,
                             const int64_t *cnt, const int32_t *ck, const int64_t *meta, int32_t *buf,
                             hipStream_t st) {
     if (n_events <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reeb_fill, dim3(n_events), dim3(NT), 0, st, m, s, n_events, off, cnt, ck, meta, buf);
+    hipLaunchKernelGGL(k_reeb_fill, dim3(n_events), dim3(NT), 0, st, m, s, ev0, n_events, off, cnt, ck, meta, buf);
     return hipGetLastError();
 }
 hipError_t launch_reeb_mean(const DMesh &m, int n_events, const int64_t *off, const int64_t *cnt,
@@ -2658,9 +2671,10 @@ __global__ void k_tunnel_count(DState s, int nt, int64_t *cnt) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x)
         cnt[i] = tunnel_path(s, i, nullptr);
 }
-__global__ void k_tunnel_fill(DMesh m, DState s, int nt, const int64_t *off, int32_t *out, double *len) {
+// tunnels t0 .. t0+nt-1; off (nt+1 entries) and len are relative to t0
+__global__ void k_tunnel_fill(DMesh m, DState s, int t0, int nt, const int64_t *off, int32_t *out, double *len) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
-        const int64_t n = tunnel_path(s, i, out + off[i]);
+        const int64_t n = tunnel_path(s, t0 + i, out + off[i]);
         const int32_t *c = out + off[i];
         double L = 0.0;
         for (int64_t q = 0; q < n; ++q) {
@@ -2677,10 +2691,10 @@ hipError_t launch_tunnel_count(const DState &s, int n_tunnels, int64_t *cnt, hip
     hipLaunchKernelGGL(k_tunnel_count, dim3((n_tunnels + 63) / 64), dim3(64), 0, st, s, n_tunnels, cnt);
     return hipGetLastError();
 }
-hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int n_tunnels, const int64_t *off, int32_t *out,
+hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int t0, int n_tunnels, const int64_t *off, int32_t *out,
                               double *len, hipStream_t st) {
     if (n_tunnels <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tunnel_fill, dim3((n_tunnels + 63) / 64), dim3(64), 0, st, m, s, n_tunnels, off, out, len);
+    hipLaunchKernelGGL(k_tunnel_fill, dim3((n_tunnels + 63) / 64), dim3(64), 0, st, m, s, t0, n_tunnels, off, out, len);
     return hipGetLastError();
 }
 

@@ -1,7 +1,11 @@
-"""Writes tests/golden/oracle_summaries.json from the CPU oracle only.
+"""Writes tests/golden/oracle_summaries.json and oracle_full.json from the
+CPU oracle only.
 
-Run from the repository root:  python -m tests.golden.make_golden
-or:  python tests/golden/make_golden.py
+Run from the repository root:  python tests/golden/make_golden.py
+  --no-full          small summaries only
+  --full NAME ...    recompute only the named full-size cases and merge them
+                     into oracle_full.json (the lattice cases take minutes to
+                     hours of one core each)
 """
 import json
 import os
@@ -42,34 +46,57 @@ def summarize(r):
 # full-size workloads: digests of every output plus sampled values
 FULL_CASES = {
     "pretzel256_s0": lambda: mg.pretzel(256, rng_seed=0),
+    # the 10^3-cell strut lattice (genus 2300) on 256^3 and 512^3 grids
+    "lattice10_256_s0": lambda: mg.lattice(10, 256, rng_seed=0),
+    "lattice10_512_s0": lambda: mg.lattice(10, 512, rng_seed=0),
+    # the full-size lattice (1024^3 grid, about 95M vertices)
+    "lattice10_1024_s0": lambda: mg.lattice(10, 1024, rng_seed=0),
 }
 
 
-def main(full: bool = True):
+def main(full: bool = True, only=None):
+    import gc
+    import time
     import oracle
     oracle.build(force=False)
-    out = {}
-    for name, make in CASES.items():
-        m = make()
-        r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed)
-        out[name] = summarize(r)
-    with open(os.path.join(HERE, "oracle_summaries.json"), "w") as f:
-        json.dump(out, f, indent=1, sort_keys=True)
+    if not only:
+        out = {}
+        for name, make in CASES.items():
+            m = make()
+            r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed)
+            out[name] = summarize(r)
+        with open(os.path.join(HERE, "oracle_summaries.json"), "w") as f:
+            json.dump(out, f, indent=1, sort_keys=True)
     if not full:
         return
     sys.path.insert(0, os.path.dirname(HERE))
     from _digest import canon_oracle, digests
-    full_out = {}
+    path = os.path.join(HERE, "oracle_full.json")
+    full_out = json.load(open(path)) if (only and os.path.exists(path)) else {}
     for name, make in FULL_CASES.items():
+        if only and name not in only:
+            continue
+        t0 = time.time()
         m = make()
+        t1 = time.time()
         r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed)
+        t2 = time.time()
         d = digests(canon_oracle(r))
         d["nv"] = int(m.nv)
+        d["nf"] = int(m.nf)
         d["seed_vertex"] = int(m.seed)
+        d["oracle_seconds"] = round(t2 - t1, 1)
         full_out[name] = d
-    with open(os.path.join(HERE, "oracle_full.json"), "w") as f:
-        json.dump(full_out, f, indent=1, sort_keys=True)
+        print(f"{name}: nv={m.nv} steps={r.steps} events={r.n_events} handles={r.n_handles} "
+              f"mesh {t1 - t0:.0f} s, oracle {t2 - t1:.0f} s", flush=True)
+        del m, r
+        gc.collect()
+        # written after every case: a later case may take hours
+        with open(path, "w") as f:
+            json.dump(full_out, f, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":
-    main(full="--no-full" not in sys.argv)
+    argv = sys.argv[1:]
+    only = argv[argv.index("--full") + 1:] if "--full" in argv else None
+    main(full="--no-full" not in argv, only=only)

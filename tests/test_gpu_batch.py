@@ -132,3 +132,40 @@ def test_batch_schedule_changes_no_result():
     for x in M:
         x.close()
     ctx.close()
+
+
+def test_batch_edge_events_and_final_checkpoint(oracle_mod):
+    """The rare event meshes (3-way merge and 1-to-3 splits, a DEGENERATE
+    node, monkey-saddle splits) batched with tori, each with its own seed
+    parameters, and field snapshots that include each mesh's last step (the
+    step at which its pass stops): every output equals the oracle's."""
+    import paper_2105_13168_amd as vls
+    from test_oracle_edge_events import EDGE_CASES
+    ctx = vls.Context(0)
+    ms, kws = [], []
+    for _name, make, kw in EDGE_CASES:
+        ms.append(make())
+        kws.append(dict(kw))
+    for s in range(2):
+        t = mg.torus_grid(rng_seed=s)
+        ms.append(t)
+        kws.append(dict(seed_vertex=t.seed))
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    orc = []
+    for m, kw in zip(ms, kws):
+        rk = {k: v for k, v in kw.items() if k != "seed_vertex"}
+        o = oracle_mod.run(m.xyz, m.tri, seed_vertex=kw["seed_vertex"], **rk)
+        ck = sorted({1, max(1, o.steps // 3), o.steps})
+        kw["ckpt_steps"] = ck
+        orc.append(oracle_mod.run(m.xyz, m.tri, seed_vertex=kw["seed_vertex"], ckpt_steps=ck, **rk))
+    per = [{k: v for k, v in kw.items() if k != "seed_vertex"} for kw in kws]
+    try:
+        res = vls.batch_run(ctx, M, [kw["seed_vertex"] for kw in kws], per_mesh=per)
+        for m, g, o in zip(ms, res, orc):
+            assert o.steps in g.ckpt
+            bad = compare(g, o, m.nv)
+            assert not bad, (m.name, bad)
+    finally:
+        for x in M:
+            x.close()
+        ctx.close()

@@ -146,3 +146,41 @@ def test_error_paths(ctx, oracle_mod):
     t[3] = t[3, ::-1]
     with pytest.raises(vls.VLSError):
         vls.Mesh(ctx, m.xyz, t)
+
+
+# the method's rare event cases (found with the oracle on the CPU): 1-to-3
+# splits at monkey saddles, a 3-way merge (two handle loops, the longest of
+# three dropped) and a DEGENERATE node (a handle swept at one saddle of one
+# front, extra cycle x = 1)
+from test_oracle_edge_events import EDGE_CASES  # noqa: E402
+
+
+@pytest.mark.parametrize("variant", ["default", "global_topology", "dense", "lockstep"])
+@pytest.mark.parametrize("name,make,kw", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+def test_parity_edge_events(ctx, oracle_mod, name, make, kw, variant):
+    import paper_2105_13168_amd as vls
+    flags = {"default": 0, "global_topology": vls.VLS_TOPO_GLOBAL_PATH, "dense": vls.VLS_DENSE_FIELD,
+             "lockstep": vls.VLS_LOCKSTEP}[variant]
+    m = make()
+    seed = kw["seed_vertex"]
+    rk = {k: v for k, v in kw.items() if k != "seed_vertex"}
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    try:
+        o = oracle_mod.run(m.xyz, m.tri, seed_vertex=seed, **rk)
+        ck = [1, max(1, o.steps // 2), o.steps]
+        o = oracle_mod.run(m.xyz, m.tri, seed_vertex=seed, ckpt_steps=ck, **rk)
+        g = M.run(seed_vertex=seed, ckpt_steps=ck, raise_on_error=False, flags=flags, **rk)
+    finally:
+        M.close()
+    ev = o.events
+    # the case occurs
+    if name == "voxel_frame":
+        assert ((ev[:, 4] == 3) & (ev[:, 2] == 2)).any() and ((ev[:, 3] == 3) & (ev[:, 5] == 3)).any()
+    elif name == "csaszar7":
+        assert (ev[:, 2] == 4).any()
+    else:
+        assert ((ev[:, 3] == 3) & (ev[:, 5] == 3)).any()
+    assert g.summary["run_status"] == 0
+    bad = compare(g, o, m.nv)
+    assert not bad, bad
+    assert g.summary["n_degenerate"] == int((ev[:, 2] == 4).sum())

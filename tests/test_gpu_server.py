@@ -190,3 +190,79 @@ def test_server_gangs_resize_and_switch(oracle_mod, two_per_cu):
         for x in M:
             x.close()
         ctx.close()
+
+
+def test_server_stalled_request_in_the_mix(oracle_mod):
+    """A request that stops at its step limit returns VLS_E_STALLED with the
+    partial results the oracle gives for the same limit, including the field
+    at its last step; the requests around it are unchanged (equal to the
+    oracle)."""
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    ms = _meshes()[:4]
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    srv = vls.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=16, slice_us=400)
+    try:
+        tickets = []
+        for i, (m, h) in enumerate(zip(ms, M)):
+            tickets.append(srv.submit(h, seed_vertex=m.seed))
+            if i == 1:
+                tickets.append(srv.submit(M[0], seed_vertex=ms[0].seed, max_steps=300, ckpt_steps=[1, 150, 300]))
+        res = _wait(srv, tickets)
+        order = [0, 1, 0, 2, 3]
+        for k, (i, r) in enumerate(zip(order, res)):
+            m = ms[i]
+            if k == 2:
+                assert r.status == vls.VLS_E_STALLED and r.summary["run_status"] == vls.VLS_E_STALLED
+                o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed, max_steps=300, ckpt_steps=[1, 150, 300])
+                assert o.status == vls.VLS_E_STALLED and 300 in r.ckpt
+            else:
+                assert r.summary["run_status"] == 0
+                o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
+            bad = compare(r, o, m.nv)
+            assert not bad, (k, m.name, bad)
+    finally:
+        srv.close()
+        for x in M:
+            x.close()
+        ctx.close()
+
+
+def test_server_shutdown_cancels_pending_requests():
+    """vls_server_shutdown: queued and running requests poll as
+    VLS_E_CANCELLED (no result), finished ones keep their results, and later
+    submits are refused with VLS_E_CANCELLED."""
+    import ctypes as C
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    small = mg.torus_grid(rng_seed=0)
+    big = mg.pretzel(72, rng_seed=1)
+    Ms = vls.Mesh(ctx, small.xyz, small.tri)
+    Mb = vls.Mesh(ctx, big.xyz, big.tri)
+    srv = vls.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=2, slice_us=200)
+    try:
+        first = srv.submit(Ms, seed_vertex=small.seed)
+        (r0,) = _wait(srv, [first])
+        assert r0.summary["run_status"] == 0
+        tickets = [srv.submit(Mb, seed_vertex=big.seed) for _ in range(8)]
+        srv.shutdown()
+        cancelled = 0
+        for t in tickets:
+            h = C.c_void_p()
+            st = vls.vls_server_poll(srv.h, C.c_uint64(t), C.byref(h))
+            assert st in (0, vls.VLS_E_CANCELLED), st
+            if st == vls.VLS_E_CANCELLED:
+                assert not h.value
+                cancelled += 1
+            else:
+                vls.vls_result_destroy(h)
+        assert cancelled >= 6          # two slots: most requests never started
+        p = vls.default_params(seed_vertex=small.seed)
+        tk = C.c_uint64()
+        assert vls.vls_server_submit(srv.h, Ms.h, C.byref(p), C.byref(tk)) == vls.VLS_E_CANCELLED
+        srv.shutdown()                 # idempotent
+    finally:
+        srv.close()
+        Ms.close()
+        Mb.close()
+        ctx.close()
