@@ -196,6 +196,25 @@ vls_status vls_run_async(struct vls_context *ctx, const struct vls_mesh *m, cons
                          void *d_workspace, size_t bytes, void *hip_stream, struct vls_result **out);
 vls_status vls_result_wait(struct vls_result *r);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the pass
+ * of vls_run_async with its workspace replaced by a static device array of
+ * 64 MiB per device, which the library holds until the process ends.  No
+ * hipMalloc, hipFree, event or stream creation happens in this call or in
+ * the wait; the result and its arrays are host memory.  The mesh (created
+ * beforehand) and the result are the caller's inputs and outputs.
+ *   - Meshes whose vls_workspace_size exceeds 64 MiB (about 150k vertices)
+ *     fail with VLS_E_BUFFER_TOO_SMALL.
+ *   - Every call on one device shares that device's array: a call made
+ *     while an earlier call's result has not been waited for (or
+ *     destroyed) fails with VLS_E_PENDING; calls that bypass this check
+ *     (another process's copy of the library aside, which has its own
+ *     array) would race on the array.  The array keeps the last run's
+ *     contents; the run clears what must start at zero itself.
+ */
+vls_status vls_run_async_noalloc(struct vls_context *ctx, const struct vls_mesh *m, const vls_params *p,
+                                 void *hip_stream, struct vls_result **out);
 
 typedef struct {
     int32_t n_handles;         /* handle loops emitted (merges: fronts involved minus one)   */

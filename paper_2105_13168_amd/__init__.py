@@ -103,6 +103,7 @@ _sig = {
     "vls_workspace_size": (C.c_int32, [_P, C.POINTER(vls_params), C.POINTER(C.c_size_t)]),
     "vls_run_async": (C.c_int32, [_P, _P, C.POINTER(vls_params), _P, C.c_size_t, _P, _PP]),
     "vls_result_wait": (C.c_int32, [_P]),
+    "vls_run_async_noalloc": (C.c_int32, [_P, _P, C.POINTER(vls_params), _P, _PP]),
     "vls_batch_run": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "vls_result_summary": (C.c_int32, [_P, C.POINTER(vls_summary)]),
     "vls_result_events": (C.c_int32, [_P, C.c_int64, _P, _I64P]),

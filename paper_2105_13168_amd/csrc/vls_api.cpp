@@ -72,6 +72,7 @@ struct vls_result {
     RunPrep *launched = nullptr;         // vls_run_async: enqueued, not yet waited for
     vls_status launch_status = VLS_OK;   // status vls_result_wait returns once done
     bool failed = false;                 // the post-passes or copies failed: no outputs
+    int static_dev = -1;                 // vls_run_async_noalloc: device whose static scratch it holds
     vls_summary sum{};
     int64_t nv = 0;
     std::vector<int64_t> ev;             // [n][16]
@@ -1090,6 +1091,25 @@ static vls_status run_in_workspace(vls_context *ctx, const vls_mesh *mc, const v
     return VLS_OK;
 }
 
+// the static scratch of a device serves one run at a time: claimed by
+// vls_run_async_noalloc, released once that run's result has been waited
+// for or destroyed
+static std::mutex g_static_mu;
+static std::unordered_map<int, bool> g_static_busy;
+static bool static_claim(int dev) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    bool &b = g_static_busy[dev];
+    if (b) return false;
+    b = true;
+    return true;
+}
+static void static_release(vls_result *r) {
+    if (r->static_dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_busy[r->static_dev] = false;
+    r->static_dev = -1;
+}
+
 // the second half of a workspace run: the step kernel's end, post-passes,
 // every result copied to the host; the workspace is free afterwards
 static vls_status wait_launched(vls_result *r) {
@@ -1107,6 +1127,7 @@ static vls_status wait_launched(vls_result *r) {
         r->failed = true;
     }
     r->launch_status = rs;
+    static_release(r);
     return rs;
 }
 
@@ -1115,6 +1136,33 @@ extern "C" {
 vls_status vls_run_async(vls_context *ctx, const vls_mesh *m, const vls_params *p, void *d_workspace,
                          size_t bytes, void *hip_stream, vls_result **out) {
     return run_in_workspace(ctx, m, p, d_workspace, bytes, (hipStream_t)hip_stream, out);
+}
+
+vls_status vls_run_async_noalloc(vls_context *ctx, const vls_mesh *m, const vls_params *p, void *hip_stream,
+                                 vls_result **out) {
+    if (!ctx || !m || !p || !out) return set_err(ctx, VLS_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (p->struct_size != sizeof(vls_params)) return set_err(ctx, VLS_E_INVALID_ARG, "vls_params.struct_size mismatch");
+    size_t need = 0;
+    (void)vls_workspace_size(m, p, &need);
+    if (need > STATIC_SCRATCH_BYTES)
+        return set_err(ctx, VLS_E_BUFFER_TOO_SMALL, "the run needs %zu bytes of workspace; the static scratch holds %zu",
+                       need, (size_t)STATIC_SCRATCH_BYTES);
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+    void *base = nullptr;
+    hipError_t e = static_scratch(ctx->device, &base);
+    if (e != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "static scratch address: %s", hipGetErrorString(e));
+    if (!static_claim(ctx->device))
+        return set_err(ctx, VLS_E_PENDING, "the static scratch of device %d is held by a result not yet waited for",
+                       ctx->device);
+    vls_status st = run_in_workspace(ctx, m, p, base, STATIC_SCRATCH_BYTES, (hipStream_t)hip_stream, out);
+    if (st != VLS_OK) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[ctx->device] = false;
+        return st;
+    }
+    (*out)->static_dev = ctx->device;
+    return VLS_OK;
 }
 
 vls_status vls_result_wait(vls_result *r) {
@@ -1383,6 +1431,7 @@ vls_status vls_result_destroy(vls_result *r) {
         delete r->launched;
         r->launched = nullptr;
     }
+    static_release(r);
     Pending &pd = r->pend;
     if (pd.active) {
         // never fetched: drop the device copies without reading them

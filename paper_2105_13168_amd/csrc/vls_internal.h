@@ -165,4 +165,9 @@ hipError_t launch_tunnel_count(const DState &s, int n_tunnels, int64_t *cnt, hip
 hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int t0, int n_tunnels, const int64_t *off, int32_t *out,
                               double *len, hipStream_t st);
 
+// bytes of the per-device static scratch of vls_run_async_noalloc, and its
+// device address on `device` (hipGetSymbolAddress, once per device)
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;
+hipError_t static_scratch(int device, void **ptr);
+
 }  // namespace vls

@@ -24,6 +24,8 @@
 // Floating point: FP64, evaluated exactly as written (built with
 // -ffp-contract=off), neighbour sums in ascending neighbour id.
 #include <climits>
+#include <mutex>
+#include <unordered_map>
 
 #include "vls_internal.h"
 
@@ -2696,6 +2698,38 @@ hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int t0, int n_tun
     if (n_tunnels <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tunnel_fill, dim3((n_tunnels + 63) / 64), dim3(64), 0, st, m, s, t0, n_tunnels, off, out, len);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// device scratch of the allocation-free entry point: one array per device,
+// held by the code object until the process ends.  Host code never uses the
+// array's name as an address (on the host it is only a stand-in for the
+// symbol); its device address comes from hipGetSymbolAddress, looked up once
+// per device with that device current, and is what kernels receive.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(int device, void **ptr) {
+    static std::mutex mu;
+    static std::unordered_map<int, void *> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr.emplace(device, p);
+    *ptr = p;
+    return hipSuccess;
 }
 
 }  // namespace vls
