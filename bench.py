@@ -5,13 +5,18 @@ A "step" here is one complete initial pass over the workload: seed region,
 every diffusion step until the front has swept the whole surface (field,
 threshold + closure, lower-link classification, front tags, split / merge /
 vanish events with handle loops), then the Reeb-position and tunnel
-post-passes.  The workload is the genus-3 pretzel (three tori R=1, r=0.35 at
-x = -1.6, 0, 1.6; level-0 surface on a 256^3 sample grid fitted per axis;
-N(0,1e-4) jitter; seed vertex from rng seed 0), with its mesh uploaded to
-HBM before the timed region.  Bulk results stay on the device (deferred),
-so the timed region holds no result download.
+post-passes.  The default workload is the full-size strut lattice: 10^3
+cells of unit struts of radius 0.15 (genus 2300), level-0 surface on a
+1024^3 sample grid (95.3M vertices, 190.5M triangles), seed vertex from rng
+seed 0, with its mesh uploaded to HBM before the timed region.  Bulk
+results stay on the device (deferred), so the timed region holds no result
+download.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+Extra keys: the 256^3 pretzel pass, the dense field step on the same
+lattice, the batch of 1024 uneven meshes, the serving trace.  They run only
+while the run stays within --time-budget seconds.
+
+    python bench.py [--gpus 1] [--steps 2] [--warmup 1]
 
 Prints one JSON line.
 """
@@ -105,16 +110,23 @@ def dense_alg_bytes(updates, degsum):
     return 20 * updates + 4 * degsum
 
 
-def dense_leg(ctx, workload, steps):
+def dense_leg(ctx, workload, steps, mesh=None):
     """The dense field step (every vertex each step) on a mesh whose working
     set is far beyond the caches, run for a fixed number of diffusion steps
     with the topology beside it, against the band-stepped default for the
-    same steps; HBM share from the algorithmic bytes of a dense step."""
+    same steps; HBM share from the algorithmic bytes of a dense step.
+    mesh = (generator mesh, uploaded Mesh, description) reuses a mesh that is
+    already on the device."""
     import ctypes as C
     import paper_2105_13168_amd as vls
     t0 = time.time()
-    m, desc = make_workload(workload)
-    M = vls.Mesh(ctx, m.xyz, m.tri)
+    if mesh is None:
+        m, desc = make_workload(workload)
+        M = vls.Mesh(ctx, m.xyz, m.tri)
+        own = True
+    else:
+        m, M, desc = mesh
+        own = False
     log(f"dense leg: {workload} V={m.nv} ({time.time() - t0:.1f}s)")
 
     def run(flags, k):
@@ -149,11 +161,50 @@ def dense_leg(ctx, workload, steps):
         "band_updates_per_step": b["active_vertex_updates"] / steps,
         "same_front": True,
     }
-    M.close()
+    if own:
+        M.close()
     return res
 
 
-def batch_leg(ctx, n, seq_sample):
+def pass_leg(ctx, workload, steps):
+    """Whole initial passes of another workload (one timed pass after a
+    warm-up), as the main line measures its own."""
+    import ctypes as C
+    import torch
+    import paper_2105_13168_amd as vls
+    m, desc = make_workload(workload)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_DEFER_RESULTS)
+    sums, ms = [], []
+    for k in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = C.c_void_p()
+        st = vls.vls_run(ctx.h, M.h, C.byref(p), C.byref(h))
+        if st != 0:
+            raise vls.VLSError(st, ctx.last_error())
+        s = vls.vls_summary()
+        vls.vls_result_summary(h, C.byref(s))
+        vls.vls_result_destroy(h)
+        torch.cuda.synchronize()
+        if k:
+            ms.append((time.perf_counter() - t0) * 1e3)
+            sums.append({f: getattr(s, f) for f, _ in vls.vls_summary._fields_})
+    M.close()
+    last = sums[-1]
+    kernel_ms = sum(x["kernel_ms"] for x in sums) / len(sums)
+    ab = alg_bytes(last["active_vertex_updates"], last["active_degree_sum"])
+    assert last["n_handles"] == last["euler_genus"]
+    return {"workload": desc, "nv": m.nv, "nf": m.nf, "diffusion_steps": last["steps"],
+            "events": last["n_events"], "handles": last["n_handles"], "ms_per_pass": sum(ms) / len(ms),
+            "step_kernel_ms": kernel_ms, "vertex_steps_per_s": m.nv * last["steps"] / (sum(ms) / len(ms) * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": ab / (kernel_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
+                         "unit": "GB/s", "frac": ab / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                         "traffic": measured_traffic(kernel_ms, workload, grid=last["grid"]),
+                         "kernel": "k_steps_dec"}}
+
+
+def batch_leg(ctx, n, seq_sample, tune=False):
     """Batch of n uneven meshes in one launch (one workgroup per mesh)
     against the same meshes run one at a time (default launch) on a sample,
     as meshes per second."""
@@ -187,17 +238,19 @@ def batch_leg(ctx, n, seq_sample):
 
     run_batch(list(range(n)))                     # warm-up: allocates every mesh's run buffers
     torch.cuda.synchronize()
-    # schedule: tuned on a sample of the workload (every 4th mesh), then the
-    # whole batch timed with the tuned and the default schedule
-    from paper_2105_13168_amd.tune import tune_batch
-    t0 = time.time()
-    samp = list(range(0, n, 4))
-    tuned = tune_batch(ctx, [M[i] for i in samp], [ms[i].seed for i in samp])
-    log(f"batch schedule tuned on {len(samp)} meshes: {tuned} ({time.time() - t0:.1f}s)")
+    # schedule: the default; with tune, also the tuner's pick on a sample of
+    # the workload (every 4th mesh), both timed on the whole batch
+    tuned = {"two_per_cu": False, "gang_vertices": 0, "seconds": {}}
+    variants = [("default", 0, 0)]
+    if tune:
+        from paper_2105_13168_amd.tune import tune_batch
+        t0 = time.time()
+        samp = list(range(0, n, 4))
+        tuned = tune_batch(ctx, [M[i] for i in samp], [ms[i].seed for i in samp])
+        log(f"batch schedule tuned on {len(samp)} meshes: {tuned} ({time.time() - t0:.1f}s)")
+        variants.append(("tuned", vls.VLS_BATCH_TWO_PER_CU if tuned["two_per_cu"] else 0, tuned["gang_vertices"]))
     shapes = {}
-    for name, extra, gv in (("default", 0, 0),
-                            ("tuned", vls.VLS_BATCH_TWO_PER_CU if tuned["two_per_cu"] else 0,
-                             tuned["gang_vertices"])):
+    for name, extra, gv in variants:
         t1 = time.perf_counter()
         sm = run_batch(list(range(n)), extra, gv)
         torch.cuda.synchronize()
@@ -345,48 +398,89 @@ def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=Fals
     }
 
 
-def cpu_baseline(m, max_steps):
-    """The oracle, single-threaded, on the same mesh and seed: the whole pass
-    (max_steps 0) or its first max_steps diffusion steps."""
+def host_cpu():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(workload, max_steps, head=None):
+    """The oracle (sequential C, one thread) on a bounded sample: the first
+    max_steps diffusion steps of `workload`'s pass (0: the whole pass),
+    timed without the oracle's own mesh setup (a one-step run measures it).
+    value is in the main line's unit; when head = (nv, steps, updates) of
+    the main line's workload is given, the oracle's update rate is scaled to
+    that workload's vertex-steps per update."""
     import oracle
     oracle.build(force=False)
+    m, desc = make_workload(workload)
+    t0 = time.perf_counter()
+    oracle.run(m.xyz, m.tri, seed_vertex=m.seed, max_steps=1)
+    t_setup = time.perf_counter() - t0
     kw = {"max_steps": max_steps} if max_steps > 0 else {}
     t0 = time.perf_counter()
     r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed, **kw)
-    dt = time.perf_counter() - t0
-    steps = r.steps
-    what = "the whole pass" if max_steps <= 0 else f"the first {steps} diffusion steps of the pass"
-    return {"value": m.nv * steps / dt, "unit": "vertex-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what} ({steps} diffusion steps, single thread, {dt:.1f} s)",
-            "seconds": round(dt, 3)}
+    dt = time.perf_counter() - t0 - t_setup
+    model, ncpu = host_cpu()
+    what = "the whole pass" if max_steps <= 0 else f"the first {r.steps} diffusion steps of the pass"
+    upd_rate = r.active_updates / dt
+    out = {"unit": "vertex-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{what} on {desc} (V={m.nv}), one thread, {dt:.1f} s of stepping after {t_setup:.1f} s "
+                     f"of the oracle's mesh setup",
+           "seconds": round(dt, 3), "oracle_updates_per_s": upd_rate, "sample_vertex_steps_per_s": m.nv * r.steps / dt,
+           "host_cpu": model, "host_nproc": ncpu,
+           "threads_note": "the oracle is sequential C (no threads); nproc copies would not share one pass"}
+    if head is not None:
+        nv, steps, updates = head
+        out["value"] = upd_rate * (nv * steps / updates)
+        out["scaling"] = ("oracle update rate on the sample times the main workload's vertex-steps per "
+                          "update (dense-equivalent, as the GPU value)")
+    else:
+        out["value"] = m.nv * r.steps / dt
+    return out
 
 
 def main():
+    t_start = time.time()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="pretzel256")
+    ap.add_argument("--workload", default="lattice10_1024")
     ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle diffusion steps (0: whole pass)")
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="seconds: extra legs are skipped when they would end past it")
+    ap.add_argument("--cpu-workload", default="lattice10_256", help="oracle sample workload")
+    ap.add_argument("--cpu-steps", type=int, default=10000, help="oracle diffusion steps (0: whole pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--pretzel-passes", type=int, default=3, help="timed passes of the 256^3 pretzel (0: skip)")
     ap.add_argument("--batch", type=int, default=1024, help="meshes in the batched leg (0: skip)")
     ap.add_argument("--batch-seq-sample", type=int, default=16)
+    ap.add_argument("--tune", action="store_true", help="time the batch schedule tuner's pick too")
     ap.add_argument("--serve", type=int, default=1000, help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-lattice-share", type=float, default=0.05)
     ap.add_argument("--serve-slice-us", type=int, default=20000)
     ap.add_argument("--serve-two-per-cu", action="store_true", help="server step launches at two workgroups per CU")
-    ap.add_argument("--dense-workload", default="lattice10_512",
-                    help="mesh of the dense-step leg ('none': skip)")
-    ap.add_argument("--dense-steps", type=int, default=400)
+    ap.add_argument("--dense-workload", default="same",
+                    help="mesh of the dense-step leg ('same': the main workload's mesh; 'none': skip)")
+    ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--dense", action="store_true", help="time the whole pass with the dense field step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(meshes shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
+
+    def left():
+        return args.time_budget - (time.time() - t_start)
 
     t0 = time.time()
     m, desc = make_workload(args.workload)
@@ -411,9 +505,10 @@ def main():
         vls.vls_result_summary(h, C.byref(s))
         return h, {f: getattr(s, f) for f, _ in vls.vls_summary._fields_}
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         h, _s = one_pass()
         vls.vls_result_destroy(h)
+        log(f"warm-up pass {k + 1}/{args.warmup}: {_s['kernel_ms']:.0f} ms step kernel")
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -424,6 +519,7 @@ def main():
         h, s = one_pass()
         sums.append(s)
         handles.append(h)
+        log(f"timed pass {k + 1}/{args.steps}: {s['kernel_ms']:.0f} ms step kernel")
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
@@ -443,7 +539,7 @@ def main():
     ab = alg_bytes(upd, deg)
     achieved = ab / (kernel_ms * 1e-3) / 1e9
     value = m.nv * steps / (ms * 1e-3)
-    dense_bytes = 32.0 + 4.0 * (3.0 * m.nf) / m.nv          # per vertex: 32 B + 4 B per neighbour id
+    dense_bytes = 20.0 + 4.0 * deg / upd          # per vertex of a dense step: 20 B + 4 B per neighbour id
     out = {
         "metric": "vertex-diffusion-steps/sec",
         "value": value,
@@ -464,13 +560,15 @@ def main():
             "device_ms_per_pass": device_ms, "step_kernel_ms": kernel_ms,
             "active_updates_per_s": upd / (ms * 1e-3),
             "phase_ms": {"topology": last["topo_ms"], "topology_wait": last["wait0_ms"],
-                         "field": last["field_ms"], "field_wait": last["wait1_ms"]},
+                         "field": last["field_ms"], "field_wait": last["wait1_ms"],
+                         "topology_global_path_steps": last["topo_global_steps"]},
             "event_steps": last["event_steps"],
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel_ms, args.workload, grid=last["grid"]),
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(kernel_ms, args.workload, grid=last["grid"]),
                      "kernel": "k_steps_dec", "algorithmic_bytes": ab,
-                     # a dense step (every vertex, 32 + 4 deg bytes) at this
+                     # a dense step (every vertex, 20 + 4 deg bytes) at this
                      # vertex-steps/s would need this share of HBM peak
                      "dense_equivalent_frac": value * dense_bytes / (HBM_PEAK_GBPS * 1e9),
                      "kernel_source_hash": kernel_source_hash()},
@@ -482,20 +580,45 @@ def main():
         out["roofline"]["algorithmic_bytes"] = ab
         out["roofline"]["traffic"] = None
         out["config"]["field_step"] = "dense"
+    skipped = []
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_workload, args.cpu_steps, head=(m.nv, steps, upd))
+        log(f"cpu baseline done ({time.time() - t_start:.0f}s since start)")
     if args.dense_workload != "none" and args.dense_steps > 0:
-        out["dense_step"] = dense_leg(ctx, args.dense_workload, args.dense_steps)
+        if args.dense_workload == "same":
+            out["dense_step"] = dense_leg(ctx, args.workload, args.dense_steps, mesh=(m, M, desc))
+        elif left() > 60:
+            out["dense_step"] = dense_leg(ctx, args.dense_workload, args.dense_steps)
+        else:
+            skipped.append("dense_step")
+    M.close()
+    del m
+    if args.pretzel_passes > 0 and args.workload != "pretzel256":
+        if left() > 30:
+            out["pretzel_pass"] = pass_leg(ctx, "pretzel256", args.pretzel_passes)
+            log(f"pretzel leg done ({time.time() - t_start:.0f}s since start)")
+        else:
+            skipped.append("pretzel_pass")
     if args.batch > 0:
-        out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample)
+        if left() > 75:
+            out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample, tune=args.tune)
+            log(f"batch leg done ({time.time() - t_start:.0f}s since start)")
+        else:
+            skipped.append("batched")
     if args.serve > 0:
-        out["serving"] = serve_leg(ctx, args.serve, args.serve_rate, args.serve_lattice_share,
-                                   args.serve_slice_us, two_per_cu=args.serve_two_per_cu)
-        out["serving"]["workgroups_per_cu"] = 2 if args.serve_two_per_cu else 1
+        if left() > 80:
+            out["serving"] = serve_leg(ctx, args.serve, args.serve_rate, args.serve_lattice_share,
+                                       args.serve_slice_us, two_per_cu=args.serve_two_per_cu)
+            out["serving"]["workgroups_per_cu"] = 2 if args.serve_two_per_cu else 1
+            log(f"serving leg done ({time.time() - t_start:.0f}s since start)")
+        else:
+            skipped.append("serving")
+    if skipped:
+        out["skipped_for_time_budget"] = skipped
     if args.copy_calibration:
         copy_calibration()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, args.cpu_steps)
-    M.close()
     ctx.close()
+    out["bench_seconds"] = round(time.time() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 

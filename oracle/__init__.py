@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vls_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "vls_passes.c")]
 _LIB = os.path.join(_HERE, "_vls_oracle.so")
 
 # node types (Reeb graph)
@@ -33,10 +34,10 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "MESH_NOT_MANIFOLD", -3: "MESH_HAS_BOU
 
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (no contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+                               "-std=c99", "-shared", "-fPIC", "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -1398,7 +1398,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
 
 template <int CM, int CAP>
 __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &s, const DParams &p, int64_t t,
-                                  KSh *sh, uint64_t *lsort) {
+                                  KSh *sh, uint64_t *lsort, int sort_cap) {
     Ctl *ctl = s.ctl;
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
     const int tid = threadIdx.x;
@@ -1531,14 +1531,17 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
             }
         } else {
             // 4b. events: rank order (round, id); regular runs between events in
-            //     parallel by round, each event by wave 0
+            //     parallel by round, each event by wave 0.  The order is sorted
+            //     in LDS (the candidate tables are unused on this path) up to
+            //     sort_cap entries, else in global memory; its breakpoints
+            //     (events, first entries of a round) are found in parallel.
             const int nN = sh->nN;
             int npow = 1;
             while (npow < nN) npow <<= 1;
-            uint64_t *arr = npow <= CAP ? lsort : s.ord;
+            uint64_t *arr = npow <= sort_cap ? lsort : s.ord;
             for (int i = tid; i < npow; i += NT) arr[i] = ~0ull;
             __syncthreads();
-            if (tid == 0) sh->nnew = 0;
+            if (tid == 0) { sh->nnew = 0; sh->nbp = 0; }
             __syncthreads();
             for (int i = tid; i < nL; i += NT) {
                 if (s.Lrnd[i] < 0) continue;
@@ -1547,20 +1550,58 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
             }
             __syncthreads();
             block_bitonic(arr, npow);
-            int pos = 0;
+            for (int i = tid; i < nN; i += NT)
+                if ((arr[i] & 1ull) || (i > 0 && (arr[i] >> 33) != (arr[i - 1] >> 33))) {
+                    const int k = atomicAdd(&sh->nbp, 1);
+                    if (k < MAXBP) sh->bpu[k] = i;
+                }
+            __syncthreads();
+            const int nbp = sh->nbp < MAXBP ? sh->nbp : MAXBP;
+            const bool bp_ok = sh->nbp <= MAXBP;
+            for (int i = tid; i < nbp; i += NT) {
+                const int x = sh->bpu[i];
+                int r = 0;
+                for (int j = 0; j < nbp; ++j) r += sh->bpu[j] < x;
+                sh->bps[r] = x;
+            }
+            __syncthreads();
+            int pos = 0, kb = 0;
             while (pos < nN) {
-                // regular segment [pos, q)
-                int q = pos;
-                while (q < nN && !(arr[q] & 1ull)) q++;
+                // the regular segment [pos, q) ends at the next event q; with
+                // the breakpoints known, a round change inside it is a
+                // breakpoint too, so each run [a0, a1) is one round
+                int q, qr;
+                if (bp_ok) {
+                    while (kb < nbp && sh->bps[kb] < pos) kb++;
+                    qr = kb < nbp ? sh->bps[kb] : nN;
+                    if (qr == pos && !(arr[pos] & 1ull)) {
+                        kb++;
+                        qr = kb < nbp ? sh->bps[kb] : nN;
+                    }
+                    q = (qr < nN && (arr[qr] & 1ull)) ? qr : nN;
+                    if (qr < nN && !(arr[qr] & 1ull)) q = -1;     // round change, no event yet
+                } else {
+                    q = pos;
+                    while (q < nN && !(arr[q] & 1ull)) q++;
+                    qr = q;
+                }
+                const int stop = q < 0 ? qr : q;
                 int a0 = pos;
-                while (a0 < q) {
-                    const int r = (int)(arr[a0] >> 33);
-                    int a1 = a0;
-                    while (a1 < q && (int)(arr[a1] >> 33) == r) a1++;
+                while (a0 < stop) {
+                    int a1 = stop;
+                    if (!bp_ok) {
+                        const int r = (int)(arr[a0] >> 33);
+                        a1 = a0;
+                        while (a1 < stop && (int)(arr[a1] >> 33) == r) a1++;
+                    }
                     for (int i = a0 + tid; i < a1; i += NT)
                         regular_insert(m, s, (int32_t)((arr[i] >> 1) & 0xffffffffull));
                     __syncthreads();
                     a0 = a1;
+                }
+                if (q < 0) {
+                    pos = qr;              // continue with the next round
+                    continue;
                 }
                 if (q < nN) {
                     if (tid < WAVE)
@@ -2024,7 +2065,9 @@ __device__ __forceinline__ void phase_topo(const DMesh &m, const DState &s, cons
     const int nc = ld_relaxed(&ctl->cnt_cand[t & 3]);
     const int np = ctl->cnt_pend[(t - 1) & 1];
     if (p.topo_global || nc + np > CAP) {
-        phase_topo_global<CM, CAP>(m, s, p, t, sh, lsort);
+        // the sort buffer and the candidate tables are contiguous in LDS
+        constexpr int kSortCap = 1 << ilog2((int)((CAP * sizeof(uint64_t) + sizeof(KL<CAP>)) / sizeof(uint64_t)));
+        phase_topo_global<CM, CAP>(m, s, p, t, sh, lsort, kSortCap);
         if (threadIdx.x == 0) ctl->n_global_steps += 1;
         return;
     }

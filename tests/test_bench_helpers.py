@@ -16,8 +16,8 @@ def test_algorithmic_bytes_per_update():
     # 4 B per neighbour id: 56 B at degree 6
     assert bench.alg_bytes(1, 6) == 56
     assert bench.alg_bytes(10, 60) == 560
-    # dense step: no list entry, 48 B at degree 6
-    assert bench.dense_alg_bytes(1, 6) == 48
+    # dense step: no list entry, one row offset per vertex, 44 B at degree 6
+    assert bench.dense_alg_bytes(1, 6) == 44
     assert bench.dense_alg_bytes(0, 0) == 0
 
 
@@ -57,3 +57,8 @@ def test_committed_records_name_their_grid():
         rec = json.load(open(os.path.join(root, "profiles", f"k_steps_{name}_traffic.json")))
         assert isinstance(rec.get("grid"), int) and rec["hbm_bytes_per_launch"] > 0
         assert rec["fetch_factor"] > 0 and rec["write_factor"] > 0
+
+
+def test_host_cpu_reports_model_and_count():
+    model, n = bench.host_cpu()
+    assert isinstance(model, str) and n >= 1

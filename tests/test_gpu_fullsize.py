@@ -1,14 +1,14 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
-times (default grid of vls_run).
+times (default grid of vls_run): every output's digest equals the oracle's
+(recorded by tests/golden/make_golden.py from the oracle alone), and the
+sampled per-vertex values match one by one.
 
-* 256^3 pretzel (V = 2,188,952): every output's digest equals the oracle's
-  (recorded by tests/golden/make_golden.py from the oracle alone), and the
-  sampled per-vertex values match one by one; with the band-limited field
-  step (the default) and with the dense one.
-* 10^3-cell strut lattice on a 256^3 grid (V = 5,845,474, genus 2300): the
-  oracle is not run at this size; properties that hold at any size are
-  checked: every vertex inside, handle loops = tunnel loops = swept genus =
-  Euler genus, one Reeb node per event plus the seed.
+* 256^3 pretzel (V = 2,188,952), with the band-limited field step (the
+  default) and with the dense one.
+* the 10^3-cell strut lattice (genus 2300) on 256^3, 512^3 and 1024^3 grids
+  (V = 5.8M, 23.8M, 95.3M); besides the digests, properties that hold at
+  any size: every vertex inside, handle loops = tunnel loops = swept genus
+  = Euler genus, one Reeb node per event plus the seed.
 """
 import json
 import os
@@ -21,23 +21,10 @@ from _digest import canon_gpu, digests
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "oracle_full.json")))
 
 
-@pytest.mark.parametrize("field_step", ["band", "dense"])
-def test_pretzel256_digests_match_oracle(field_step):
-    import paper_2105_13168_amd as vls
-    flags = vls.VLS_DENSE_FIELD if field_step == "dense" else 0
-    gold = json.load(open(os.path.join(HERE, "golden", "oracle_full.json")))["pretzel256_s0"]
-    m = mg.pretzel(256, rng_seed=0)
-    assert m.nv == gold["nv"] and m.seed == gold["seed_vertex"]
-    ctx = vls.Context(0)
-    M = vls.Mesh(ctx, m.xyz, m.tri)
-    try:
-        g = M.run(seed_vertex=m.seed, flags=flags)
-        d = digests(canon_gpu(g))
-    finally:
-        M.close()
-        ctx.close()
+def _check(d, gold):
     # sampled values first (a mismatch there says where)
     idx = np.array(gold["sample_idx"])
     assert d["sample_idx"] == gold["sample_idx"]
@@ -52,22 +39,42 @@ def test_pretzel256_digests_match_oracle(field_step):
         assert d[k] == gold[k], k
 
 
-def test_lattice10_grid256_properties():
+def _run(m, flags=0):
     import paper_2105_13168_amd as vls
-    m = mg.lattice(10, 256, rng_seed=0)
-    g_expect = mg.lattice_genus(10)
     ctx = vls.Context(0)
     M = vls.Mesh(ctx, m.xyz, m.tri)
     try:
-        r = M.run(seed_vertex=m.seed)
-        s = r.summary
-        assert s["run_status"] == 0
-        assert s["euler_genus"] == g_expect
-        assert s["n_inside"] == m.nv
-        assert s["n_handles"] == g_expect and s["n_tunnels"] == g_expect
-        assert s["swept_genus"] == g_expect
-        assert len(r.reeb_nodes) == s["n_events"] + 1
-        assert (r.step < np.iinfo(np.int32).max).all()
+        g = M.run(seed_vertex=m.seed, flags=flags)
+        return g, digests(canon_gpu(g))
     finally:
         M.close()
         ctx.close()
+
+
+@pytest.mark.parametrize("field_step", ["band", "dense"])
+def test_pretzel256_digests_match_oracle(field_step):
+    import paper_2105_13168_amd as vls
+    gold = GOLD["pretzel256_s0"]
+    m = mg.pretzel(256, rng_seed=0)
+    assert m.nv == gold["nv"] and m.seed == gold["seed_vertex"]
+    _g, d = _run(m, vls.VLS_DENSE_FIELD if field_step == "dense" else 0)
+    _check(d, gold)
+
+
+@pytest.mark.parametrize("grid", [256, 512, 1024])
+def test_lattice10_digests_match_oracle(grid):
+    name = f"lattice10_{grid}_s0"
+    if name not in GOLD:
+        pytest.skip(f"no oracle digest recorded for {name} (tests/golden/make_golden.py --full {name})")
+    gold = GOLD[name]
+    m = mg.lattice(10, grid, rng_seed=0)
+    assert m.nv == gold["nv"] and m.seed == gold["seed_vertex"]
+    g_expect = mg.lattice_genus(10)
+    g, d = _run(m)
+    s = g.summary
+    assert s["run_status"] == 0
+    assert s["euler_genus"] == g_expect and s["swept_genus"] == g_expect
+    assert s["n_inside"] == m.nv
+    assert s["n_handles"] == g_expect and s["n_tunnels"] == g_expect
+    assert len(g.reeb_nodes) == s["n_events"] + 1
+    _check(d, gold)
