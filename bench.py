@@ -392,10 +392,52 @@ def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=Fals
         "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
         "mean_ms": float(lat_ms.mean()), "mean_queue_ms": float(np.mean(queue_ms)),
         "meshes_per_s": n_req / makespan, "makespan_s": makespan, "launches": stats["launches"],
+        "scheduler_ms": {k: round(stats[k], 1) for k in ("admit_ms", "launch_ms", "complete_ms")},
         "sequential": {"p50_ms": float(np.percentile(seq_lat, 50)), "p99_ms": float(np.percentile(seq_lat, 99)),
                        "meshes_per_s": n_req / (free_at - 0.0) if free_at > 0 else None,
                        "service_ms_mean": 1e3 * float(np.mean([service[int(i)] for i in pick]))},
     }
+
+
+def passes_leg(ctx, workload):
+    """The tunnel-loop pass of every handle loop and the refinement pass of
+    every tunnel after one initial pass (vls_run with VLS_REFINE_PASS): pass
+    launches timed on the device, loops found, and the passes' field steps
+    against HBM (32 + 4 deg bytes per vertex update, deg the mean degree)."""
+    import ctypes as C
+    import paper_2105_13168_amd as vls
+    m, desc = make_workload(workload)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_DEFER_RESULTS | vls.VLS_REFINE_PASS)
+    h = C.c_void_p()
+    st = vls.vls_run(ctx.h, M.h, C.byref(p), C.byref(h))
+    if st != 0:
+        raise vls.VLSError(st, ctx.last_error())
+    s = vls.vls_summary()
+    vls.vls_result_summary(h, C.byref(s))
+    labels = {3: [0, 0], 4: [0, 0]}
+    for kind, cnt in ((3, s.n_tunnel_passes), (4, s.n_refine_passes)):
+        for i in range(cnt):
+            lab = C.c_int32()
+            vls.vls_result_pass_info(h, kind, i, None, None, None, C.byref(lab), None, None)
+            if lab.value >= 0:
+                labels[kind][lab.value] += 1
+    vls.vls_result_destroy(h)
+    M.close()
+    ms = s.tunnel_pass_ms + s.refine_pass_ms
+    deg = 3.0 * m.nf / m.nv                   # mean degree: 2E / V = 3F / V
+    ab = s.pass_vertex_updates * (32.0 + 4.0 * deg)
+    return {"workload": desc, "nv": m.nv, "handles": s.n_handles,
+            "tunnel_passes": s.n_tunnel_passes, "tunnel_loops": s.n_tunnel_loops,
+            "refine_passes": s.n_refine_passes, "refined_loops": s.n_refined_loops,
+            "labels_tunnel_pass_handle_tunnel": labels[3], "labels_refine_pass_handle_tunnel": labels[4],
+            "pass_slots": s.pass_slots, "tunnel_pass_ms": s.tunnel_pass_ms, "refine_pass_ms": s.refine_pass_ms,
+            "passes_per_s": (s.n_tunnel_passes + s.n_refine_passes) / (ms * 1e-3) if ms > 0 else None,
+            "pass_vertex_updates": s.pass_vertex_updates,
+            "roofline": {"bound": "hbm", "achieved": ab / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                         "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if ms > 0 else None,
+                         "kernel": "k_passes"}}
 
 
 def host_cpu():
@@ -436,6 +478,15 @@ def cpu_baseline(workload, max_steps, head=None):
            "seconds": round(dt, 3), "oracle_updates_per_s": upd_rate, "sample_vertex_steps_per_s": m.nv * r.steps / dt,
            "host_cpu": model, "host_nproc": ncpu,
            "threads_note": "the oracle is sequential C (no threads); nproc copies would not share one pass"}
+    # the oracle's whole pass of the full workloads, timed when their digests
+    # were recorded (build container, one core): context for the sample
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "oracle_full.json")) as f:
+            gold = json.load(f)
+        out["oracle_whole_pass_seconds_recorded"] = {k: v["oracle_seconds"] for k, v in gold.items()
+                                                     if "oracle_seconds" in v}
+    except (OSError, ValueError, KeyError):
+        pass
     if head is not None:
         nv, steps, updates = head
         out["value"] = upd_rate * (nv * steps / updates)
@@ -473,6 +524,8 @@ def main():
                     help="mesh of the dense-step leg ('same': the main workload's mesh; 'none': skip)")
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--dense", action="store_true", help="time the whole pass with the dense field step")
+    ap.add_argument("--passes-workload", default="lattice10_256",
+                    help="mesh of the tunnel-loop / refinement pass leg ('none': skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -599,6 +652,12 @@ def main():
             log(f"pretzel leg done ({time.time() - t_start:.0f}s since start)")
         else:
             skipped.append("pretzel_pass")
+    if args.passes_workload != "none":
+        if left() > 60:
+            out["passes"] = passes_leg(ctx, args.passes_workload)
+            log(f"passes leg done ({time.time() - t_start:.0f}s since start)")
+        else:
+            skipped.append("passes")
     if args.batch > 0:
         if left() > 75:
             out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample, tune=args.tune)

@@ -81,6 +81,11 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
                                     update list (streams the whole mesh each step; vls_run's default
                                     grid is then every co-resident workgroup); identical results;
                                     meshes below 2^29 vertices (else VLS_E_INVALID_ARG) */
+#define VLS_TUNNEL_PASS 128u     /* vls_run only: after the initial pass, a tunnel-loop pass for every
+                                    handle loop (Section "Tunnel loop pass"): loops of kind 3 */
+#define VLS_REFINE_PASS 256u     /* vls_run only: also a handle-refinement pass for every tunnel of the
+                                    tunnel-loop pass (Section "Handle refinement pass"): loops of
+                                    kind 4; implies VLS_TUNNEL_PASS */
 #define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]) and the server (creation
                                     flags): two workgroups per CU, each with a 1024-candidate LDS
                                     topology path and one list entry per field thread; default: one
@@ -113,6 +118,10 @@ typedef struct vls_params {
     int64_t gang_vertices;     /* vls_batch_run / server (per_mesh[0] for a batch): a mesh
                                   gets one workgroup per this many vertices (at least 2 to
                                   form a gang, at most 64); 0 = 65536                     */
+    int32_t pass_slots;        /* tunnel-loop / refinement passes run at once (each on one
+                                  workgroup with its own per-vertex state); 0 = as many as
+                                  co-resident workgroups and a quarter of free memory allow */
+    int32_t reserved;
 } vls_params;
 
 struct vls_context;
@@ -250,6 +259,16 @@ typedef struct {
     /* event resolution split: merge loop walks and output, split walkers,
        relabel walks, the rest (classification, ids, records) */
     double event_split_ms[4];
+    /* tunnel-loop / handle-refinement passes (VLS_TUNNEL_PASS, VLS_REFINE_PASS):
+       passes run and passes that produced a loop, passes run at once,
+       device time of each kind's launch, and the vertex updates of all */
+    int32_t n_tunnel_passes, n_tunnel_loops, n_refine_passes, n_refined_loops;
+    int32_t pass_slots, pass_pad;
+    double tunnel_pass_ms, refine_pass_ms;
+    int64_t pass_vertex_updates;
+    /* topology steps on the global-memory path: candidates, closure,
+       classification, insertion and events (device clock) */
+    double topo_global_split_ms[4];
 } vls_summary;
 vls_status vls_result_summary(const struct vls_result *r, vls_summary *s);
 
@@ -276,9 +295,29 @@ vls_status vls_result_event_fronts(const struct vls_result *r, int64_t cap, int6
  * edges_uv[*][0] (edges_uv[*][1] = next vertex); pts/length for its vertex
  * polyline.  kind 2 = every involved loop of every merge (handle loops and
  * the ignored longest one), in event order.
+ * kind 3 = the tunnel loop of handle loop i from the tunnel-loop pass, kind
+ * 4 = the refined handle loop of tunnel i from the handle-refinement pass
+ * (with VLS_TUNNEL_PASS / VLS_REFINE_PASS): closed vertex paths, written as
+ * kind 1 (edges_uv[*][0] the vertices, pts their positions, length the
+ * closed polyline's); n_out = 0 when that pass produced no loop.
  */
 vls_status vls_result_loop(const struct vls_result *r, int32_t kind, int32_t i, int64_t cap,
                            int32_t *edges_uv, double *pts, double *length, int64_t *n_out);
+/*
+ * Outcome of pass i of kind 3 (tunnel-loop) or 4 (handle-refinement)
+ * (Sections "Tunnel loop pass", "Handle refinement pass", "Distinguishing
+ * handle and tunnel loops"): status (0; VLS_E_STALLED when the diffusion
+ * stopped before reaching the other side; VLS_E_INVALID_ARG when its
+ * source loop was missing or degenerate; VLS_E_CAPACITY when the loop
+ * buffer overflowed), diffusion steps, the vertex reached first on the
+ * other side, and the normal-offset test: label 0 = handle (the loop grows
+ * when moved along the surface normals by a tenth of its mean edge length),
+ * 1 = tunnel (it shrinks), -1 = no loop; length and offset length.
+ * Any output pointer may be NULL.
+ */
+vls_status vls_result_pass_info(const struct vls_result *r, int32_t kind, int32_t i, int32_t *status,
+                                int64_t *steps, int32_t *reached, int32_t *label, double *length,
+                                double *offset_length);
 /* per-loop info for kind 0 or 2: event index, front id, kept (1 = handle loop) */
 vls_status vls_result_loop_info(const struct vls_result *r, int32_t kind, int32_t i,
                                 int64_t *event, int64_t *front_id, int32_t *kept);
@@ -336,6 +375,9 @@ vls_status vls_batch_run(struct vls_context *ctx, int32_t n, const struct vls_me
  *   launches finished requests are completed (post-passes, results to host)
  *   and queued ones admitted as slots and budget free up.  A request's
  *   results are identical to a vls_run of the same mesh and parameters.
+ *   The run state of finished requests is kept for later requests of the
+ *   same mesh (up to a quarter of hbm_budget_bytes, outside the budget), so
+ *   a repeated mesh is admitted without allocating.
  * vls_server_poll: VLS_E_PENDING until the request is done; then *out
  *   receives its result (owned by the caller) and the call returns the run
  *   status; the ticket is then forgotten.  Thread-safe.
@@ -358,6 +400,11 @@ vls_status vls_server_poll(struct vls_server *srv, uint64_t ticket, struct vls_r
    state currently admitted (bytes), requests queued and running */
 vls_status vls_server_stats(const struct vls_server *srv, int64_t *launches, int64_t *completed,
                             int64_t *admitted_bytes, int32_t *queued, int32_t *running);
+/* host time the scheduler thread has spent admitting requests (run state,
+   seed initialisation), launching slices (including the wait for each), and
+   completing finished requests (post-passes, results to host), in ms */
+vls_status vls_server_timing(const struct vls_server *srv, double *admit_ms, double *launch_ms,
+                             double *complete_ms);
 vls_status vls_server_shutdown(struct vls_server *srv);
 vls_status vls_server_destroy(struct vls_server *srv);
 

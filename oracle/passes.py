@@ -254,15 +254,27 @@ def refine_pass(g: MeshGraph, cycle, **kw):
 
 
 def vertex_normals(g: MeshGraph):
-    """Area-weighted vertex normals: the sum of the incident triangles'
-    cross products, normalised."""
+    """Area-weighted vertex normals: the cross products of a vertex's
+    triangles (w, c_j, c_j+1) over its counter-clockwise link from its
+    smallest neighbour id, summed in that order, normalised."""
     p = g.xyz
-    t = g.tri
-    fn = np.cross(p[t[:, 1]] - p[t[:, 0]], p[t[:, 2]] - p[t[:, 0]])
     n = np.zeros_like(p)
-    for k in range(3):
-        np.add.at(n, t[:, k], fn)
-    return n / np.linalg.norm(n, axis=1)[:, None]
+    for w in range(g.nv):
+        s = g._succ[w]
+        c0 = min(s)
+        link = [c0]
+        while len(link) < len(s):
+            link.append(s[link[-1]])
+        sx = sy = sz = 0.0
+        for j in range(len(link)):
+            a = p[link[j]] - p[w]
+            b = p[link[(j + 1) % len(link)]] - p[w]
+            sx = sx + (a[1] * b[2] - a[2] * b[1])
+            sy = sy + (a[2] * b[0] - a[0] * b[2])
+            sz = sz + (a[0] * b[1] - a[1] * b[0])
+        ln = math.sqrt((sx * sx + sy * sy) + sz * sz)
+        n[w] = (sx / ln, sy / ln, sz / ln)
+    return n
 
 
 def offset_label(g: MeshGraph, cycle, normals, rel_eps=0.1):

@@ -35,6 +35,8 @@ VLS_COHERENT_SHARING = 8
 VLS_LOCKSTEP = 16
 VLS_BATCH_TWO_PER_CU = 32
 VLS_DENSE_FIELD = 64
+VLS_TUNNEL_PASS = 128
+VLS_REFINE_PASS = 256
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 
@@ -46,7 +48,7 @@ class vls_params(C.Structure):
                 ("seed_radius", C.c_int32), ("stall_steps", C.c_int32),
                 ("max_steps", C.c_int64), ("flags", C.c_uint32), ("n_ckpt", C.c_int32),
                 ("ckpt_steps", C.POINTER(C.c_int64)), ("grid", C.c_int32), ("block", C.c_int32),
-                ("gang_vertices", C.c_int64)]
+                ("gang_vertices", C.c_int64), ("pass_slots", C.c_int32), ("reserved", C.c_int32)]
 
 
 class vls_summary(C.Structure):
@@ -62,7 +64,12 @@ class vls_summary(C.Structure):
                 ("topo_rounds_ms", C.c_double), ("topo_round_steps", C.c_int32),
                 ("topo_global_steps", C.c_int32), ("server_queue_ms", C.c_double),
                 ("server_latency_ms", C.c_double), ("field_barrier_ms", C.c_double),
-                ("event_split_ms", C.c_double * 4)]
+                ("event_split_ms", C.c_double * 4),
+                ("n_tunnel_passes", C.c_int32), ("n_tunnel_loops", C.c_int32),
+                ("n_refine_passes", C.c_int32), ("n_refined_loops", C.c_int32),
+                ("pass_slots", C.c_int32), ("pass_pad", C.c_int32),
+                ("tunnel_pass_ms", C.c_double), ("refine_pass_ms", C.c_double),
+                ("pass_vertex_updates", C.c_int64), ("topo_global_split_ms", C.c_double * 4)]
 
 
 class vls_reeb_node(C.Structure):
@@ -111,6 +118,9 @@ _sig = {
     "vls_result_loop": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P,
                                     C.POINTER(C.c_double), _I64P]),
     "vls_result_loop_info": (C.c_int32, [_P, C.c_int32, C.c_int32, _I64P, _I64P, C.POINTER(C.c_int32)]),
+    "vls_result_pass_info": (C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), _I64P,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]),
     "vls_result_reeb": (C.c_int32, [_P, C.c_int64, _P, C.c_int64, _P, _I64P, _I64P]),
     "vls_result_field": (C.c_int32, [_P, C.c_int64, _P]),
     "vls_result_vertices": (C.c_int32, [_P, _P, _P, _P]),
@@ -120,6 +130,7 @@ _sig = {
     "vls_server_submit": (C.c_int32, [_P, _P, C.POINTER(vls_params), C.POINTER(C.c_uint64)]),
     "vls_server_poll": (C.c_int32, [_P, C.c_uint64, _PP]),
     "vls_server_stats": (C.c_int32, [_P, _I64P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "vls_server_timing": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "vls_server_shutdown": (C.c_int32, [_P]),
     "vls_server_destroy": (C.c_int32, [_P]),
 }
@@ -279,6 +290,22 @@ class Result:
             uv = np.zeros((cnt.value, 2), dtype=np.int32)
             vls_result_loop(h, 1, i, cnt.value, uv.ctypes.data, None, C.byref(L), C.byref(cnt))
             self.tunnels.append(uv[:, 0].copy())
+        # tunnel-loop (kind 3) and handle-refinement (kind 4) passes
+        self.passes = {3: [], 4: []}
+        for kind, cnt in ((3, self.summary["n_tunnel_passes"]), (4, self.summary["n_refine_passes"])):
+            for i in range(cnt):
+                st, steps, reached, label = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32()
+                L, L1 = C.c_double(), C.c_double()
+                vls_result_pass_info(h, kind, i, C.byref(st), C.byref(steps), C.byref(reached), C.byref(label),
+                                     C.byref(L), C.byref(L1))
+                n = C.c_int64()
+                vls_result_loop(h, kind, i, 0, None, None, None, C.byref(n))
+                uv = np.zeros((n.value, 2), dtype=np.int32)
+                if n.value:
+                    vls_result_loop(h, kind, i, n.value, uv.ctypes.data, None, None, C.byref(n))
+                self.passes[kind].append(dict(status=st.value, steps=steps.value, reached=reached.value,
+                                              label=label.value, length=L.value, offset_length=L1.value,
+                                              cycle=uv[:, 0].copy()))
         nn, ne = C.c_int64(), C.c_int64()
         vls_result_reeb(h, 0, None, 0, None, C.byref(nn), C.byref(ne))
         nodes = (vls_reeb_node * max(1, nn.value))()
@@ -384,8 +411,11 @@ class Server:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
         q, r = C.c_int32(), C.c_int32()
         vls_server_stats(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(q), C.byref(r))
+        x, y, z = C.c_double(), C.c_double(), C.c_double()
+        vls_server_timing(self.h, C.byref(x), C.byref(y), C.byref(z))
         return {"launches": a.value, "completed": b.value, "admitted_bytes": c.value,
-                "queued": q.value, "running": r.value}
+                "queued": q.value, "running": r.value, "admit_ms": x.value, "launch_ms": y.value,
+                "complete_ms": z.value}
 
     def close(self):
         if getattr(self, "h", None):

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvls.so")
-SOURCES = [os.path.join(CSRC, "vls_api.cpp"), os.path.join(CSRC, "vls_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "vls_api.cpp"), os.path.join(CSRC, "vls_kernels.hip"),
+           os.path.join(CSRC, "vls_passes.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

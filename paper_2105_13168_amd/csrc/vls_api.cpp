@@ -93,6 +93,10 @@ struct vls_result {
     std::vector<int64_t> ckpt_steps;
     std::vector<double> ckpt;            // [n_ckpt][nv]
     std::vector<int32_t> ckpt_ok;
+    // tunnel-loop (index 0) and handle-refinement (index 1) passes
+    std::vector<PassResult> pres[2];
+    std::vector<int32_t> pout[2];
+    std::vector<double> pass_xyz;        // mesh positions, kept when the passes ran
 };
 
 static vls_status set_err(vls_context *ctx, vls_status s, const char *fmt, ...) {
@@ -454,6 +458,7 @@ static size_t post_bytes(const vls_mesh *m) {
 struct RunBuffers {
     DevArena arena;
     DState s{};
+    int64_t nv = 0, nnz = 0, genus = 0;   // the mesh shape it was sized for
     ~RunBuffers() { arena.release(); }
 };
 
@@ -469,6 +474,9 @@ static size_t run_buffer_bytes(const vls_mesh *m) {
 
 static vls_status make_run_buffers(vls_mesh *m, RunBuffers **out) {
     auto rb = std::make_unique<RunBuffers>();
+    rb->nv = m->nv;
+    rb->nnz = m->nnz;
+    rb->genus = m->euler_genus;
     hipError_t e = alloc_state(m, rb->arena, rb->s);
     if (e != hipSuccess) return set_err(m->ctx, VLS_E_OUT_OF_MEMORY, "device allocation failed: %s", hipGetErrorString(e));
     *out = rb.release();
@@ -671,7 +679,9 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     if (p->block != 0 && p->block != 256) return set_err(ctx, VLS_E_INVALID_ARG, "block must be 256");
     if ((p->flags & VLS_DENSE_FIELD) && nv >= (int64_t)1 << 29)
         return set_err(ctx, VLS_E_INVALID_ARG, "VLS_DENSE_FIELD needs fewer than 2^29 vertices");
-    if (p->n_ckpt < 0) return set_err(ctx, VLS_E_INVALID_ARG, "n_ckpt");
+    if (p->n_ckpt < 0 || p->pass_slots < 0) return set_err(ctx, VLS_E_INVALID_ARG, "n_ckpt / pass_slots");
+    if ((p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS)) && (priv || ws))
+        return set_err(ctx, VLS_E_INVALID_ARG, "the tunnel-loop and refinement passes run with vls_run only");
     rp.m = m;
     rp.seed = seed;
     rp.rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
@@ -865,6 +875,135 @@ static vls_status post_passes(vls_context *ctx, RunPrep &rp, const Ctl &c, vls_r
     return VLS_OK;
 }
 
+// Tunnel-loop passes of every handle loop and, with VLS_REFINE_PASS, the
+// refinement pass of every tunnel, after the initial pass (vls_run only).
+// As many passes run at once as there are co-resident workgroups and slots
+// of per-vertex state within a quarter of the free device memory (the
+// paper's rule: as many passes as memory allows).
+static vls_status run_passes(vls_context *ctx, RunPrep &rp, const vls_params *p, const Ctl &c, vls_result &r) {
+    const bool refine = (p->flags & VLS_REFINE_PASS) != 0;
+    if (!(p->flags & VLS_TUNNEL_PASS) && !refine) return VLS_OK;
+    vls_mesh *m = rp.m;
+    hipStream_t stream = rp.stream;
+    const int nl = c.n_loops;
+    std::vector<int64_t> lp((size_t)nl * 8);
+    if (nl) HIPCHK(ctx, hipMemcpyAsync(lp.data(), rp.s.lp, lp.size() * 8, hipMemcpyDeviceToHost, stream));
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    std::vector<PassTask> tun;
+    for (int i = 0; i < nl; ++i)
+        if (lp[8 * (size_t)i + 2]) tun.push_back(PassTask{0, i});
+    const int nt = (int)tun.size();
+    vls_summary &S = r.sum;
+    S.n_tunnel_passes = nt;
+    S.n_refine_passes = refine ? nt : 0;
+    if (nt == 0) return VLS_OK;
+    // slots
+    const int64_t nv = m->nv, nnz = m->nnz;
+    DevArena cnt;
+    cnt.mode = DevArena::COUNT;
+    PassSlot tmpl{};
+    auto alloc_slot = [&](DevArena &A, PassSlot &q) -> hipError_t {
+        hipError_t e = hipSuccess;
+#define P_(ptr, n) if (e == hipSuccess) e = A.get(&(ptr), (size_t)(n))
+        P_(q.rho, nv); P_(q.tmp, nv); P_(q.ta, nv); P_(q.prev, nv); P_(q.key, nv); P_(q.par, nv);
+        P_(q.mark, nv); P_(q.cst, nv); P_(q.upd, nv); P_(q.flag, nv); P_(q.pos, nv); P_(q.U[0], nv);
+        P_(q.U[1], nv); P_(q.cand, nv); P_(q.pend[0], nv); P_(q.pend[1], nv); P_(q.touched, nv);
+        P_(q.flist, nv); P_(q.buf, nv); P_(q.side, nv); P_(q.cutbits, nnz / 32 + 1); P_(q.cutpos, nnz);
+#undef P_
+        return e;
+    };
+    (void)alloc_slot(cnt, tmpl);
+    const size_t slot_bytes = cnt.used;
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(ctx, hipMemGetInfo(&free_b, &total_b));
+    const int maxg = max_coresident_passes();
+    if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query of the pass kernel failed");
+    int64_t ns = std::min<int64_t>({(int64_t)nt, (int64_t)maxg, (int64_t)(free_b / 4 / slot_bytes)});
+    if (p->pass_slots > 0) ns = std::min<int64_t>(ns, p->pass_slots);
+    if (ns < 1) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "no memory for one pass slot (%zu bytes)", slot_bytes);
+    DevArena A;   // hipMalloc'ed, released on return
+    struct Rel { DevArena &a; ~Rel() { a.release(); } } rel{A};
+    std::vector<PassSlot> slots((size_t)ns);
+    for (auto &q : slots) {
+        if (alloc_slot(A, q) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "pass slots");
+        HIPCHK(ctx, launch_pass_slot_init(q, (int32_t)nv, nnz, stream));
+    }
+    PassSlot *dslots = nullptr;
+    PassTask *dtasks = nullptr;
+    PassResult *dres[2] = {nullptr, nullptr};
+    int32_t *dout[2] = {nullptr, nullptr};
+    int *dnext = nullptr;
+    unsigned long long *dused = nullptr;
+    const int64_t out_cap = 2 * nv + (1 << 20);
+    if (A.get(&dslots, (size_t)ns) || A.get(&dtasks, (size_t)nt) || A.get(&dres[0], (size_t)nt) ||
+        A.get(&dres[1], (size_t)nt) || A.get(&dout[0], (size_t)out_cap) || A.get(&dout[1], (size_t)out_cap) ||
+        A.get(&dnext, 2) || A.get(&dused, 2))
+        return set_err(ctx, VLS_E_OUT_OF_MEMORY, "pass buffers");
+    HIPCHK(ctx, hipMemcpyAsync(dslots, slots.data(), slots.size() * sizeof(PassSlot), hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemsetAsync(dnext, 0, 2 * sizeof(int), stream));
+    HIPCHK(ctx, hipMemsetAsync(dused, 0, 2 * sizeof(unsigned long long), stream));
+    PassArgs a{};
+    a.m = m->d;
+    a.s = rp.s;
+    a.nslots = (int)ns;
+    a.slots = dslots;
+    a.out_cap = out_cap;
+    a.tau = rp.dp.tau;
+    a.a = rp.dp.a;
+    a.w = rp.dp.w;
+    a.e = rp.dp.e;
+    a.c = rp.dp.c;
+    a.max_steps = p->max_steps;
+    a.stall_steps = p->stall_steps;
+    a.rel_eps = 0.1;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    struct EvRel { hipEvent_t *e; ~EvRel() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } evrel{ev};
+    for (auto &e : ev) HIPCHK(ctx, hipEventCreate(&e));
+    HIPCHK(ctx, hipEventRecord(ev[0], stream));
+    for (int k = 0; k < (refine ? 2 : 1); ++k) {
+        std::vector<PassTask> tasks(tun);
+        if (k == 1)
+            for (int i = 0; i < nt; ++i) tasks[i] = PassTask{1, i};
+        HIPCHK(ctx, hipMemcpyAsync(dtasks, tasks.data(), nt * sizeof(PassTask), hipMemcpyHostToDevice, stream));
+        a.tasks = dtasks;
+        a.ntasks = nt;
+        a.next = dnext + k;
+        a.res = dres[k];
+        a.out = dout[k];
+        a.out_used = dused + k;
+        a.src_res = dres[0];
+        a.src_out = dout[0];
+        HIPCHK(ctx, launch_passes(a, stream));
+        HIPCHK(ctx, hipEventRecord(ev[k + 1], stream));
+    }
+    unsigned long long used[2] = {0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(used, dused, sizeof used, hipMemcpyDeviceToHost, stream));
+    for (int k = 0; k < (refine ? 2 : 1); ++k) {
+        r.pres[k].resize(nt);
+        HIPCHK(ctx, hipMemcpyAsync(r.pres[k].data(), dres[k], nt * sizeof(PassResult), hipMemcpyDeviceToHost, stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    for (int k = 0; k < (refine ? 2 : 1); ++k) {
+        const int64_t nu = std::min<int64_t>((int64_t)used[k], out_cap);
+        r.pout[k].resize((size_t)nu);
+        if (nu) HIPCHK(ctx, hipMemcpyAsync(r.pout[k].data(), dout[k], nu * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    float ms0 = 0.f, ms1 = 0.f;
+    (void)hipEventElapsedTime(&ms0, ev[0], ev[1]);
+    if (refine) (void)hipEventElapsedTime(&ms1, ev[1], ev[2]);
+    S.tunnel_pass_ms = ms0;
+    S.refine_pass_ms = ms1;
+    S.pass_slots = (int32_t)ns;
+    r.pass_xyz = m->xyz;
+    for (int k = 0; k < 2; ++k)
+        for (const PassResult &q : r.pres[k]) {
+            S.pass_vertex_updates += q.updates;
+            if (q.status == 0) (k ? S.n_refined_loops : S.n_tunnel_loops) += 1;
+        }
+    return VLS_OK;
+}
+
 // after the step kernel: post-passes, summary, result object r (bulk
 // results deferred until fetched unless copied here)
 static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p, int grid, int block,
@@ -879,6 +1018,8 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     vls_result *r = &R;
     r->nv = nv;
     if (vls_status ps = post_passes(ctx, rp, c, *r)) return ps;
+    if (c.status == 0)
+        if (vls_status ps = run_passes(ctx, rp, p, c, *r)) return ps;
     float ms_k = 0.f, ms_t = 0.f;
     if (!rp.ws) {
         HIPCHK(ctx, hipEventRecord(rp.e3, stream));
@@ -931,6 +1072,7 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     S.topo_global_steps = c.n_global_steps;
     S.field_barrier_ms = (double)c.clk_fbar * 1e-5;
     for (int q = 0; q < 4; ++q) S.event_split_ms[q] = (double)c.clk_evp[q] * 1e-5;
+    for (int q = 0; q < 4; ++q) S.topo_global_split_ms[q] = (double)c.clk_g[q] * 1e-5;
     vls_status rs = c.status;
     if (rs == VLS_E_INVARIANT || rs == VLS_E_CAPACITY)
         set_err(ctx, rs, "device reported %s (detail %d) at step %lld", vls_status_string(rs), c.err_code, (long long)c.steps);
@@ -1181,6 +1323,9 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
         for (int32_t j = 0; j < i; ++j)
             if (meshes[j] == meshes[i]) return set_err(ctx, VLS_E_INVALID_ARG, "mesh %d appears twice in the batch", i);
     }
+    for (int32_t i = 0; i < n; ++i)
+        if (per_mesh[i].flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS))
+            return set_err(ctx, VLS_E_INVALID_ARG, "the tunnel-loop and refinement passes run with vls_run only");
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
     hipStream_t stream = ctx->stream;
     std::vector<RunPrep> preps(n);
@@ -1323,6 +1468,23 @@ vls_status vls_result_loop(const vls_result *r, int32_t kind, int32_t i, int64_t
         if (pts) std::memcpy(pts, r->lp_pts.data() + 3 * off, n * 3 * sizeof(double));
         return VLS_OK;
     }
+    if (kind == 3 || kind == 4) {
+        const std::vector<PassResult> &v = r->pres[kind - 3];
+        if (i < 0 || i >= (int32_t)v.size()) return VLS_E_INVALID_ARG;
+        const PassResult &q = v[i];
+        const int64_t n = q.status == 0 ? q.n : 0;
+        *n_out = n;
+        if (length) *length = q.status == 0 ? q.length : 0.0;
+        if (cap == 0 || n == 0) return VLS_OK;
+        if (cap < n) return VLS_E_BUFFER_TOO_SMALL;
+        const int32_t *c = r->pout[kind - 3].data() + q.off;
+        const double *xyz = r->pass_xyz.data();
+        for (int64_t k = 0; k < n; ++k) {
+            if (edges_uv) { edges_uv[2 * k] = c[k]; edges_uv[2 * k + 1] = c[(k + 1) % n]; }
+            if (pts) std::memcpy(pts + 3 * k, xyz + 3 * (int64_t)c[k], 3 * sizeof(double));
+        }
+        return VLS_OK;
+    }
     if (kind == 1) {
         const int64_t nt = (int64_t)r->tn.size() / 4;
         if (i < 0 || i >= nt) return VLS_E_INVALID_ARG;
@@ -1339,6 +1501,22 @@ vls_status vls_result_loop(const vls_result *r, int32_t kind, int32_t i, int64_t
         return VLS_OK;
     }
     return VLS_E_INVALID_ARG;
+}
+
+vls_status vls_result_pass_info(const vls_result *r, int32_t kind, int32_t i, int32_t *status, int64_t *steps,
+                                int32_t *reached, int32_t *label, double *length, double *offset_length) {
+    if (!r || (kind != 3 && kind != 4)) return VLS_E_INVALID_ARG;
+    if (vls_status fs = ensure(r)) return fs;
+    const std::vector<PassResult> &v = r->pres[kind - 3];
+    if (i < 0 || i >= (int32_t)v.size()) return VLS_E_INVALID_ARG;
+    const PassResult &q = v[i];
+    if (status) *status = q.status;
+    if (steps) *steps = q.steps;
+    if (reached) *reached = q.reached;
+    if (label) *label = q.status == 0 ? q.label : -1;
+    if (length) *length = q.status == 0 ? q.length : 0.0;
+    if (offset_length) *offset_length = q.status == 0 ? q.offset_length : 0.0;
+    return VLS_OK;
 }
 
 vls_status vls_result_loop_info(const vls_result *r, int32_t kind, int32_t i, int64_t *event, int64_t *front_id,
@@ -1497,10 +1675,41 @@ struct vls_server {
     int cap = 0;
     std::vector<int32_t> hdone;
     std::string thread_err;
+    // run state of finished requests kept for the next request of the same
+    // mesh shape (no allocation on admission), up to pool_cap bytes; one
+    // post-pass scratch reused by every completion (grown when needed)
+    std::unordered_map<const vls_mesh *, std::vector<std::unique_ptr<RunBuffers>>> pool;
+    size_t pooled = 0, pool_cap = 0;
+    void *post_buf = nullptr;
+    size_t post_cap = 0;
+    // host time of the scheduler's phases (ms): admissions, launches incl.
+    // their wait, completions
+    double t_admit_ms = 0.0, t_launch_ms = 0.0, t_complete_ms = 0.0;
 
     ~vls_server() {
         for (void *q : {dm, ds, dp, dord, dnext, ddone, dtg, dsl}) if (q) (void)hipFree(q);
+        pool.clear();
+        if (post_buf) (void)hipFree(post_buf);
         if (ctx.own_stream && ctx.stream) (void)hipStreamDestroy(ctx.stream);
+    }
+    std::unique_ptr<RunBuffers> take_buffers(const vls_mesh *m) {
+        auto it = pool.find(m);
+        if (it == pool.end()) return nullptr;
+        while (!it->second.empty()) {
+            std::unique_ptr<RunBuffers> rb = std::move(it->second.back());
+            it->second.pop_back();
+            const size_t b = rb->arena.used;
+            pooled -= b;
+            if (rb->nv == m->nv && rb->nnz == m->nnz && rb->genus == m->euler_genus) return rb;
+        }
+        return nullptr;
+    }
+    void give_buffers(const vls_mesh *m, std::unique_ptr<RunBuffers> rb) {
+        if (!rb) return;
+        const size_t b = rb->arena.used;
+        if (pooled + b > pool_cap) return;       // freed
+        pooled += b;
+        pool[m].push_back(std::move(rb));
     }
     void finish(SrvReq *q, vls_status st, vls_result *r);
     void complete(SrvReq *q);
@@ -1511,6 +1720,7 @@ struct vls_server {
 
 // marks q done (status, result), releases its admission charge
 void vls_server::finish(SrvReq *q, vls_status st, vls_result *r) {
+    if (st == VLS_OK || is_run_status(st)) give_buffers(q->m, std::move(q->rb));
     q->rb.reset();
     q->prep.reset();
     std::lock_guard<std::mutex> lk(mu);
@@ -1529,6 +1739,19 @@ void vls_server::finish(SrvReq *q, vls_status st, vls_result *r) {
 // a request whose step kernel finished: post-passes, results to the host
 void vls_server::complete(SrvReq *q) {
     if (hipEventRecord(q->prep->e2, ctx.stream) != hipSuccess) { finish(q, VLS_E_DEVICE, nullptr); return; }
+    // post-pass scratch: the server's reusable block
+    const size_t need = post_bytes(q->m);
+    if (need > post_cap) {
+        if (post_buf) (void)hipFree(post_buf);
+        post_buf = nullptr;
+        post_cap = 0;
+        if (hipMalloc(&post_buf, need) != hipSuccess) { post_buf = nullptr; finish(q, VLS_E_OUT_OF_MEMORY, nullptr); return; }
+        post_cap = need;
+    }
+    q->prep->post.mode = DevArena::CARVE;
+    q->prep->post.base = (char *)post_buf;
+    q->prep->post.cap = post_cap;
+    q->prep->post.used = 0;
     auto r = std::make_unique<vls_result>();
     vls_status rs = finish_run(&ctx, *q->prep, &q->p, 0, 256, -1.0, *r);
     if (rs != VLS_OK && !is_run_status(rs)) { finish(q, rs, nullptr); return; }
@@ -1538,10 +1761,14 @@ void vls_server::complete(SrvReq *q) {
 // device run state and seed initialisation of a newly admitted request
 bool vls_server::admit_one(SrvReq *q) {
     q->t_admit = Clock::now();
-    RunBuffers *rb = nullptr;
-    vls_status st = make_run_buffers(q->m, &rb);
-    if (st) { finish(q, st, nullptr); return false; }
-    q->rb.reset(rb);
+    q->rb = take_buffers(q->m);
+    vls_status st = VLS_OK;
+    if (!q->rb) {
+        RunBuffers *rb = nullptr;
+        st = make_run_buffers(q->m, &rb);
+        if (st) { finish(q, st, nullptr); return false; }
+        q->rb.reset(rb);
+    }
     q->prep = std::make_unique<RunPrep>();
     vls_params pp = q->p;
     pp.ckpt_steps = q->ckpt.empty() ? nullptr : q->ckpt.data();
@@ -1554,6 +1781,7 @@ bool vls_server::admit_one(SrvReq *q) {
 // one bounded launch over the running requests (largest first); false on a
 // device error (every running request then fails)
 bool vls_server::launch_slice() {
+    const auto tl = Clock::now();
     const int n = (int)active.size();
     if (n > cap) {
         for (void *q : {dm, ds, dp, dord, dnext, ddone, dtg, dsl}) if (q) (void)hipFree(q);
@@ -1604,6 +1832,8 @@ bool vls_server::launch_slice() {
         hipStreamSynchronize(st))
         return false;
     launches += 1;
+    const auto tc = Clock::now();
+    t_launch_ms += ms_between(tl, tc);
     // done_out is indexed by visit order
     std::vector<SrvReq *> still;
     std::vector<SrvReq *> fin;
@@ -1612,6 +1842,7 @@ bool vls_server::launch_slice() {
     for (int i = 0; i < n; ++i) (flag[i] ? fin : still).push_back(active[i]);
     active.swap(still);
     for (SrvReq *q : fin) complete(q);
+    t_complete_ms += ms_between(tc, Clock::now());
     return true;
 }
 
@@ -1631,8 +1862,10 @@ void vls_server::loop() {
                 admit.push_back(q);
             }
         }
+        const auto ta = Clock::now();
         for (SrvReq *q : admit)
             if (admit_one(q)) active.push_back(q);
+        t_admit_ms += ms_between(ta, Clock::now());
         if (active.empty()) continue;
         if (!launch_slice()) {
             thread_err = "device error in the server's step launch";
@@ -1657,6 +1890,7 @@ vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t 
         return set_err(ctx, VLS_E_DEVICE, "server stream");
     s->ctx.own_stream = true;
     s->budget = hbm_budget_bytes;
+    s->pool_cap = hbm_budget_bytes / 4;
     s->max_slots = max_slots;
     s->slice_ticks = (unsigned long long)slice_us * 100ull;    // s_memrealtime runs at 100 MHz
     s->occ = (flags & VLS_BATCH_TWO_PER_CU) ? 2 : 1;
@@ -1674,6 +1908,7 @@ vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t 
 vls_status vls_server_submit(vls_server *srv, const vls_mesh *m, const vls_params *p, uint64_t *ticket) {
     if (!srv || !m || !p || !ticket) return VLS_E_INVALID_ARG;
     if (p->struct_size != sizeof(vls_params)) return VLS_E_INVALID_ARG;
+    if (p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS)) return VLS_E_INVALID_ARG;
     auto q = std::make_unique<SrvReq>();
     q->m = const_cast<vls_mesh *>(m);
     q->p = *p;
@@ -1723,6 +1958,16 @@ vls_status vls_server_stats(const vls_server *srv, int64_t *launches, int64_t *c
         for (auto &kv : s->reqs) r += !kv.second->done;
         *running = r - (int32_t)s->queue.size();
     }
+    return VLS_OK;
+}
+
+vls_status vls_server_timing(const vls_server *srv, double *admit_ms, double *launch_ms, double *complete_ms) {
+    if (!srv) return VLS_E_INVALID_ARG;
+    vls_server *s = const_cast<vls_server *>(srv);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (admit_ms) *admit_ms = s->t_admit_ms;
+    if (launch_ms) *launch_ms = s->t_launch_ms;
+    if (complete_ms) *complete_ms = s->t_complete_ms;
     return VLS_OK;
 }
 

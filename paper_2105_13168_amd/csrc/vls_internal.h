@@ -77,6 +77,7 @@ struct Ctl {
     unsigned long long clk_fbar;   // field workgroup 1: wait for the other field workgroups
     unsigned long long clk_evp[4]; // events: merge walks, split walkers, relabel walks, the rest
     unsigned long long clk_ev0;
+    unsigned long long clk_g[4];   // global-memory topology path: candidates, closure, classification, insertion
     int32_t n_round_steps, n_global_steps;
     // batched mode: next iteration to run (a mesh may be advanced over
     // several launches, each visit bounded in time), the first iteration of
@@ -140,6 +141,66 @@ struct DParams {
     int32_t lockstep;        // 1: one grid barrier per step instead of the decoupled kernel
     int32_t dense;           // 1: the field step updates every vertex (no update list)
 };
+
+// ---------------------------------------------------------------------------
+// tunnel-loop and handle-refinement passes (vls_passes.hip): one pass per
+// workgroup at a time, each workgroup with its own slot of per-vertex state
+// ---------------------------------------------------------------------------
+struct PassSlot {
+    double *rho;             // [nv] the pass's field (one buffer: Jacobi values go through tmp)
+    double *tmp;             // [nv] new values of the update list, by list position
+    double *ta;              // [nv] arrival time of inserted vertices
+    double *prev;            // [nv] value before the step of a vertex that crossed the threshold
+    uint64_t *key;           // [nv] (step << 32) | round, KEY_OUT outside
+    int32_t *par;            // [nv] streamline parent
+    int32_t *mark;           // [nv] update-list membership (step number; 0 = never listed)
+    int32_t *cst;            // [nv] candidate de-duplication (step number)
+    int32_t *upd;            // [nv] step of the last update that crossed the threshold
+    int32_t *flag;           // [nv] PF_* bits
+    int32_t *pos;            // [nv] loop-erasure positions (-1)
+    int32_t *U[2];           // [nv] update lists (step parity)
+    int32_t *cand;           // [nv] crossers of the step
+    int32_t *pend[2];        // [nv] crossers not yet connected (step parity)
+    int32_t *touched;        // [nv] every vertex listed at least once (reset at the end)
+    int32_t *flist;          // [nv] every vertex with a flag (reset at the end)
+    int32_t *buf;            // [nv] streamline, then the closed loop
+    int32_t *side;           // [nv] the start side in loop order
+    uint32_t *cutbits;       // [nnz/32 + 1] cut half-edges, ascending-row layout
+    int32_t *cutpos;         // [nnz] set cut bits (reset at the end)
+};
+struct PassTask {
+    int32_t kind;            // 0: tunnel pass of a handle loop; 1: refinement pass of a tunnel
+    int32_t src;             // kind 0: loop index (every involved loop of every merge); kind 1: tunnel task
+};
+struct PassResult {
+    int32_t status;          // 0, VLS_E_STALLED, VLS_E_INVALID_ARG (no usable input), VLS_E_CAPACITY
+    int32_t reached;         // vertex the pass reached on the other side (-1)
+    int32_t label;           // 0 handle, 1 tunnel (offset along the normals), -1 none
+    int32_t pad;
+    int64_t steps, off, n, updates;
+    double length, offset_length;
+};
+struct PassArgs {
+    DMesh m;
+    DState s;                // the initial pass's results: keys, events, loops
+    const PassTask *tasks;
+    int ntasks;
+    int nslots;
+    int *next;               // task counter
+    const PassSlot *slots;   // [nslots]
+    PassResult *res;         // [ntasks]
+    int32_t *out;            // closed loops, appended
+    int64_t out_cap;
+    unsigned long long *out_used;
+    const PassResult *src_res;   // refinement passes: the tunnel passes' results
+    const int32_t *src_out;      //   and loops
+    double tau, a, w, e, c;
+    int64_t max_steps, stall_steps;
+    double rel_eps;          // offset of the handle/tunnel test, times the mean edge length of the loop
+};
+hipError_t launch_passes(const PassArgs &a, hipStream_t st);
+hipError_t launch_pass_slot_init(const PassSlot &s, int32_t nv, int64_t nnz, hipStream_t st);
+int max_coresident_passes();
 
 // host launchers (vls_kernels.hip)
 hipError_t launch_init(const DMesh &m, const DState &s, int64_t nnz, hipStream_t st);

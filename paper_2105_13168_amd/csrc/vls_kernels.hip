@@ -1402,6 +1402,8 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
     Ctl *ctl = s.ctl;
     const double *__restrict__ rho = (t & 1) ? s.rho1 : s.rho0;
     const int tid = threadIdx.x;
+    const unsigned long long g0 = DCLK();
+    unsigned long long g1 = g0, g2 = g0, g3 = g0;
     if (tid == 0) { sh->nL = 0; sh->nN = 0; sh->nnew = 0; sh->event = 0; sh->npend = 0; }
     __syncthreads();
     // 1. candidates: this step's crossers plus the pending ones, de-duplicated
@@ -1423,6 +1425,7 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
     const int nL = sh->nL;
     const uint64_t tk = (uint64_t)t << 32;
     int round = 0;
+    g1 = g2 = g3 = DCLK();
     if (nL > 0) {
         // 2. closure rounds: round 0 touches the inside set of step t-1,
         //    round j touches round j-1
@@ -1467,6 +1470,7 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
         }
         // rounds used: 0 .. round-1
         const int nrounds = round;
+        g2 = DCLK();
         // 3. lower-link classification of every inserted vertex
         for (int i = tid; i < nL; i += NT) {
             if (s.Lrnd[i] < 0) continue;
@@ -1520,6 +1524,7 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
             if (nlow == 0 || d > MAXDEG) atomicOr(&sh->event, 2);
         }
         __syncthreads();
+        g3 = DCLK();
         if (sh->event & 2) {
             if (tid == 0) fail(s, ST_INVARIANT, 12);
         } else if (!sh->event) {
@@ -1619,6 +1624,11 @@ __device__ __forceinline__ void phase_topo_global(const DMesh &m, const DState &
         if (s.Lrnd[i] < 0) s.pend[t & 1][atomicAdd(&sh->npend, 1)] = s.L[i];
     __syncthreads();
     if (tid == 0) {
+        const unsigned long long g4 = DCLK();
+        ctl->clk_g[0] += g1 - g0;
+        ctl->clk_g[1] += g2 - g1;
+        ctl->clk_g[2] += g3 - g2;
+        ctl->clk_g[3] += g4 - g3;
         ctl->cnt_pend[t & 1] = sh->npend;
         const int nN = sh->nN;
         ctl->n_inside += nN;
@@ -1733,49 +1743,44 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     for (int i = tid; i < HCAP; i += NT) kl->hk[i] = -1;
     if (tid == 0) { sh->nL = 0; sh->nN = 0; sh->nnew = 0; sh->event = 0; sh->npend = 0; }
     __syncthreads();
-    // 1. candidates, de-duplicated through the hash
+    // 1. candidates, de-duplicated through the hash, and closure round 0
+    //    (touches the inside set of step t-1), fused: entry i is candidate i
+    //    of the step's list (a repeat of an earlier candidate leaves a hole,
+    //    Lv = -1), handled by the thread that reads it, whose link row is
+    //    loaded together with the candidate's key.  The first entry of each
+    //    thread keeps its link (ids and pre-step keys) in registers for the
+    //    later rounds and the classification.
     const int32_t *cl = s.cand[t & 1];
     const int32_t *pl = s.pend[(t - 1) & 1];
-    for (int i = tid; i < nc + np; i += NT) {
-        const int32_t x = i < nc ? ldx<CM>(cl + i) : pl[i - nc];
-        // crossers of step t were checked against rho_t by the field phase;
-        // pending ones are re-checked here
-        if (ldg(s.key + x) != KEY_OUT || (i >= nc && !(ldx<CM>(rho + x) > p.tau))) continue;
-        uint32_t h = hslot<CAP>(x);
-        for (int g = 0; g < HCAP; ++g) {
-            const int32_t old = atomicCAS(&kl->hk[h], -1, x);
-            if (old == -1) {
-                const int slot = atomicAdd(&sh->nL, 1);
-                kl->Lv[slot] = x;
-                kl->Lr[slot] = -1;
-                kl->hv[h] = slot;
-                break;
-            }
-            if (old == x) break;
-            h = (h + 1) & (HCAP - 1);
-        }
-    }
-    __syncthreads();
-    const int nL = sh->nL;
-    k1 = DCLK();
-    if (nL == 0) {
-        if (tid == 0) ctl->clk_t[0] += k1 - k0;
-        return;
-    }
-    // 2. closure round 0: touches the inside set of step t-1
-    int n0 = 0;
-    // the first entry of each thread keeps its link (ids and pre-step keys)
-    // in registers for the classification below
+    const int nL = nc + np;
+    int n0 = 0, nhole = 0;
     int32_t cnb[GB];
     uint64_t ckn[GB];
     bool cached = false;
     for (int i = tid; i < nL; i += NT) {
-        const int32_t x = kl->Lv[i];
+        const int32_t x = i < nc ? ldx<CM>(cl + i) : pl[i - nc];
+        // crossers of step t were checked against rho_t by the field phase;
+        // pending ones are re-checked here
+        const uint64_t kx = ldg(s.key + x);
+        const double rx = i >= nc ? ldx<CM>(rho + x) : 1.0;
+        int32_t nb[GB];
         int32_t b;
         int d;
+        const bool row = load_lrow(m, x, nb, b, d);
+        kl->Lv[i] = -1;
+        kl->Lr[i] = -1;
+        if (kx != KEY_OUT || !(rx > p.tau)) { nhole++; continue; }
+        bool fresh = false;
+        uint32_t h = hslot<CAP>(x);
+        for (int g = 0; g < HCAP; ++g) {
+            const int32_t old = atomicCAS(&kl->hk[h], -1, x);
+            if (old == -1) { kl->hv[h] = i; fresh = true; break; }
+            if (old == x) break;
+            h = (h + 1) & (HCAP - 1);
+        }
+        if (!fresh) { nhole++; continue; }
         bool hit = false;
-        int32_t nb[GB];
-        if (load_lrow(m, x, nb, b, d)) {
+        if (row) {
             uint64_t kn[GB];
 #pragma unroll
             for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(s.key + nb[j]) : KEY_OUT;
@@ -1795,21 +1800,29 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
                 for (int j = 0; j < GB; ++j) hit = hit || kn[j] < tk;
             }
         }
+        kl->Lv[i] = x;
         kl->Lb[i] = b;
         kl->Lg[i] = d;
         kl->Lr[i] = hit ? 0 : -1;
         n0 += hit;
     }
+    if (nhole) atomicAdd(&sh->nL, nhole);     // sh->nL counts the holes on this path
+    k1 = DCLK();
     if (n0) atomicAdd(&sh->nN, n0);
     __syncthreads();
+    const int nreal = nL - sh->nL;
+    if (nreal == 0) {
+        if (tid == 0) ctl->clk_t[0] += k1 - k0;
+        return;
+    }
     int nrounds = sh->nN ? 1 : 0;
     // later rounds (rare): touch the previous round, found through the hash
-    if (sh->nN && sh->nN < nL) {
+    if (sh->nN && sh->nN < nreal) {
         const unsigned long long kr = DCLK();
         for (int round = 1;; ++round) {
             for (int i = tid; i < nL; i += NT) {
                 int flag = 0;
-                if (kl->Lr[i] == -1) {
+                if (kl->Lr[i] == -1 && kl->Lv[i] >= 0) {
                     if (i == tid && cached) {
 #pragma unroll
                         for (int j = 0; j < GB; ++j) {
@@ -1840,7 +1853,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
             __syncthreads();
             if (tid == 0) sh->nN += nnew;
             __syncthreads();
-            if (sh->nN == nL) break;
+            if (sh->nN == nreal) break;
         }
         if (tid == 0) {
             ctl->clk_rounds += DCLK() - kr;
@@ -2047,7 +2060,7 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
     }
     // 5. crossers not connected this step wait for the next
     for (int i = tid; i < nL; i += NT)
-        if (kl->Lr[i] < 0) s.pend[t & 1][atomicAdd(&sh->npend, 1)] = kl->Lv[i];
+        if (kl->Lr[i] < 0 && kl->Lv[i] >= 0) s.pend[t & 1][atomicAdd(&sh->npend, 1)] = kl->Lv[i];
     __syncthreads();
     if (tid == 0) {
         const unsigned long long k4 = DCLK();

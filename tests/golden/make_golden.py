@@ -96,7 +96,48 @@ def main(full: bool = True, only=None):
             json.dump(full_out, f, indent=1, sort_keys=True)
 
 
+# the batched workload (1024 uneven meshes, base seed 0): one combined
+# digest of every output per mesh
+BATCH_FIELDS = ("steps", "status", "n_events", "n_handles", "n_loops", "n_tunnels", "T", "rnd", "parent", "rho",
+                "events", "fronts", "reeb_pos", "reeb_edges", "loops", "tunnels")
+_BATCH = None
+
+
+def combined_digest(d: dict) -> str:
+    import hashlib
+    return hashlib.sha256(json.dumps([d[k] for k in BATCH_FIELDS]).encode()).hexdigest()
+
+
+def _batch_one(i):
+    import oracle
+    sys.path.insert(0, os.path.dirname(HERE))
+    from _digest import canon_oracle, digests
+    m = _BATCH[i]
+    r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed)
+    d = digests(canon_oracle(r))
+    return {"nv": int(m.nv), "seed_vertex": int(m.seed), "steps": d["steps"], "n_events": d["n_events"],
+            "n_handles": d["n_handles"], "digest": combined_digest(d)}
+
+
+def main_batch(n=1024, workers=6):
+    import multiprocessing as mp
+    import time
+    import oracle
+    global _BATCH
+    oracle.build(force=False)
+    t0 = time.time()
+    _BATCH = mg.batch_workload(n, base_seed=0)
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = pool.map(_batch_one, range(n), chunksize=4)
+    with open(os.path.join(HERE, "oracle_batch1024.json"), "w") as f:
+        json.dump({"base_seed": 0, "meshes": out}, f, indent=0)
+    print(f"batch digests: {n} meshes, {time.time() - t0:.0f} s", flush=True)
+
+
 if __name__ == "__main__":
     argv = sys.argv[1:]
+    if "--batch" in argv:
+        main_batch()
+        sys.exit(0)
     only = argv[argv.index("--full") + 1:] if "--full" in argv else None
     main(full="--no-full" not in argv, only=only)

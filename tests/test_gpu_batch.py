@@ -169,3 +169,34 @@ def test_batch_edge_events_and_final_checkpoint(oracle_mod):
         for x in M:
             x.close()
         ctx.close()
+
+
+def test_batch1024_digests_match_oracle():
+    """The bench's batch of 1024 uneven meshes (tori with V ~ logU[1e3, 2e5]
+    and chains of 2..10 tori), one batched launch: every mesh's outputs
+    equal the oracle's, by a combined digest per mesh recorded by
+    tests/golden/make_golden.py --batch from the oracle alone."""
+    import json
+    import os
+    import paper_2105_13168_amd as vls
+    from _digest import canon_gpu, digests
+    from golden.make_golden import combined_digest
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "oracle_batch1024.json")))["meshes"]
+    ms = mg.batch_workload(1024, base_seed=0)
+    assert [m.nv for m in ms] == [g["nv"] for g in gold]
+    ctx = vls.Context(0)
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    try:
+        res = vls.batch_run(ctx, M, [m.seed for m in ms])
+        bad = []
+        for i, (g, want) in enumerate(zip(res, gold)):
+            d = digests(canon_gpu(g))
+            if (d["steps"], d["n_events"], d["n_handles"]) != (want["steps"], want["n_events"], want["n_handles"]) \
+                    or combined_digest(d) != want["digest"]:
+                bad.append(i)
+        assert not bad, f"{len(bad)} meshes differ from the oracle, first {bad[:10]}"
+    finally:
+        for x in M:
+            x.close()
+        ctx.close()
