@@ -1683,16 +1683,26 @@ struct vls_server {
     void *post_buf = nullptr;
     size_t post_cap = 0;
     // host time of the scheduler's phases (ms): admissions, launches incl.
-    // their wait, completions
+    // their wait; and of the completion thread's work
     double t_admit_ms = 0.0, t_launch_ms = 0.0, t_complete_ms = 0.0;
+    // completions (post-passes, results to the host) run on their own thread
+    // and stream, beside the next slices
+    vls_context cctx;
+    std::thread cth;
+    std::deque<SrvReq *> cq;
+    std::condition_variable ccv;
+    bool cstop = false;
+    std::mutex pool_mu;
 
     ~vls_server() {
         for (void *q : {dm, ds, dp, dord, dnext, ddone, dtg, dsl}) if (q) (void)hipFree(q);
         pool.clear();
         if (post_buf) (void)hipFree(post_buf);
         if (ctx.own_stream && ctx.stream) (void)hipStreamDestroy(ctx.stream);
+        if (cctx.own_stream && cctx.stream) (void)hipStreamDestroy(cctx.stream);
     }
     std::unique_ptr<RunBuffers> take_buffers(const vls_mesh *m) {
+        std::lock_guard<std::mutex> lk(pool_mu);
         auto it = pool.find(m);
         if (it == pool.end()) return nullptr;
         while (!it->second.empty()) {
@@ -1706,6 +1716,7 @@ struct vls_server {
     }
     void give_buffers(const vls_mesh *m, std::unique_ptr<RunBuffers> rb) {
         if (!rb) return;
+        std::lock_guard<std::mutex> lk(pool_mu);
         const size_t b = rb->arena.used;
         if (pooled + b > pool_cap) return;       // freed
         pooled += b;
@@ -1716,6 +1727,7 @@ struct vls_server {
     bool admit_one(SrvReq *q);
     bool launch_slice();
     void loop();
+    void complete_loop();
 };
 
 // marks q done (status, result), releases its admission charge
@@ -1738,7 +1750,9 @@ void vls_server::finish(SrvReq *q, vls_status st, vls_result *r) {
 
 // a request whose step kernel finished: post-passes, results to the host
 void vls_server::complete(SrvReq *q) {
-    if (hipEventRecord(q->prep->e2, ctx.stream) != hipSuccess) { finish(q, VLS_E_DEVICE, nullptr); return; }
+    // the request's device work ended with the slice that finished it; the
+    // post-passes and copies go on the completion stream
+    q->prep->stream = cctx.stream;
     // post-pass scratch: the server's reusable block
     const size_t need = post_bytes(q->m);
     if (need > post_cap) {
@@ -1753,9 +1767,31 @@ void vls_server::complete(SrvReq *q) {
     q->prep->post.cap = post_cap;
     q->prep->post.used = 0;
     auto r = std::make_unique<vls_result>();
-    vls_status rs = finish_run(&ctx, *q->prep, &q->p, 0, 256, -1.0, *r);
+    vls_status rs = finish_run(&cctx, *q->prep, &q->p, 0, 256, -1.0, *r);
     if (rs != VLS_OK && !is_run_status(rs)) { finish(q, rs, nullptr); return; }
     finish(q, rs, r.release());
+}
+
+void vls_server::complete_loop() {
+    (void)hipSetDevice(cctx.device);
+    for (;;) {
+        SrvReq *q = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            ccv.wait(lk, [&] { return cstop || !cq.empty(); });
+            if (cq.empty()) break;
+            q = cq.front();
+            cq.pop_front();
+        }
+        const auto t0 = Clock::now();
+        complete(q);
+        const double ms = ms_between(t0, Clock::now());
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            t_complete_ms += ms;
+        }
+        cv.notify_one();       // budget freed: the scheduler may admit more
+    }
 }
 
 // device run state and seed initialisation of a newly admitted request
@@ -1841,8 +1877,18 @@ bool vls_server::launch_slice() {
     for (int w = 0; w < n; ++w) flag[order[w]] = hdone[w];
     for (int i = 0; i < n; ++i) (flag[i] ? fin : still).push_back(active[i]);
     active.swap(still);
-    for (SrvReq *q : fin) complete(q);
-    t_complete_ms += ms_between(tc, Clock::now());
+    for (SrvReq *q : fin) {
+        // kernel time of the request ends with this slice
+        if (hipEventRecord(q->prep->e2, st) != hipSuccess) return false;
+    }
+    if (!fin.empty()) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (SrvReq *q : fin) cq.push_back(q);
+        }
+        ccv.notify_one();
+    }
+    (void)tc;
     return true;
 }
 
@@ -1852,11 +1898,16 @@ void vls_server::loop() {
         std::vector<SrvReq *> admit;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            // a request fits when its run state fits the budget beside what is
+            // admitted (running or still completing), or when nothing is
+            cv.wait(lk, [&] {
+                return stop || !active.empty() ||
+                       (!queue.empty() && (used + queue.front()->bytes <= budget || used == 0));
+            });
             if (stop) break;
             while (!queue.empty() && (int)(active.size() + admit.size()) < max_slots) {
                 SrvReq *q = queue.front();
-                if (used + q->bytes > budget && !(active.empty() && admit.empty())) break;
+                if (used + q->bytes > budget && !(used == 0 && admit.empty())) break;
                 queue.pop_front();
                 used += q->bytes;
                 admit.push_back(q);
@@ -1889,6 +1940,10 @@ vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t 
     if (hipStreamCreateWithFlags(&s->ctx.stream, hipStreamNonBlocking) != hipSuccess)
         return set_err(ctx, VLS_E_DEVICE, "server stream");
     s->ctx.own_stream = true;
+    s->cctx.device = ctx->device;
+    if (hipStreamCreateWithFlags(&s->cctx.stream, hipStreamNonBlocking) != hipSuccess)
+        return set_err(ctx, VLS_E_DEVICE, "server completion stream");
+    s->cctx.own_stream = true;
     s->budget = hbm_budget_bytes;
     s->pool_cap = hbm_budget_bytes / 4;
     s->max_slots = max_slots;
@@ -1897,8 +1952,19 @@ vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t 
     s->cm = (flags & VLS_COHERENT_SHARING) ? 1 : 0;
     vls_server *raw = s.get();
     try {
+        s->cth = std::thread([raw] { raw->complete_loop(); });
+    } catch (...) {
+        return set_err(ctx, VLS_E_OUT_OF_MEMORY, "server thread");
+    }
+    try {
         s->th = std::thread([raw] { raw->loop(); });
     } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->cstop = true;
+        }
+        s->ccv.notify_all();
+        s->cth.join();
         return set_err(ctx, VLS_E_OUT_OF_MEMORY, "server thread");
     }
     *out = s.release();
@@ -1983,6 +2049,13 @@ vls_status vls_server_shutdown(vls_server *srv) {
     }
     srv->cv.notify_all();
     if (srv->th.joinable()) srv->th.join();
+    // requests that finished on the device are completed normally
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->cstop = true;
+    }
+    srv->ccv.notify_all();
+    if (srv->cth.joinable()) srv->cth.join();
     // the scheduler has stopped after its last launch: the requests it was
     // running and those still queued end as cancelled (their polls say so)
     (void)hipSetDevice(srv->ctx.device);
