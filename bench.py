@@ -652,12 +652,6 @@ def main():
             log(f"pretzel leg done ({time.time() - t_start:.0f}s since start)")
         else:
             skipped.append("pretzel_pass")
-    if args.passes_workload != "none":
-        if left() > 60:
-            out["passes"] = passes_leg(ctx, args.passes_workload)
-            log(f"passes leg done ({time.time() - t_start:.0f}s since start)")
-        else:
-            skipped.append("passes")
     if args.batch > 0:
         if left() > 75:
             out["batched"] = batch_leg(ctx, args.batch, args.batch_seq_sample, tune=args.tune)
@@ -672,6 +666,12 @@ def main():
             log(f"serving leg done ({time.time() - t_start:.0f}s since start)")
         else:
             skipped.append("serving")
+    if args.passes_workload != "none":
+        if left() > 60:
+            out["passes"] = passes_leg(ctx, args.passes_workload)
+            log(f"passes leg done ({time.time() - t_start:.0f}s since start)")
+        else:
+            skipped.append("passes")
     if skipped:
         out["skipped_for_time_budget"] = skipped
     if args.copy_calibration:

@@ -119,8 +119,9 @@ typedef struct vls_params {
                                   gets one workgroup per this many vertices (at least 2 to
                                   form a gang, at most 64); 0 = 65536                     */
     int32_t pass_slots;        /* tunnel-loop / refinement passes run at once (each on one
-                                  workgroup with its own per-vertex state); 0 = as many as
-                                  co-resident workgroups and a quarter of free memory allow */
+                                  workgroup with its own per-vertex state, about 100 B per
+                                  vertex); 0 = as many as co-resident workgroups and half of
+                                  the free device memory allow */
     int32_t reserved;
 } vls_params;
 

@@ -878,8 +878,8 @@ static vls_status post_passes(vls_context *ctx, RunPrep &rp, const Ctl &c, vls_r
 // Tunnel-loop passes of every handle loop and, with VLS_REFINE_PASS, the
 // refinement pass of every tunnel, after the initial pass (vls_run only).
 // As many passes run at once as there are co-resident workgroups and slots
-// of per-vertex state within a quarter of the free device memory (the
-// paper's rule: as many passes as memory allows).
+// of per-vertex state within half of the free device memory (the paper's
+// rule: as many passes as memory allows).
 static vls_status run_passes(vls_context *ctx, RunPrep &rp, const vls_params *p, const Ctl &c, vls_result &r) {
     const bool refine = (p->flags & VLS_REFINE_PASS) != 0;
     if (!(p->flags & VLS_TUNNEL_PASS) && !refine) return VLS_OK;
@@ -908,7 +908,7 @@ static vls_status run_passes(vls_context *ctx, RunPrep &rp, const vls_params *p,
         P_(q.rho, nv); P_(q.tmp, nv); P_(q.ta, nv); P_(q.prev, nv); P_(q.key, nv); P_(q.par, nv);
         P_(q.mark, nv); P_(q.cst, nv); P_(q.upd, nv); P_(q.flag, nv); P_(q.pos, nv); P_(q.U[0], nv);
         P_(q.U[1], nv); P_(q.cand, nv); P_(q.pend[0], nv); P_(q.pend[1], nv); P_(q.touched, nv);
-        P_(q.flist, nv); P_(q.buf, nv); P_(q.side, nv); P_(q.cutbits, nnz / 32 + 1); P_(q.cutpos, nnz);
+        P_(q.flist, nv); P_(q.buf, nv); P_(q.side, nv); P_(q.cutbits, nnz / 32 + 1);
 #undef P_
         return e;
     };
@@ -918,7 +918,7 @@ static vls_status run_passes(vls_context *ctx, RunPrep &rp, const vls_params *p,
     HIPCHK(ctx, hipMemGetInfo(&free_b, &total_b));
     const int maxg = max_coresident_passes();
     if (maxg <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query of the pass kernel failed");
-    int64_t ns = std::min<int64_t>({(int64_t)nt, (int64_t)maxg, (int64_t)(free_b / 4 / slot_bytes)});
+    int64_t ns = std::min<int64_t>({(int64_t)nt, (int64_t)maxg, (int64_t)(free_b / 2 / slot_bytes)});
     if (p->pass_slots > 0) ns = std::min<int64_t>(ns, p->pass_slots);
     if (ns < 1) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "no memory for one pass slot (%zu bytes)", slot_bytes);
     DevArena A;   // hipMalloc'ed, released on return

@@ -166,7 +166,6 @@ struct PassSlot {
     int32_t *buf;            // [nv] streamline, then the closed loop
     int32_t *side;           // [nv] the start side in loop order
     uint32_t *cutbits;       // [nnz/32 + 1] cut half-edges, ascending-row layout
-    int32_t *cutpos;         // [nnz] set cut bits (reset at the end)
 };
 struct PassTask {
     int32_t kind;            // 0: tunnel pass of a handle loop; 1: refinement pass of a tunnel

@@ -49,7 +49,7 @@ enum { PS_OK = 0, PS_INVALID = -1, PS_STALLED = -7, PS_CAPACITY = -14 };
 
 struct PSh {
     int task, kind, src;
-    int nU, nUn, ncand, npn, nnew, nonfixed, nflag, ncut, ntouch, nside;
+    int nU, nUn, ncand, npn, nnew, nonfixed, nflag, ntouch, nside;
     int bad;
     unsigned long long reached;
     int32_t ev_v;
@@ -83,21 +83,27 @@ __device__ __forceinline__ int set_flag(const PassSlot &S, PSh &sh, int32_t v, i
     return old;
 }
 
-__device__ __forceinline__ void set_cut_he(const PassArgs &A, const PassSlot &S, PSh &sh, int32_t a, int32_t b) {
+// sets (or clears) the cut bit of half-edge a -> b
+__device__ __forceinline__ void cut_he_bit(const PassArgs &A, const PassSlot &S, int32_t a, int32_t b, bool clear) {
     for (int64_t i = A.m.rp[a]; i < A.m.rp[a + 1]; ++i)
         if (A.m.adj[i] == b) {
             const uint32_t bit = 1u << (i & 31);
-            if (!(atomicOr(&S.cutbits[i >> 5], bit) & bit)) S.cutpos[atomicAdd(&sh.ncut, 1)] = (int32_t)i;
+            if (clear) atomicAnd(&S.cutbits[i >> 5], ~bit);
+            else atomicOr(&S.cutbits[i >> 5], bit);
             return;
         }
 }
 
-// the undirected edge {a, b} leaves the operator
-__device__ __forceinline__ void set_cut(const PassArgs &A, const PassSlot &S, PSh &sh, int32_t a, int32_t b) {
-    set_cut_he(A, S, sh, a, b);
-    set_cut_he(A, S, sh, b, a);
-    set_flag(S, sh, a, PF_CUTV);
-    set_flag(S, sh, b, PF_CUTV);
+// the undirected edge {a, b} leaves the operator (clear: returns to it;
+// the flags are reset separately)
+__device__ __forceinline__ void set_cut(const PassArgs &A, const PassSlot &S, PSh &sh, int32_t a, int32_t b,
+                                        bool clear = false) {
+    cut_he_bit(A, S, a, b, clear);
+    cut_he_bit(A, S, b, a, clear);
+    if (!clear) {
+        set_flag(S, sh, a, PF_CUTV);
+        set_flag(S, sh, b, PF_CUTV);
+    }
 }
 
 // appends y to the update list of step t once (mark = t); records the first
@@ -230,7 +236,7 @@ __global__ void __launch_bounds__(PT) k_passes(PassArgs A) {
     for (;;) {
         if (tid == 0) {
             sh.task = atomicAdd(A.next, 1);
-            sh.nflag = sh.ncut = sh.ntouch = sh.nside = 0;
+            sh.nflag = sh.ntouch = sh.nside = 0;
             sh.bad = 0;
             sh.nU = 0;
         }
@@ -515,6 +521,33 @@ __global__ void __launch_bounds__(PT) k_passes(PassArgs A) {
         }
         __syncthreads();
         // --- back to the reset state ---------------------------------------
+        // cut bits: the set-up's edges again, cleared (the flags that chose
+        // them are still set)
+        if (T.kind == 0) {
+            const int64_t *lp = A.s.lp + 8 * (int64_t)T.src;
+            const int32_t *he = A.s.lp_he + 2 * lp[3];
+            for (int64_t k = tid; k < lp[4]; k += PT) set_cut(A, S, sh, he[2 * k], he[2 * k + 1], true);
+        } else {
+            const PassResult &Q = A.src_res[T.src];
+            const int64_t n = Q.status == PS_OK ? Q.n : 0;
+            const int32_t *W = A.src_out + (Q.status == PS_OK ? Q.off : 0);
+            for (int64_t k = tid; k < (n < 3 ? 0 : n); k += PT) {
+                const int32_t w = W[k], nx = W[(k + 1) % n], pv = W[(k + n - 1) % n];
+                const int64_t b = m.rp[w];
+                const int d = (int)(m.rp[w + 1] - b);
+                int jn = -1, jp = -1;
+                for (int j = 0; j < d; ++j) {
+                    if (m.cyc[b + j] == nx) jn = j;
+                    if (m.cyc[b + j] == pv) jp = j;
+                }
+                if (jn < 0 || jp < 0 || jn == jp) continue;
+                for (int j = (jn + 1) % d; j != jp; j = (j + 1) % d) {
+                    const int32_t y = m.cyc[b + j];
+                    if (!(S.flag[y] & PF_INW)) set_cut(A, S, sh, w, y, true);
+                }
+            }
+        }
+        __syncthreads();
         for (int k = tid; k < sh.ntouch; k += PT) {
             const int32_t y = S.touched[k];
             S.rho[y] = 0.0;
@@ -525,7 +558,6 @@ __global__ void __launch_bounds__(PT) k_passes(PassArgs A) {
             S.upd[y] = 0;
         }
         for (int k = tid; k < sh.nflag; k += PT) S.flag[S.flist[k]] = 0;
-        for (int k = tid; k < sh.ncut; k += PT) S.cutbits[S.cutpos[k] >> 5] = 0u;
         if (tid == 0) A.res[task] = R;
         __syncthreads();
     }
