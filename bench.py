@@ -511,6 +511,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10000, help="oracle diffusion steps (0: whole pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--maps-out", default="",
+                    help="write the process's memory map here at interpreter exit (places the addresses of "
+                         "frames that later exit handlers print)")
     ap.add_argument("--pretzel-passes", type=int, default=3, help="timed passes of the 256^3 pretzel (0: skip)")
     ap.add_argument("--batch", type=int, default=1024, help="meshes in the batched leg (0: skip)")
     ap.add_argument("--batch-seq-sample", type=int, default=16)
@@ -527,6 +530,14 @@ def main():
     ap.add_argument("--passes-workload", default="lattice10_256",
                     help="mesh of the tunnel-loop / refinement pass leg ('none': skip)")
     args = ap.parse_args()
+    if args.maps_out:
+        import atexit
+        import shutil
+
+        def _dump_maps(path=args.maps_out):
+            with open("/proc/self/maps") as src, open(path, "w") as dst:
+                shutil.copyfileobj(src, dst)
+        atexit.register(_dump_maps)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(meshes shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
