@@ -43,7 +43,7 @@ __all__ = [
     "Mesh", "torus_grid", "marching_tets", "sdf_surface", "pretzel", "batch_workload",
     "sdf_sphere", "sdf_torus", "sdf_union_tori", "sdf_box", "jittered",
     "pick_seed", "euler_characteristic", "pretzel_sdf", "multi_torus", "uv_sphere",
-    "voxel_surface", "voxel_frame", "csaszar_torus",
+    "voxel_surface", "voxel_frame", "csaszar_torus", "octahedron", "icosphere", "relaxed",
 ]
 
 
@@ -147,6 +147,76 @@ def uv_sphere(n_lat: int = 30, n_lon: int = 40, jitter: float = 1e-3, rng_seed: 
     xyz = xyz + rng.normal(0.0, jitter, size=xyz.shape)
     seed = int(rng.integers(xyz.shape[0]))
     return Mesh(xyz, tri, seed, f"uvsphere{n_lat}x{n_lon}")
+
+
+def octahedron(radius: float = 1.0, rng_seed: int = 0) -> Mesh:
+    """Regular octahedron (8 equilateral faces, every vertex of valence 4),
+    outward oriented; the seed vertex from the PRNG."""
+    xyz = radius * np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]],
+                            dtype=np.float64)
+    tri = np.array([[0, 2, 4], [2, 1, 4], [1, 3, 4], [3, 0, 4],
+                    [2, 0, 5], [1, 2, 5], [3, 1, 5], [0, 3, 5]], dtype=np.int32)
+    seed = int(np.random.default_rng(rng_seed).integers(6))
+    return Mesh(xyz, tri, seed, "octahedron")
+
+
+def icosphere(subdiv: int = 0, radius: float = 1.0, rng_seed: int = 0) -> Mesh:
+    """Regular icosahedron (subdiv 0: 20 equilateral faces, every vertex of
+    valence 5), each further level splitting every triangle into four and
+    projecting the new vertices onto the sphere; outward oriented; the seed
+    vertex from the PRNG."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    xyz = [[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0], [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+           [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]]
+    xyz = [list(np.asarray(p, dtype=np.float64) / np.linalg.norm(p)) for p in xyz]
+    tri = [[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9], [5, 11, 4], [11, 10, 2],
+           [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9], [4, 9, 5],
+           [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]]
+    for _ in range(subdiv):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                p = np.asarray(xyz[a]) + np.asarray(xyz[b])
+                xyz.append(list(p / np.linalg.norm(p)))
+                mid[key] = len(xyz) - 1
+            return mid[key]
+        nt = []
+        for a, b, c in tri:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nt += [[a, ab, ca], [b, bc, ab], [c, ca, bc], [ab, bc, ca]]
+        tri = nt
+    xyz = radius * np.asarray(xyz, dtype=np.float64)
+    seed = int(np.random.default_rng(rng_seed).integers(xyz.shape[0]))
+    return Mesh(xyz, np.asarray(tri, dtype=np.int32), seed, f"icosphere{subdiv}")
+
+
+def relaxed(m: Mesh, f, iters: int = 10, lam: float = 0.5, h: float = 1e-6) -> Mesh:
+    """Better-shaped triangles on the same surface, for the finite-element
+    operator (marching-tetrahedra slivers make its coefficients, and so its
+    stable explicit step, extreme): ``iters`` rounds of moving every vertex
+    a fraction ``lam`` towards the mean of its neighbours, then three Newton
+    steps back onto the level 0 of the distance function ``f`` (central
+    differences of step ``h``).  Connectivity, and so the genus, is kept."""
+    import scipy.sparse as sp
+    xyz = m.xyz.copy()
+    nv = xyz.shape[0]
+    t = m.tri.astype(np.int64)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    A = sp.coo_matrix((np.ones(e.shape[0]), (e[:, 0], e[:, 1])), shape=(nv, nv)).tocsr()
+    A = ((A + A.T) > 0).astype(np.float64)
+    deg = np.asarray(A.sum(axis=1)).ravel()
+    for _ in range(iters):
+        xyz = xyz + lam * ((A @ xyz) / deg[:, None] - xyz)
+        for _ in range(3):
+            x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+            fx = f(x, y, z)
+            g = np.stack([(f(x + h, y, z) - f(x - h, y, z)) / (2 * h),
+                          (f(x, y + h, z) - f(x, y - h, z)) / (2 * h),
+                          (f(x, y, z + h) - f(x, y, z - h)) / (2 * h)], axis=1)
+            xyz = xyz - (fx / np.maximum((g * g).sum(axis=1), 1e-30))[:, None] * g
+    return Mesh(xyz, m.tri, m.seed, (m.name or "mesh") + f"_relaxed{iters}")
 
 
 # ---------------------------------------------------------------------------

@@ -48,7 +48,7 @@ class _Params(C.Structure):
                 ("seed_radius", C.c_int32), ("seed_vertex", C.c_int64),
                 ("max_steps", C.c_int64), ("stall_steps", C.c_int64),
                 ("dense", C.c_int32), ("n_ckpt", C.c_int32),
-                ("ckpt_steps", C.POINTER(C.c_int64))]
+                ("ckpt_steps", C.POINTER(C.c_int64)), ("fem", C.c_int32)]
 
 
 _lib = None
@@ -76,6 +76,8 @@ def _load():
             f = getattr(lib, name)
             f.restype = rt
             f.argtypes = [P]
+        lib.orc_fem_operator.restype = C.c_int32
+        lib.orc_fem_operator.argtypes = [C.c_int64, P, C.c_int64, P, P, P, P, P, P]
         lib.orc_ckpt.restype = C.POINTER(C.c_double)
         lib.orc_ckpt.argtypes = [P, C.c_int32]
         for name in ["orc_steplog", "orc_events", "orc_event_ids", "orc_front_birth",
@@ -164,7 +166,7 @@ class OracleResult:
 def default_params(**kw):
     p = dict(tau=0.5, mu=0.25, a=1.0 / 25.0, w=(1.0 / 25.0) / 5.0, e=1.0 / 30.0,
              dt_mode=0, seed_radius=2, seed_vertex=0, max_steps=10_000_000,
-             stall_steps=200_000, dense=0, ckpt_steps=())
+             stall_steps=200_000, dense=0, ckpt_steps=(), fem=0)
     p.update(kw)
     return p
 
@@ -178,7 +180,7 @@ def run(xyz, tri, **kw) -> OracleResult:
     cp = _Params(p["tau"], p["mu"], p["a"], p["w"], p["e"], int(p["dt_mode"]),
                  int(p["seed_radius"]), int(p["seed_vertex"]), int(p["max_steps"]),
                  int(p["stall_steps"]), int(p["dense"]), int(ck.size),
-                 ck.ctypes.data_as(C.POINTER(C.c_int64)) if ck.size else None)
+                 ck.ctypes.data_as(C.POINTER(C.c_int64)) if ck.size else None, int(p["fem"]))
     h = lib.orc_run(xyz.shape[0], xyz.ctypes.data, tri.shape[0], tri.ctypes.data, C.byref(cp))
     if not h:
         raise MemoryError("oracle allocation failed")
@@ -234,6 +236,26 @@ def run(xyz, tri, **kw) -> OracleResult:
         return r
     finally:
         lib.orc_free(h)
+
+
+def fem_operator(xyz, tri):
+    """The oracle's finite-element operator of a closed mesh: (rp, adj, g,
+    mass, sigma, dmax) with g[i] the coefficient of half-edge v -> adj[i]
+    (sigma * cot weight / lumped mass) for i in rp[v]:rp[v+1]."""
+    lib = _load()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    nv, nf = xyz.shape[0], tri.shape[0]
+    rp = np.zeros(nv + 1, dtype=np.int64)
+    adj = np.zeros(3 * nf, dtype=np.int32)
+    g = np.zeros(3 * nf, dtype=np.float64)
+    mass = np.zeros(nv, dtype=np.float64)
+    scal = np.zeros(2, dtype=np.float64)
+    rc = lib.orc_fem_operator(nv, xyz.ctypes.data, nf, tri.ctypes.data, rp.ctypes.data, adj.ctypes.data,
+                              g.ctypes.data, mass.ctypes.data, scal.ctypes.data)
+    if rc:
+        raise ValueError(f"oracle mesh check failed: {STATUS.get(rc, rc)}")
+    return rp, adj, g, mass, float(scal[0]), float(scal[1])
 
 
 # ---------------------------------------------------------------------------

@@ -18,6 +18,9 @@
  *     constant step; coefficients mu=1/4, e=1/30, a=1/25, w=a/5 from
  *     "Implementation details"), followed by the column normalisation, which
  *     for one region plus the base layer is a clip to [0,1];
+ *   - optionally (fem) the Laplacian of linear finite elements (cotangent
+ *     weights, lumped mass) in place of the uniform graph Laplacian, scaled
+ *     to equal it on equilateral meshes ("Implementation details");
  *   - thresholding into an inside set and the front = triangles with one or
  *     two inside vertices (Section "Performance Considerations");
  *   - front labelling by connected components of front triangles joined
@@ -71,6 +74,7 @@ typedef struct {
     int32_t dense;        /* 1: update every vertex every step             */
     int32_t n_ckpt;
     const int64_t *ckpt_steps;
+    int32_t fem;          /* 1: cotangent finite-element operator           */
 } orc_params;
 
 /* growable arrays */
@@ -141,6 +145,10 @@ typedef struct {
     int32_t *ckpt_done;
     int64_t gsum_h;   /* handle loops emitted                               */
     int64_t gsum_x;   /* extra cycles of degenerate events                  */
+    /* finite-element operator (fem runs only)                              */
+    double *fem_g;    /* [nnz] coefficient of half-edge v->adj[i]           */
+    double *fem_mass; /* [nv] lumped mass                                   */
+    double fem_sigma, fem_dmax;
 } orc;
 
 /* ------------------------------------------------------------------------ */
@@ -269,12 +277,83 @@ static double field_value(const orc *o, const double *rho, int64_t v, double c,
     double s = rho[o->adj[b0]];
     for (int64_t i = b0 + 1; i < b1; ++i) s = s + rho[o->adj[i]];
     double r = rho[v];
-    double lap = s - (double)(b1 - b0) * r;
+    double lap;
+    if (o->fem_g) {
+        lap = o->fem_g[b0] * (rho[o->adj[b0]] - r);
+        for (int64_t i = b0 + 1; i < b1; ++i) lap = lap + o->fem_g[i] * (rho[o->adj[i]] - r);
+    } else {
+        lap = s - (double)(b1 - b0) * r;
+    }
     double d = (a * lap + w * (2.0 * r - 1.0)) + e * sqrt(r * (1.0 - r));
     double x = r + c * d;
     if (x < 0.0) x = 0.0;
     if (x > 1.0) x = 1.0;
     return x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* cotangent finite-element operator (Section "Mathematical representation   */
+/* and data structure", "Implementation details": the Laplacian of linear    */
+/* finite elements on the surface mesh)                                      */
+/* ------------------------------------------------------------------------ */
+/* For a vertex v with counter-clockwise link c_0..c_{d-1}:
+     mass m_v  = (sum_k area(v, c_k, c_{k+1})) / 3         (lumped P1 mass)
+     k_vu      = (cot of the angle opposite vu in (v,u,a) +
+                  cot of the angle opposite vu in (v,b,u)) / 2
+                 with a, b the link successor and predecessor of u
+     (L rho)(v) = sigma / m_v * sum_u k_vu (rho_u - rho_v)
+   sigma = sqrt(3) times the mean lumped mass: on a mesh of equilateral
+   triangles with one valence every coefficient sigma k_vu / m_v is 1, so
+   the operator is the uniform graph Laplacian there and the coefficients
+   a, w, e and the step rule keep their meaning.  The explicit step uses the
+   largest absolute row sum in place of the maximum degree. */
+static double tri_area(const double *x, int64_t v, int64_t p, int64_t q) {
+    const double e0 = x[3 * p] - x[3 * v], e1 = x[3 * p + 1] - x[3 * v + 1], e2 = x[3 * p + 2] - x[3 * v + 2];
+    const double f0 = x[3 * q] - x[3 * v], f1 = x[3 * q + 1] - x[3 * v + 1], f2 = x[3 * q + 2] - x[3 * v + 2];
+    const double c0 = e1 * f2 - e2 * f1, c1 = e2 * f0 - e0 * f2, c2 = e0 * f1 - e1 * f0;
+    return 0.5 * sqrt((c0 * c0 + c1 * c1) + c2 * c2);
+}
+
+/* cotangent of the angle at apex between the edges to v and to u */
+static double cot_at(const double *x, int64_t apex, int64_t v, int64_t u) {
+    const double p0 = x[3 * v] - x[3 * apex], p1 = x[3 * v + 1] - x[3 * apex + 1], p2 = x[3 * v + 2] - x[3 * apex + 2];
+    const double q0 = x[3 * u] - x[3 * apex], q1 = x[3 * u + 1] - x[3 * apex + 1], q2 = x[3 * u + 2] - x[3 * apex + 2];
+    const double dot = (p0 * q0 + p1 * q1) + p2 * q2;
+    const double c0 = p1 * q2 - p2 * q1, c1 = p2 * q0 - p0 * q2, c2 = p0 * q1 - p1 * q0;
+    return dot / sqrt((c0 * c0 + c1 * c1) + c2 * c2);
+}
+
+static int fem_operator(orc *o) {
+    const int64_t nv = o->nv;
+    const double *x = o->xyz;
+    o->fem_g = (double *)malloc((size_t)o->nnz * sizeof(double));
+    o->fem_mass = (double *)malloc((size_t)nv * sizeof(double));
+    if (!o->fem_g || !o->fem_mass) return ORC_E_OUT_OF_MEMORY;
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t b0 = o->rp[v], d = o->rp[v + 1] - b0;
+        double S = 0.0;
+        for (int64_t k = 0; k < d; ++k) S = S + tri_area(x, v, o->cyc[b0 + k], o->cyc[b0 + (k + 1) % d]);
+        o->fem_mass[v] = S / 3.0;
+    }
+    double T = 0.0;
+    for (int64_t v = 0; v < nv; ++v) T = T + o->fem_mass[v];
+    o->fem_sigma = (sqrt(3.0) * T) / (double)nv;
+    o->fem_dmax = 0.0;
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t b0 = o->rp[v], d = o->rp[v + 1] - b0;
+        double D = 0.0;
+        for (int64_t i = b0; i < b0 + d; ++i) {
+            const int64_t u = o->adj[i];
+            int64_t k = 0;
+            while (o->cyc[b0 + k] != u) ++k;
+            const int64_t a = o->cyc[b0 + (k + 1) % d], b = o->cyc[b0 + (k + d - 1) % d];
+            const double kvu = 0.5 * (cot_at(x, a, v, u) + cot_at(x, b, v, u));
+            o->fem_g[i] = (o->fem_sigma * kvu) / o->fem_mass[v];
+            D = D + fabs(o->fem_g[i]);
+        }
+        if (D > o->fem_dmax) o->fem_dmax = D;
+    }
+    return ORC_OK;
 }
 
 /* a vertex whose value is 0 or 1 and whose neighbours all share it is a
@@ -719,7 +798,12 @@ static int cmp_pair(const void *a, const void *b) {
 static int run(orc *o, const orc_params *p) {
     int64_t nv = o->nv;
     const double a = p->a, w = p->w, e = p->e, tau = p->tau;
-    double dt = p->dt_mode == 1 ? 0.25 / (double)o->dmax : 50.0 / (double)o->dmax;
+    if (p->fem) {
+        int fr = fem_operator(o);
+        if (fr) return fr;
+    }
+    const double dmx = p->fem ? o->fem_dmax : (double)o->dmax;
+    double dt = p->dt_mode == 1 ? 0.25 / dmx : 50.0 / dmx;
     double c = dt * (p->mu / 2.0);
     o->rho = (double *)calloc((size_t)nv, sizeof(double));
     o->T = (int64_t *)malloc((size_t)nv * sizeof(int64_t));
@@ -905,5 +989,29 @@ void orc_free(void *h) {
     free(o->lp.p); free(o->lp_len.p); free(o->lp_he.p); free(o->lp_pts.p);
     free(o->tn.p); free(o->tn_v.p);
     free(o->ckpt_steps); free(o->ckpt); free(o->ckpt_done);
+    free(o->fem_g); free(o->fem_mass);
     free(o);
+}
+
+/* the finite-element operator alone: rp [nv+1] and adj [nnz] (ascending
+   neighbours), coefficients g [nnz] (sigma k_vu / m_v), masses [nv],
+   scal = {sigma, largest absolute row sum}; nnz = 3 nf on a closed mesh.
+   Returns 0 or a mesh error. */
+int32_t orc_fem_operator(int64_t nv, const double *xyz, int64_t nf, const int32_t *tri, int64_t *rp,
+                         int32_t *adj, double *g, double *mass, double *scal) {
+    orc *o = (orc *)calloc(1, sizeof(orc));
+    if (!o) return ORC_E_OUT_OF_MEMORY;
+    int32_t rc = build_mesh(o, nv, xyz, nf, tri);
+    if (!rc) rc = fem_operator(o);
+    if (!rc) {
+        memcpy(rp, o->rp, (size_t)(nv + 1) * sizeof(int64_t));
+        memcpy(adj, o->adj, (size_t)o->nnz * sizeof(int32_t));
+        memcpy(g, o->fem_g, (size_t)o->nnz * sizeof(double));
+        memcpy(mass, o->fem_mass, (size_t)nv * sizeof(double));
+        scal[0] = o->fem_sigma;
+        scal[1] = o->fem_dmax;
+    }
+    o->xyz = NULL;
+    orc_free(o);
+    return rc;
 }
