@@ -42,6 +42,10 @@ def make_workload(name):
     if name == "pretzel256":
         m = mg.pretzel(256, rng_seed=0)
         desc = "genus-3 pretzel, level-0 surface of three tori SDFs on a 256^3 grid (marching tetrahedra)"
+    elif name == "pretzel128_relaxed":
+        m = mg.relaxed(mg.pretzel(128, rng_seed=0), mg.pretzel_sdf(), 10)
+        desc = ("genus-3 pretzel on a 128^3 grid (marching tetrahedra), relaxed: ten rounds of moving each vertex "
+                "halfway to its neighbours' mean and projecting back onto the surface")
     elif name == "torus64x32":
         m = mg.torus_grid(rng_seed=0)
         desc = "64x32 torus grid, R=1, r=0.4"
@@ -166,15 +170,30 @@ def dense_leg(ctx, workload, steps, mesh=None):
     return res
 
 
-def pass_leg(ctx, workload, steps):
-    """Whole initial passes of another workload (one timed pass after a
-    warm-up), as the main line measures its own."""
+def fem_alg_bytes(updates, degsum):
+    # the update-list step's bytes plus, per updated vertex, its row offset
+    # 4 and, per neighbour, the operator coefficient 8
+    return 36 * updates + 12 * degsum
+
+
+def pass_leg(ctx, workload, steps, fem=False):
+    """Whole initial passes of another workload (timed passes after a
+    warm-up), as the main line measures its own; fem: with the
+    finite-element operator (prepared once, outside the timed passes)."""
     import ctypes as C
     import torch
     import paper_2105_13168_amd as vls
     m, desc = make_workload(workload)
     M = vls.Mesh(ctx, m.xyz, m.tri)
-    p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_DEFER_RESULTS)
+    flags = vls.VLS_DEFER_RESULTS
+    fem_info = None
+    if fem:
+        t0 = time.perf_counter()
+        sigma, rowmax = M.prepare_fem()
+        fem_info = {"prepare_s": time.perf_counter() - t0, "sigma": sigma, "row_sum_max": rowmax,
+                    "max_degree": M.dmax}
+        flags |= vls.VLS_FEM_LAPLACIAN
+    p = vls.default_params(seed_vertex=m.seed, flags=flags)
     sums, ms = [], []
     for k in range(steps + 1):
         torch.cuda.synchronize()
@@ -193,15 +212,24 @@ def pass_leg(ctx, workload, steps):
     M.close()
     last = sums[-1]
     kernel_ms = sum(x["kernel_ms"] for x in sums) / len(sums)
-    ab = alg_bytes(last["active_vertex_updates"], last["active_degree_sum"])
+    ab = (fem_alg_bytes if fem else alg_bytes)(last["active_vertex_updates"], last["active_degree_sum"])
     assert last["n_handles"] == last["euler_genus"]
-    return {"workload": desc, "nv": m.nv, "nf": m.nf, "diffusion_steps": last["steps"],
+    extra = {}
+    if fem:
+        extra["operator"] = fem_info
+        extra["field_operator"] = "cotangent finite elements (VLS_FEM_LAPLACIAN)"
+        try:
+            with open(os.path.join(ROOT, "tests", "golden", "oracle_full.json")) as f:
+                extra["oracle_whole_pass_seconds_recorded"] = json.load(f)[workload + "_fem_s0"]["oracle_seconds"]
+        except (OSError, KeyError, ValueError):
+            pass
+    return {**extra, "workload": desc, "nv": m.nv, "nf": m.nf, "diffusion_steps": last["steps"],
             "events": last["n_events"], "handles": last["n_handles"], "ms_per_pass": sum(ms) / len(ms),
             "step_kernel_ms": kernel_ms, "vertex_steps_per_s": m.nv * last["steps"] / (sum(ms) / len(ms) * 1e-3),
             "roofline": {"bound": "hbm", "achieved": ab / (kernel_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
                          "unit": "GB/s", "frac": ab / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                         "traffic": measured_traffic(kernel_ms, workload, grid=last["grid"]),
-                         "kernel": "k_steps_dec"}}
+                         "traffic": None if fem else measured_traffic(kernel_ms, workload, grid=last["grid"]),
+                         "kernel": "k_steps_dec<0, true>" if fem else "k_steps_dec"}}
 
 
 def batch_leg(ctx, n, seq_sample, tune=False):
@@ -529,6 +557,8 @@ def main():
     ap.add_argument("--dense", action="store_true", help="time the whole pass with the dense field step")
     ap.add_argument("--passes-workload", default="lattice10_256",
                     help="mesh of the tunnel-loop / refinement pass leg ('none': skip)")
+    ap.add_argument("--fem-passes", type=int, default=2,
+                    help="timed passes of the relaxed 128^3 pretzel with the finite-element operator (0: skip)")
     args = ap.parse_args()
     if args.maps_out:
         import atexit
@@ -625,7 +655,16 @@ def main():
             "active_updates_per_s": upd / (ms * 1e-3),
             "phase_ms": {"topology": last["topo_ms"], "topology_wait": last["wait0_ms"],
                          "field": last["field_ms"], "field_wait": last["wait1_ms"],
-                         "topology_global_path_steps": last["topo_global_steps"]},
+                         "topology_global_path_steps": last["topo_global_steps"],
+                         "topology_split": {k: v for k, v in zip(
+                             ("candidates", "closure", "classification", "insert_events"), last["topo_split_ms"])},
+                         "topology_event_steps_ms": last["topo_event_ms"],
+                         "topology_rounds_ms": last["topo_rounds_ms"],
+                         "event_split": {k: v for k, v in zip(
+                             ("merge_walks", "split_walkers", "relabel", "rest"), last["event_split_ms"])},
+                         "global_path_split": {k: v for k, v in zip(
+                             ("candidates", "closure", "classification", "insert_events"),
+                             last["topo_global_split_ms"])}},
             "event_steps": last["event_steps"],
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -683,6 +722,12 @@ def main():
             log(f"passes leg done ({time.time() - t_start:.0f}s since start)")
         else:
             skipped.append("passes")
+    if args.fem_passes > 0:
+        if left() > 45:
+            out["fem_pass"] = pass_leg(ctx, "pretzel128_relaxed", args.fem_passes, fem=True)
+            log(f"finite-element leg done ({time.time() - t_start:.0f}s since start)")
+        else:
+            skipped.append("fem_pass")
     if skipped:
         out["skipped_for_time_budget"] = skipped
     if args.copy_calibration:

@@ -86,6 +86,15 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
 #define VLS_REFINE_PASS 256u     /* vls_run only: also a handle-refinement pass for every tunnel of the
                                     tunnel-loop pass (Section "Handle refinement pass"): loops of
                                     kind 4; implies VLS_TUNNEL_PASS */
+#define VLS_FEM_LAPLACIAN 512u   /* vls_run and the workspace calls: the field step uses the Laplacian of
+                                    linear finite elements (Section "Mathematical representation and
+                                    data structure", "Implementation details") in place of the uniform
+                                    graph Laplacian: cotangent weights over lumped masses, scaled by
+                                    sqrt(3) x the mean lumped mass (so that on a mesh of equilateral
+                                    triangles of one valence it is the graph Laplacian), dt = 50 (or
+                                    0.25) over its largest absolute row sum; see vls_mesh_prepare_fem.
+                                    Not with VLS_DENSE_FIELD, the passes, vls_batch_run or the server
+                                    (VLS_E_INVALID_ARG) */
 #define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]) and the server (creation
                                     flags): two workgroups per CU, each with a 1024-candidate LDS
                                     topology path and one list entry per field thread; default: one
@@ -159,6 +168,37 @@ vls_status vls_mesh_create(struct vls_context *ctx, int64_t nv, const double *xy
 vls_status vls_mesh_info(const struct vls_mesh *m, int64_t *nv, int64_t *ne, int64_t *nf,
                          int32_t *dmax, int32_t *euler_genus);
 vls_status vls_mesh_destroy(struct vls_mesh *m);
+
+/*
+ * The Laplacian of linear finite elements on the mesh (Section
+ * "Mathematical representation and data structure", "Implementation
+ * details": the fields are discretised with standard linear finite elements
+ * and the mesh's Laplacian matrix is computed once), for runs with
+ * VLS_FEM_LAPLACIAN.  Computed on the device and kept with the mesh
+ * (8 bytes per half-edge) until vls_mesh_destroy; later calls return the
+ * kept values.  For vertex v with counter-clockwise link c_0..c_{d-1}:
+ *   lumped mass  m_v = (sum over k of area(v, c_k, c_{k+1})) / 3,
+ *   weight       k_vu = (cot(angle at a) + cot(angle at b)) / 2, a and b the
+ *                link successor and predecessor of u (the two vertices
+ *                facing the edge vu),
+ *   coefficient  g_vu = sigma * k_vu / m_v,  sigma = sqrt(3) * mean(m_v),
+ * and the field step's Laplacian is sum over ascending neighbours u of
+ * g_vu * (rho_u - rho_v).  *sigma and *row_sum_max (the largest sum of
+ * |g_vu| over a row; the step size is 50 / row_sum_max) may be NULL.
+ * vls_run prepares the operator by itself; the workspace calls, which
+ * allocate nothing, need it prepared first.  Errors: VLS_E_OUT_OF_MEMORY,
+ * VLS_E_DEVICE, VLS_E_INVALID_ARG for a degenerate operator (a zero or
+ * non-finite row sum, from degenerate triangles).
+ */
+vls_status vls_mesh_prepare_fem(struct vls_mesh *m, double *sigma, double *row_sum_max);
+
+/*
+ * The prepared coefficients g_vu, nnz of them, in CSR order of ascending
+ * neighbours (row v holds v's neighbours in increasing id).  cap = 0 only
+ * reports *n_out = nnz; a smaller positive cap gives VLS_E_BUFFER_TOO_SMALL;
+ * VLS_E_INVALID_ARG before vls_mesh_prepare_fem.
+ */
+vls_status vls_mesh_fem_coefficients(const struct vls_mesh *m, int64_t cap, double *g, int64_t *n_out);
 
 /*
  * The initial pass (Section "Initial Pass"), blocking.  Runs the seed

@@ -37,6 +37,7 @@ VLS_BATCH_TWO_PER_CU = 32
 VLS_DENSE_FIELD = 64
 VLS_TUNNEL_PASS = 128
 VLS_REFINE_PASS = 256
+VLS_FEM_LAPLACIAN = 512
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 
@@ -106,6 +107,8 @@ _sig = {
     "vls_mesh_create": (C.c_int32, [_P, C.c_int64, _P, C.c_int64, _P, _PP]),
     "vls_mesh_info": (C.c_int32, [_P, _I64P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vls_mesh_destroy": (C.c_int32, [_P]),
+    "vls_mesh_prepare_fem": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vls_mesh_fem_coefficients": (C.c_int32, [_P, C.c_int64, _P, _I64P]),
     "vls_run": (C.c_int32, [_P, _P, C.POINTER(vls_params), _PP]),
     "vls_workspace_size": (C.c_int32, [_P, C.POINTER(vls_params), C.POINTER(C.c_size_t)]),
     "vls_run_async": (C.c_int32, [_P, _P, C.POINTER(vls_params), _P, C.c_size_t, _P, _PP]),
@@ -220,6 +223,28 @@ class Mesh:
         if st != VLS_OK and raise_on_error and st != -7:
             raise VLSError(st, r.error)
         return r
+
+    def prepare_fem(self):
+        """The finite-element operator of the mesh (computed once on the
+        device): returns (sigma, largest absolute row sum)."""
+        sg, dm = C.c_double(), C.c_double()
+        st = vls_mesh_prepare_fem(self.h, C.byref(sg), C.byref(dm))
+        if st != VLS_OK:
+            raise VLSError(st, self.ctx.last_error())
+        return sg.value, dm.value
+
+    def fem_coefficients(self) -> np.ndarray:
+        """The operator's coefficient per half-edge, CSR order of ascending
+        neighbours."""
+        n = C.c_int64()
+        st = vls_mesh_fem_coefficients(self.h, 0, None, C.byref(n))
+        if st != VLS_OK:
+            raise VLSError(st, self.ctx.last_error())
+        g = np.empty(n.value, dtype=np.float64)
+        st = vls_mesh_fem_coefficients(self.h, n.value, g.ctypes.data, C.byref(n))
+        if st != VLS_OK:
+            raise VLSError(st, self.ctx.last_error())
+        return g
 
     def close(self):
         if getattr(self, "h", None):

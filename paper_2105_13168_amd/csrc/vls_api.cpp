@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -52,6 +53,7 @@ struct vls_mesh {
     std::vector<void *> allocs;
     RunBuffers *rb = nullptr;
     vls_result *pending = nullptr;       // run whose results still sit in rb
+    double fem_sigma = 0.0, fem_dmax = 0.0;   // finite-element operator (d.fem_g) once prepared
 };
 
 struct RunPrep;   // one run in flight (defined with the run sequence)
@@ -615,6 +617,65 @@ vls_status vls_mesh_info(const vls_mesh *m, int64_t *nv, int64_t *ne, int64_t *n
     return VLS_OK;
 }
 
+vls_status vls_mesh_prepare_fem(vls_mesh *m, double *sigma, double *row_sum_max) {
+    if (!m) return VLS_E_INVALID_ARG;
+    vls_context *ctx = m->ctx;
+    if (!m->d.fem_g) {
+        if (m->pending) (void)fetch_results(m->pending);
+        if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
+        void *g = nullptr, *tmp = nullptr;
+        const size_t gb = (size_t)m->nnz * sizeof(double) + 64;
+        const size_t mb = ((size_t)m->nv * sizeof(double) + 255) & ~(size_t)255;
+        if (hipMalloc(&g, gb) != hipSuccess) return set_err(ctx, VLS_E_OUT_OF_MEMORY, "operator coefficients");
+        if (hipMalloc(&tmp, mb + 256 + 64) != hipSuccess) {
+            (void)hipFree(g);
+            return set_err(ctx, VLS_E_OUT_OF_MEMORY, "operator scratch");
+        }
+        double *mass = (double *)tmp;
+        double *scal = (double *)((char *)tmp + mb);
+        unsigned long long *bits = (unsigned long long *)((char *)tmp + mb + 128);
+        double hs[2] = {0.0, 0.0};
+        unsigned long long hb = 0;
+        hipStream_t st = ctx->stream;
+        hipError_t e = hipMemsetAsync(bits, 0, sizeof(unsigned long long), st);
+        if (e == hipSuccess) e = launch_fem_operator(m->d, mass, scal, (double *)g, bits, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, scal, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hb, bits, sizeof hb, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) {
+            (void)hipFree(g);
+            return set_err(ctx, VLS_E_DEVICE, "finite-element operator: %s", hipGetErrorString(e));
+        }
+        std::memcpy(&hs[1], &hb, sizeof(double));
+        if (!(hs[1] > 0.0) || !std::isfinite(hs[1])) {
+            (void)hipFree(g);
+            return set_err(ctx, VLS_E_INVALID_ARG, "finite-element operator is degenerate (largest row sum %g)", hs[1]);
+        }
+        m->allocs.push_back(g);
+        m->d.fem_g = (const double *)g;
+        m->fem_sigma = hs[0];
+        m->fem_dmax = hs[1];
+    }
+    if (sigma) *sigma = m->fem_sigma;
+    if (row_sum_max) *row_sum_max = m->fem_dmax;
+    return VLS_OK;
+}
+
+vls_status vls_mesh_fem_coefficients(const vls_mesh *m, int64_t cap, double *g, int64_t *n_out) {
+    if (!m || !n_out) return VLS_E_INVALID_ARG;
+    if (!m->d.fem_g) return set_err(m->ctx, VLS_E_INVALID_ARG, "the finite-element operator is not prepared");
+    *n_out = m->nnz;
+    if (cap == 0) return VLS_OK;
+    if (cap < m->nnz || !g) return VLS_E_BUFFER_TOO_SMALL;
+    if (hipSetDevice(m->ctx->device) != hipSuccess) return set_err(m->ctx, VLS_E_DEVICE, "hipSetDevice");
+    if (hipMemcpyAsync(g, m->d.fem_g, (size_t)m->nnz * sizeof(double), hipMemcpyDeviceToHost, m->ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(m->ctx->stream) != hipSuccess)
+        return set_err(m->ctx, VLS_E_DEVICE, "coefficient copy failed");
+    return VLS_OK;
+}
+
 vls_status vls_mesh_destroy(vls_mesh *m) {
     if (!m) return VLS_E_INVALID_ARG;
     if (m->pending) (void)fetch_results(m->pending);
@@ -682,6 +743,17 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     if (p->n_ckpt < 0 || p->pass_slots < 0) return set_err(ctx, VLS_E_INVALID_ARG, "n_ckpt / pass_slots");
     if ((p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS)) && (priv || ws))
         return set_err(ctx, VLS_E_INVALID_ARG, "the tunnel-loop and refinement passes run with vls_run only");
+    const bool fem = (p->flags & VLS_FEM_LAPLACIAN) != 0;
+    if (fem) {
+        if (p->flags & (VLS_DENSE_FIELD | VLS_TUNNEL_PASS | VLS_REFINE_PASS))
+            return set_err(ctx, VLS_E_INVALID_ARG,
+                           "VLS_FEM_LAPLACIAN runs with the update-list field step of the initial pass only");
+        if (priv) return set_err(ctx, VLS_E_INVALID_ARG, "VLS_FEM_LAPLACIAN is not served");
+        if (!m->d.fem_g) {
+            if (ws) return set_err(ctx, VLS_E_INVALID_ARG, "VLS_FEM_LAPLACIAN: call vls_mesh_prepare_fem first");
+            if (vls_status fs = vls_mesh_prepare_fem(m, nullptr, nullptr)) return fs;
+        }
+    }
     rp.m = m;
     rp.seed = seed;
     rp.rec_field = (p->flags & VLS_RECORD_FIELD) && p->n_ckpt > 0 && p->ckpt_steps;
@@ -729,7 +801,8 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
         if (rp.post.cap < post_bytes(m)) return set_err(ctx, VLS_E_BUFFER_TOO_SMALL, "workspace too small for the post-passes");
     }
     DParams &dp = rp.dp;
-    const double dt = p->dt_mode == 1 ? 0.25 / (double)m->dmax : 50.0 / (double)m->dmax;
+    const double dmx = fem ? m->fem_dmax : (double)m->dmax;
+    const double dt = p->dt_mode == 1 ? 0.25 / dmx : 50.0 / dmx;
     dp.tau = p->tau;
     dp.a = p->a;
     dp.w = p->w;
@@ -743,6 +816,7 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     dp.coherent = (p->flags & VLS_COHERENT_SHARING) ? 1 : 0;
     dp.lockstep = (p->flags & VLS_LOCKSTEP) ? 1 : 0;
     dp.dense = (p->flags & VLS_DENSE_FIELD) ? 1 : 0;
+    dp.fem = fem ? 1 : 0;
     if (!ws) {
         HIPCHK(ctx, hipEventCreate(&rp.e0));
         HIPCHK(ctx, hipEventCreate(&rp.e1));
@@ -1323,9 +1397,12 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
         for (int32_t j = 0; j < i; ++j)
             if (meshes[j] == meshes[i]) return set_err(ctx, VLS_E_INVALID_ARG, "mesh %d appears twice in the batch", i);
     }
-    for (int32_t i = 0; i < n; ++i)
+    for (int32_t i = 0; i < n; ++i) {
         if (per_mesh[i].flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS))
             return set_err(ctx, VLS_E_INVALID_ARG, "the tunnel-loop and refinement passes run with vls_run only");
+        if (per_mesh[i].flags & VLS_FEM_LAPLACIAN)
+            return set_err(ctx, VLS_E_INVALID_ARG, "VLS_FEM_LAPLACIAN runs with vls_run and the workspace calls only");
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "hipSetDevice");
     hipStream_t stream = ctx->stream;
     std::vector<RunPrep> preps(n);
@@ -1974,7 +2051,7 @@ vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t 
 vls_status vls_server_submit(vls_server *srv, const vls_mesh *m, const vls_params *p, uint64_t *ticket) {
     if (!srv || !m || !p || !ticket) return VLS_E_INVALID_ARG;
     if (p->struct_size != sizeof(vls_params)) return VLS_E_INVALID_ARG;
-    if (p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS)) return VLS_E_INVALID_ARG;
+    if (p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS | VLS_FEM_LAPLACIAN)) return VLS_E_INVALID_ARG;
     auto q = std::make_unique<SrvReq>();
     q->m = const_cast<vls_mesh *>(m);
     q->p = *p;

@@ -31,6 +31,8 @@ struct DMesh {
                           //   padded with -1, first half-edge index in the last slot;
                           //   first entry -2 when the degree exceeds ELL_W - 1
     const double *xyz;    // [nv][3]
+    const double *fem_g;  // [nnz] finite-element operator coefficients, ascending-neighbour order
+                          //   (sigma * cot weight / lumped mass); null until prepared
 };
 
 constexpr int ELL_W = 16;             // width of the padded neighbour rows (64 B)
@@ -140,6 +142,7 @@ struct DParams {
     int32_t coherent;        // 1: coherent atomic shared accesses, release-only barrier
     int32_t lockstep;        // 1: one grid barrier per step instead of the decoupled kernel
     int32_t dense;           // 1: the field step updates every vertex (no update list)
+    int32_t fem;             // 1: the finite-element operator (m.fem_g) in place of the graph Laplacian
 };
 
 // ---------------------------------------------------------------------------
@@ -204,6 +207,11 @@ int max_coresident_passes();
 // host launchers (vls_kernels.hip)
 hipError_t launch_init(const DMesh &m, const DState &s, int64_t nnz, hipStream_t st);
 hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
+// the finite-element operator of a mesh: lumped masses (scratch [nv]),
+// scal = {sigma, largest absolute row sum} (scratch [2]), coefficients g
+// [nnz]; dmax_bits [1] zeroed by the caller
+hipError_t launch_fem_operator(const DMesh &m, double *mass, double *scal, double *g,
+                               unsigned long long *dmax_bits, hipStream_t st);
 hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int grid, int block,
                         hipStream_t st);
 int max_coresident_blocks(int block, size_t lds_bytes);

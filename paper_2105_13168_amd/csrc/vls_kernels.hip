@@ -355,7 +355,12 @@ hipError_t launch_seed(const DMesh &m, const DState &s, const DParams &p, hipStr
 // values, marks, stamps) -> (stores, claim exchanges) -> (one list and one
 // candidate reservation per wave) -> list stores.  Each thread runs FK
 // entries through every stage together so that their round trips overlap.
-template <int CM, int FK = 2>
+//
+// FE: the finite-element operator, sum_j g_j (rho_j - rho_v) over the
+// ascending neighbours with the coefficients of half-edges rp[v] + j, in
+// place of sum_j rho_j - deg rho_v; the fixed-point test is unchanged (a
+// value 0 or 1 with every neighbour equal has a zero sum either way).
+template <int CM, int FK = 2, bool FE = false>
 __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                             int worker, int nworkers) {
     Ctl *ctl = s.ctl;
@@ -389,8 +394,10 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
             const int i = base + k * NT + threadIdx.x;
             v[k] = i < end ? ldx<CM>(list + i) : -1;
         }
-        // padded neighbour row, own value, own mark, own key
+        // padded neighbour row, own value, own mark, own key (and the row
+        // offset of the operator's coefficients)
         int32_t mv[FK];
+        int32_t rb[FK];
 #pragma unroll
         for (int k = 0; k < FK; ++k) {
             keep[k] = false; cand[k] = false; big[k] = false; cmask[k] = 0; d[k] = 0;
@@ -404,10 +411,11 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
                 r[k] = ldx<CM>(rin + v[k]);
                 mv[k] = ldx<CM>(mk_cur + v[k]);
                 kv[k] = ldx<CM>(s.key + v[k]);
+                rb[k] = FE ? ldg(m.rp + v[k]) : 0;
             } else {
 #pragma unroll
                 for (int j = 0; j < GB; ++j) nb[k][j] = 0;
-                r[k] = 0.0; mv[k] = 0; kv[k] = 0;
+                r[k] = 0.0; mv[k] = 0; kv[k] = 0; rb[k] = 0;
             }
         }
         // neighbour values, marks and stamps; sum, fixed-point test, marks,
@@ -419,6 +427,7 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
         }
         double xs[FK][GB];
         int32_t mu[FK][GB], st[FK][GB];
+        double gw[FE ? FK : 1][FE ? GB : 1];
 #pragma unroll
         for (int k = 0; k < FK; ++k) {
             if (keep[k] && !big[k]) {
@@ -435,6 +444,10 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
                 for (int j = 0; j < GB; ++j) mu[k][j] = ldx<CM>(mk_cur + g[j]);
 #pragma unroll
                 for (int j = 0; j < GB; ++j) st[k][j] = *(const GLOBAL_AS int32_t *)(s.stamp + g[j]);
+                if constexpr (FE) {
+#pragma unroll
+                    for (int j = 0; j < GB; ++j) gw[k][j] = nb[k][j] != v[k] ? ldg(m.fem_g + rb[k] + j) : 0.0;
+                }
             }
         }
 #pragma unroll
@@ -450,12 +463,14 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
                 dk = 0;
 #pragma unroll
                 for (int j = 0; j < GB; ++j) dk += nb[k][j] != vk;
-                sum = xs[k][0];
+                if constexpr (FE) sum = gw[k][0] * (xs[k][0] - rk);
+                else sum = xs[k][0];
                 quiet = quiet && xs[k][0] == rk;
 #pragma unroll
                 for (int j = 1; j < GB; ++j)
                     if (j < dk) {
-                        sum = sum + xs[k][j];
+                        if constexpr (FE) sum = sum + gw[k][j] * (xs[k][j] - rk);
+                        else sum = sum + xs[k][j];
                         quiet = quiet && xs[k][j] == rk;
                     }
                 if (!quiet) {
@@ -473,11 +488,14 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
                 // degree above the row width: row offsets and the ascending list
                 const int32_t b = ldg(m.rp + vk), e = ldg(m.rp + vk + 1);
                 dk = e - b;
-                sum = ldx<CM>(rin + m.adj[b]);
-                quiet = quiet && sum == rk;
+                const double x0 = ldx<CM>(rin + m.adj[b]);
+                if constexpr (FE) sum = ldg(m.fem_g + b) * (x0 - rk);
+                else sum = x0;
+                quiet = quiet && x0 == rk;
                 for (int32_t j = b + 1; j < e; ++j) {
                     const double xn = ldx<CM>(rin + m.adj[j]);
-                    sum = sum + xn;
+                    if constexpr (FE) sum = sum + ldg(m.fem_g + j) * (xn - rk);
+                    else sum = sum + xn;
                     quiet = quiet && xn == rk;
                 }
                 if (!quiet) {
@@ -493,7 +511,7 @@ __device__ __forceinline__ void phase_field(const DMesh &m, const DState &s, con
                 }
             }
             d[k] = dk;
-            const double lap = sum - (double)dk * rk;
+            const double lap = FE ? sum : sum - (double)dk * rk;
             const double dd = (p.a * lap + p.w * (2.0 * rk - 1.0)) + p.e * sqrt(rk * (1.0 - rk));
             double x = rk + p.c * dd;
             if (x < 0.0) x = 0.0;
@@ -2105,7 +2123,7 @@ __device__ __forceinline__ void phase_topo(const DMesh &m, const DState &s, cons
 // ---------------------------------------------------------------------------
 // the persistent step kernel
 // ---------------------------------------------------------------------------
-template <int CM>
+template <int CM, bool FE = false>
 __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
     extern __shared__ __align__(16) unsigned char lds[];
     const unsigned G = gridDim.x;
@@ -2131,11 +2149,13 @@ __global__ void __launch_bounds__(NT) k_steps(DMesh m, DState s, DParams p) {
                 ctl->stop[j & 1] = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (G == 1) {
                 __syncthreads();
-                if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, 0, 1, (LDS_AS int32_t *)lsort);
+                if (FE) phase_field<CM, 1, true>(m, s, p, j + 1, 0, 1);
+                else if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, 0, 1, (LDS_AS int32_t *)lsort);
                 else phase_field<CM>(m, s, p, j + 1, 0, 1);
             }
         } else {
-            if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1, (LDS_AS int32_t *)lsort);
+            if (FE) phase_field<CM, 1, true>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
+            else if (p.dense) phase_field_dense<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1, (LDS_AS int32_t *)lsort);
             else phase_field<CM>(m, s, p, j + 1, blockIdx.x - 1, G - 1);
         }
         // field snapshots of step j (its buffer is not written in this iteration)
@@ -2217,7 +2237,7 @@ template <int CM> __device__ __forceinline__ void hand_off_release() {
 // of s_memrealtime; the field then completes exactly one more step, so the
 // exit state is again "iterations below t+1 complete".  Rank 0 returns the
 // next iteration.  Every wait is bounded (an overrun records an error).
-template <int CM, int CAP, int FK>
+template <int CM, int CAP, int FK, bool FE = false>
 __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s, const DParams &p, int rank, int G,
                                                 int64_t j0, unsigned long long budget, KSh *ksh, KL<CAP> *kl,
                                                 uint64_t *lsort, int &go) {
@@ -2287,7 +2307,8 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
         __syncthreads();
         const unsigned long long c1 = __builtin_amdgcn_s_memrealtime();
         if (!go) break;
-        if (p.dense) phase_field_dense<CM>(m, s, p, t, worker, (int)W, (LDS_AS int32_t *)lsort);
+        if (FE) phase_field<CM, FK, true>(m, s, p, t, worker, (int)W);
+        else if (p.dense) phase_field_dense<CM>(m, s, p, t, worker, (int)W, (LDS_AS int32_t *)lsort);
         else phase_field<CM, FK>(m, s, p, t, worker, (int)W);
         // field snapshot of step t-1 (its buffer is not written by step t)
         for (int q = 0; q < s.n_ckpt; ++q) {
@@ -2314,7 +2335,7 @@ __device__ __forceinline__ int64_t gang_advance(const DMesh &m, const DState &s,
 }
 
 // the decoupled step kernel of one mesh: the whole grid is one gang
-template <int CM>
+template <int CM, bool FE = false>
 __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int go;
@@ -2322,7 +2343,8 @@ __global__ void __launch_bounds__(NT) k_steps_dec(DMesh m, DState s, DParams p) 
     uint64_t *lsort = (uint64_t *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15));
     KL<LCAP> *kl = (KL<LCAP> *)(lds + ((sizeof(KSh) + 15) & ~(size_t)15) + LCAP * sizeof(uint64_t));
     if (__hip_atomic_load(&s.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    (void)gang_advance<CM, LCAP, 2>(m, s, p, (int)blockIdx.x, (int)gridDim.x, 0, ~0ull, ksh, kl, lsort, go);
+    (void)gang_advance<CM, LCAP, FE ? 1 : 2, FE>(m, s, p, (int)blockIdx.x, (int)gridDim.x, 0, ~0ull, ksh, kl, lsort,
+                                                  go);
 }
 
 // ---------------------------------------------------------------------------
@@ -2490,6 +2512,87 @@ int max_coresident_batch(size_t lds_bytes, int occ) {
     return per_cu * cus;
 }
 
+// ---------------------------------------------------------------------------
+// the finite-element operator of a mesh (Section "Mathematical representation
+// and data structure", "Implementation details": linear finite elements):
+// lumped masses m_v = (sum of the areas of v's triangles, counter-clockwise
+// from the smallest neighbour) / 3; cotangent weights k_vu = (cot at the
+// link successor a of u + cot at its predecessor b) / 2, the angles facing
+// the edge vu; sigma = sqrt(3) * (sum of the masses in id order) / nv, so
+// that on equilateral meshes of one valence every coefficient is 1;
+// coefficient g = (sigma * k_vu) / m_v per half-edge in ascending-neighbour
+// order; the explicit step takes the largest absolute row sum.  Every
+// expression is evaluated in the order written, without contraction, and
+// every sum runs in the order stated, so the coefficients are the same bits
+// wherever they are computed that way.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fem_tri_area(const double *x, int64_t v, int64_t p, int64_t q) {
+    const double e0 = x[3 * p] - x[3 * v], e1 = x[3 * p + 1] - x[3 * v + 1], e2 = x[3 * p + 2] - x[3 * v + 2];
+    const double f0 = x[3 * q] - x[3 * v], f1 = x[3 * q + 1] - x[3 * v + 1], f2 = x[3 * q + 2] - x[3 * v + 2];
+    const double c0 = e1 * f2 - e2 * f1, c1 = e2 * f0 - e0 * f2, c2 = e0 * f1 - e1 * f0;
+    return 0.5 * sqrt((c0 * c0 + c1 * c1) + c2 * c2);
+}
+
+// cotangent of the angle at `apex` between its edges to v and to u
+__device__ __forceinline__ double fem_cot(const double *x, int64_t apex, int64_t v, int64_t u) {
+    const double p0 = x[3 * v] - x[3 * apex], p1 = x[3 * v + 1] - x[3 * apex + 1], p2 = x[3 * v + 2] - x[3 * apex + 2];
+    const double q0 = x[3 * u] - x[3 * apex], q1 = x[3 * u + 1] - x[3 * apex + 1], q2 = x[3 * u + 2] - x[3 * apex + 2];
+    const double dot = (p0 * q0 + p1 * q1) + p2 * q2;
+    const double c0 = p1 * q2 - p2 * q1, c1 = p2 * q0 - p0 * q2, c2 = p0 * q1 - p1 * q0;
+    return dot / sqrt((c0 * c0 + c1 * c1) + c2 * c2);
+}
+
+__global__ void k_fem_mass(DMesh m, double *mass) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= m.nv) return;
+    const int32_t b0 = m.rp[v], d = m.rp[v + 1] - b0;
+    double S = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        const int32_t k1 = k + 1 < d ? k + 1 : 0;
+        S = S + fem_tri_area(m.xyz, v, m.cyc[b0 + k], m.cyc[b0 + k1]);
+    }
+    mass[v] = S / 3.0;
+}
+
+// one lane: the masses summed in id order (the order fixes the bits)
+__global__ void k_fem_sigma(const double *mass, int64_t nv, double *scal) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double T = 0.0;
+    for (int64_t v = 0; v < nv; ++v) T = T + mass[v];
+    scal[0] = (sqrt(3.0) * T) / (double)nv;
+}
+
+__global__ void k_fem_coef(DMesh m, const double *mass, const double *scal, double *g,
+                           unsigned long long *dmax_bits) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= m.nv) return;
+    const double sigma = scal[0];
+    const int32_t b0 = m.rp[v], d = m.rp[v + 1] - b0;
+    double D = 0.0;
+    for (int32_t i = b0; i < b0 + d; ++i) {
+        const int32_t u = m.adj[i];
+        int32_t k = 0;
+        while (k < d - 1 && m.cyc[b0 + k] != u) ++k;
+        const int32_t a = m.cyc[b0 + (k + 1 < d ? k + 1 : 0)], b = m.cyc[b0 + (k > 0 ? k - 1 : d - 1)];
+        const double kvu = 0.5 * (fem_cot(m.xyz, a, v, u) + fem_cot(m.xyz, b, v, u));
+        const double gi = (sigma * kvu) / mass[v];
+        g[i] = gi;
+        D = D + fabs(gi);
+    }
+    // non-negative doubles order as their bit patterns
+    atomicMax(dmax_bits, (unsigned long long)__double_as_longlong(D));
+}
+
+hipError_t launch_fem_operator(const DMesh &m, double *mass, double *scal, double *g,
+                               unsigned long long *dmax_bits, hipStream_t st) {
+    const unsigned blocks = (unsigned)((m.nv + NT - 1) / NT);
+    hipLaunchKernelGGL(k_fem_mass, dim3(blocks), dim3(NT), 0, st, m, mass);
+    hipLaunchKernelGGL(k_fem_sigma, dim3(1), dim3(64), 0, st, (const double *)mass, (int64_t)m.nv, scal);
+    hipLaunchKernelGGL(k_fem_coef, dim3(blocks), dim3(NT), 0, st, m, (const double *)mass, (const double *)scal, g,
+                       dmax_bits);
+    return hipGetLastError();
+}
+
 // dynamic LDS of the solo step kernels: topology tables of LCAP candidates
 size_t step_lds_bytes(int block, int dmax) {
     (void)block;
@@ -2506,8 +2609,10 @@ size_t batch_lds_bytes(int occ) {
 
 int max_coresident_blocks(int block, size_t lds_bytes) {
     // the smallest residency over every variant the launcher may pick
-    const void *fns[4] = {(const void *)k_steps<0>, (const void *)k_steps<1>, (const void *)k_steps_dec<0>,
-                          (const void *)k_steps_dec<1>};
+    const void *fns[8] = {(const void *)k_steps<0>, (const void *)k_steps<1>, (const void *)k_steps_dec<0>,
+                          (const void *)k_steps_dec<1>, (const void *)k_steps<0, true>,
+                          (const void *)k_steps<1, true>, (const void *)k_steps_dec<0, true>,
+                          (const void *)k_steps_dec<1, true>};
     int per_cu = 1 << 30;
     for (const void *f : fns) {
         int n = 0;
@@ -2529,8 +2634,14 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
     DParams pp = p;
     void *args[] = {&mm, &ss, &pp};
     const void *fn;
-    if (p.lockstep || grid < 2) fn = p.coherent ? (const void *)k_steps<1> : (const void *)k_steps<0>;
-    else fn = p.coherent ? (const void *)k_steps_dec<1> : (const void *)k_steps_dec<0>;
+    if (p.fem) {
+        if (p.lockstep || grid < 2) fn = p.coherent ? (const void *)k_steps<1, true> : (const void *)k_steps<0, true>;
+        else fn = p.coherent ? (const void *)k_steps_dec<1, true> : (const void *)k_steps_dec<0, true>;
+    } else if (p.lockstep || grid < 2) {
+        fn = p.coherent ? (const void *)k_steps<1> : (const void *)k_steps<0>;
+    } else {
+        fn = p.coherent ? (const void *)k_steps_dec<1> : (const void *)k_steps_dec<0>;
+    }
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, st);
 }
 

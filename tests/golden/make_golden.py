@@ -51,7 +51,16 @@ FULL_CASES = {
     "lattice10_512_s0": lambda: mg.lattice(10, 512, rng_seed=0),
     # the full-size lattice (1024^3 grid, about 95M vertices)
     "lattice10_1024_s0": lambda: mg.lattice(10, 1024, rng_seed=0),
+    # the finite-element operator variant on a relaxed 128^3 pretzel
+    "pretzel128_relaxed_fem_s0": (lambda: mg.relaxed(mg.pretzel(128, rng_seed=0), mg.pretzel_sdf(), 10),
+                                  {"fem": 1}),
 }
+
+
+def xyz_digest(xyz) -> str:
+    import hashlib
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(xyz, dtype=np.float64).tobytes()).hexdigest()
 
 
 def main(full: bool = True, only=None):
@@ -73,15 +82,19 @@ def main(full: bool = True, only=None):
     from _digest import canon_oracle, digests
     path = os.path.join(HERE, "oracle_full.json")
     full_out = json.load(open(path)) if (only and os.path.exists(path)) else {}
-    for name, make in FULL_CASES.items():
+    for name, case in FULL_CASES.items():
         if only and name not in only:
             continue
+        make, kw = case if isinstance(case, tuple) else (case, {})
         t0 = time.time()
         m = make()
         t1 = time.time()
-        r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed)
+        r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed, **kw)
         t2 = time.time()
         d = digests(canon_oracle(r))
+        if kw:
+            d["run_kwargs"] = kw
+            d["xyz_sha256"] = xyz_digest(m.xyz)
         d["nv"] = int(m.nv)
         d["nf"] = int(m.nf)
         d["seed_vertex"] = int(m.seed)

@@ -78,3 +78,23 @@ def test_lattice10_digests_match_oracle(grid):
     assert s["n_handles"] == g_expect and s["n_tunnels"] == g_expect
     assert len(g.reeb_nodes) == s["n_events"] + 1
     _check(d, gold)
+
+
+def test_pretzel128_relaxed_fem_digests_match_oracle():
+    """The finite-element operator variant at the largest size the oracle
+    finishes in minutes: the relaxed 128^3 pretzel (the explicit step of the
+    cotangent operator is tens of times shorter than the graph Laplacian's,
+    so the pass takes that many more steps)."""
+    import paper_2105_13168_amd as vls
+    name = "pretzel128_relaxed_fem_s0"
+    if name not in GOLD:
+        pytest.skip(f"no oracle digest recorded for {name} (tests/golden/make_golden.py --full {name})")
+    gold = GOLD[name]
+    m = mg.relaxed(mg.pretzel(128, rng_seed=0), mg.pretzel_sdf(), 10)
+    from golden.make_golden import xyz_digest
+    assert xyz_digest(m.xyz) == gold["xyz_sha256"], "relaxed mesh differs from the one the digests were taken on"
+    assert m.nv == gold["nv"] and m.seed == gold["seed_vertex"]
+    g, d = _run(m, vls.VLS_FEM_LAPLACIAN)
+    s = g.summary
+    assert s["run_status"] == 0 and s["n_handles"] == 3 and s["n_tunnels"] == 3
+    _check(d, gold)
