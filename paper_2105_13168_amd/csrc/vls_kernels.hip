@@ -2769,20 +2769,44 @@ __global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const i
             arr = (uint32_t *)(buf + o);
         }
         block_bitonic_t<uint32_t>(arr, np);
-        if (threadIdx.x == 0) {
+        // wave 0 sums the distinct ids' positions in ascending id order: each
+        // lane gathers one entry of a 64-entry chunk (64 loads in flight),
+        // then every lane adds the chunk's values in lane order from
+        // shuffles, so the sum's order, and its bits, are those of one lane
+        // walking the sorted list
+        if (threadIdx.x < WAVE) {
+            const int lane = (int)threadIdx.x;
             double sx = 0.0, sy = 0.0, sz = 0.0;
             long long c = 0;
-            for (int64_t i = 0; i < n; ++i) {
-                if (i > 0 && arr[i] == arr[i - 1]) continue;
-                const double *x = m.xyz + 3 * (int64_t)arr[i];
-                sx = sx + x[0];
-                sy = sy + x[1];
-                sz = sz + x[2];
-                c++;
+            for (int64_t c0 = 0; c0 < n; c0 += WAVE) {
+                const int64_t i = c0 + lane;
+                bool first = false;
+                double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+                if (i < n) {
+                    first = i == 0 || arr[i] != arr[i - 1];
+                    if (first) {
+                        const double *x = m.xyz + 3 * (int64_t)arr[i];
+                        x0 = x[0];
+                        x1 = x[1];
+                        x2 = x[2];
+                    }
+                }
+                const unsigned long long fm = __ballot(first);
+                for (int l = 0; l < WAVE; ++l) {
+                    const double y0 = __shfl(x0, l), y1 = __shfl(x1, l), y2 = __shfl(x2, l);
+                    if ((fm >> l) & 1ull) {
+                        sx = sx + y0;
+                        sy = sy + y1;
+                        sz = sz + y2;
+                        c++;
+                    }
+                }
             }
-            pos[3 * ev] = sx / (double)c;
-            pos[3 * ev + 1] = sy / (double)c;
-            pos[3 * ev + 2] = sz / (double)c;
+            if (lane == 0) {
+                pos[3 * ev] = sx / (double)c;
+                pos[3 * ev + 1] = sy / (double)c;
+                pos[3 * ev + 2] = sz / (double)c;
+            }
         }
         __syncthreads();
     }
