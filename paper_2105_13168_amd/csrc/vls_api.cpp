@@ -712,6 +712,11 @@ struct RunPrep {
     std::vector<int64_t> ckpt;  // vls_run_async: checkpoint list kept for the wait
     int grid = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    // post-pass outputs computed for many runs at once (vls_batch_run)
+    bool post_given = false;
+    std::vector<double> g_node_pos, g_tn_len;
+    std::vector<int32_t> g_tn, g_tn_v;
+    std::vector<int64_t> g_tn_off;
     ~RunPrep() {
         for (void *q : tmp_allocs) (void)hipFree(q);
         post.release();
@@ -949,6 +954,130 @@ static vls_status post_passes(vls_context *ctx, RunPrep &rp, const Ctl &c, vls_r
     return VLS_OK;
 }
 
+// Post-passes of a whole batch: the events (and tunnels) of every mesh are
+// listed together and each pass is one launch over a chunk of that list, so
+// the meshes' short dependent walks run side by side instead of mesh after
+// mesh with a synchronisation between each.  The outputs are those of
+// post_passes (the same kernels' bodies, one entry per block or thread),
+// handed to finish_run through the RunPreps.  dm / ds: the batch's device
+// arrays of meshes and run states; cs: each run's control block.
+constexpr int kMultiEvents = 4096;
+constexpr int kMultiTunnels = 65536;
+static vls_status batch_post_passes(vls_context *ctx, const vls_mesh *const *meshes, std::vector<RunPrep> &preps,
+                                    const std::vector<Ctl> &cs, const DMesh *dm, const DState *ds,
+                                    hipStream_t stream) {
+    const int n = (int)preps.size();
+    std::vector<int32_t> evm, eve, tnm, tnt;
+    size_t fill_cap = (size_t)1 << 22, path_cap = (size_t)1 << 22;
+    for (int i = 0; i < n; ++i) {
+        RunPrep &rp = preps[i];
+        const int nev = cs[i].n_events, ntn = cs[i].n_tunnels;
+        rp.g_node_pos.assign((size_t)nev * 3, 0.0);
+        rp.g_tn.resize((size_t)ntn * 4);
+        rp.g_tn_off.assign(ntn + 1, 0);
+        rp.g_tn_len.assign(ntn, 0.0);
+        rp.g_tn_v.clear();
+        for (int e = 0; e < nev; ++e) { evm.push_back(i); eve.push_back(e); }
+        for (int e = 0; e < ntn; ++e) { tnm.push_back(i); tnt.push_back(e); }
+        fill_cap = std::max(fill_cap, post_fill_entries(meshes[i]));
+        path_cap = std::max(path_cap, (size_t)(2 * meshes[i]->nv + 2));
+        if (ntn)
+            HIPCHK(ctx, hipMemcpyAsync(rp.g_tn.data(), rp.s.tn, (size_t)ntn * 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                       stream));
+    }
+    const int E = (int)evm.size(), T = (int)tnm.size();
+    DevArena A;
+    const int C = kMultiEvents;
+    int32_t *devm = nullptr, *deve = nullptr, *dtnm = nullptr, *dtnt = nullptr, *dck = nullptr, *dbuf = nullptr,
+            *dpath = nullptr;
+    int64_t *dcnt = nullptr, *doff = nullptr, *dmeta = nullptr, *dtcnt = nullptr, *dtoff = nullptr;
+    double *dpos = nullptr, *dlen = nullptr;
+    struct Rel { DevArena *a; ~Rel() { a->release(); } } rel{&A};
+    if (A.get(&devm, E) || A.get(&deve, E) || A.get(&dtnm, T) || A.get(&dtnt, T) || A.get(&dcnt, C + 1) ||
+        A.get(&doff, C + 1) || A.get(&dck, (size_t)C * 16 * 64) || A.get(&dmeta, (size_t)C * 16 * 4) ||
+        A.get(&dpos, (size_t)C * 3) || A.get(&dbuf, fill_cap + 16) || A.get(&dtcnt, kMultiTunnels + 1) ||
+        A.get(&dtoff, kMultiTunnels + 1) || A.get(&dlen, kMultiTunnels) || A.get(&dpath, path_cap + 16))
+        return set_err(ctx, VLS_E_OUT_OF_MEMORY, "batch post-pass buffers");
+    if (E) {
+        HIPCHK(ctx, hipMemcpyAsync(devm, evm.data(), (size_t)E * 4, hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, hipMemcpyAsync(deve, eve.data(), (size_t)E * 4, hipMemcpyHostToDevice, stream));
+    }
+    if (T) {
+        HIPCHK(ctx, hipMemcpyAsync(dtnm, tnm.data(), (size_t)T * 4, hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, hipMemcpyAsync(dtnt, tnt.data(), (size_t)T * 4, hipMemcpyHostToDevice, stream));
+    }
+    std::vector<int64_t> cnt(C + 1), np(C), off;
+    std::vector<double> pos((size_t)C * 3);
+    for (int g0 = 0; g0 < E; g0 += C) {
+        const int nc = std::min(C, E - g0);
+        HIPCHK(ctx, launch_reeb_count_multi(dm, ds, devm + g0, deve + g0, nc, dcnt, dck, dmeta, stream));
+        HIPCHK(ctx, hipMemcpyAsync(cnt.data(), dcnt, nc * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        for (int i = 0; i < nc; ++i) {
+            int64_t q = 1;
+            while (q < cnt[i]) q <<= 1;
+            np[i] = q;
+        }
+        for (int a = 0; a < nc;) {
+            int b = a;
+            int64_t used = 0;
+            while (b < nc && used + np[b] <= (int64_t)fill_cap) used += np[b++];
+            if (b == a) return set_err(ctx, VLS_E_CAPACITY, "post-pass scratch too small for one event's front triangles");
+            off.assign(b - a + 1, 0);
+            for (int i = a; i < b; ++i) off[i - a + 1] = off[i - a] + np[i];
+            HIPCHK(ctx, hipMemcpyAsync(doff, off.data(), (b - a + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+            HIPCHK(ctx, launch_reeb_fill_multi(dm, ds, devm, deve, g0 + a, b - a, doff, dcnt + a,
+                                               dck + (size_t)a * 16 * 64, dmeta + (size_t)a * 16 * 4, dbuf, stream));
+            HIPCHK(ctx, launch_reeb_mean_multi(dm, devm, g0 + a, b - a, doff, dcnt + a, dbuf, dpos + 3 * (size_t)a,
+                                               stream));
+            // the offsets are re-uploaded by the next sub-chunk: wait for this one
+            HIPCHK(ctx, hipStreamSynchronize(stream));
+            a = b;
+        }
+        HIPCHK(ctx, hipMemcpyAsync(pos.data(), dpos, (size_t)nc * 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        for (int i = 0; i < nc; ++i)
+            std::memcpy(preps[evm[g0 + i]].g_node_pos.data() + 3 * (size_t)eve[g0 + i], pos.data() + 3 * (size_t)i,
+                        3 * sizeof(double));
+    }
+    std::vector<int64_t> tc(kMultiTunnels + 1), toff;
+    std::vector<int32_t> path;
+    std::vector<double> len(kMultiTunnels);
+    for (int g0 = 0; g0 < T; g0 += kMultiTunnels) {
+        const int nt = std::min(kMultiTunnels, T - g0);
+        HIPCHK(ctx, launch_tunnel_count_multi(ds, dtnm + g0, dtnt + g0, nt, dtcnt, stream));
+        HIPCHK(ctx, hipMemcpyAsync(tc.data(), dtcnt, nt * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        for (int a = 0; a < nt;) {
+            int b = a;
+            int64_t used = 0;
+            while (b < nt && used + tc[b] <= (int64_t)path_cap) used += tc[b++];
+            if (b == a) return set_err(ctx, VLS_E_CAPACITY, "post-pass scratch too small for one tunnel path");
+            toff.assign(b - a + 1, 0);
+            for (int i = a; i < b; ++i) toff[i - a + 1] = toff[i - a] + tc[i];
+            HIPCHK(ctx, hipMemcpyAsync(dtoff, toff.data(), (b - a + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+            HIPCHK(ctx, launch_tunnel_fill_multi(dm, ds, dtnm, dtnt, g0 + a, b - a, dtoff, dpath, dlen + a, stream));
+            path.resize((size_t)toff[b - a]);
+            HIPCHK(ctx, hipMemcpyAsync(path.data(), dpath, path.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+            HIPCHK(ctx, hipStreamSynchronize(stream));
+            // tunnels of one mesh are consecutive in the list and in order
+            for (int i = a; i < b; ++i) {
+                RunPrep &rp = preps[tnm[g0 + i]];
+                const int k = tnt[g0 + i];
+                rp.g_tn_off[k + 1] = rp.g_tn_off[k] + tc[i];
+                rp.g_tn_v.insert(rp.g_tn_v.end(), path.begin() + toff[i - a], path.begin() + toff[i - a + 1]);
+            }
+            a = b;
+        }
+        HIPCHK(ctx, hipMemcpyAsync(len.data(), dlen, nt * sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        for (int i = 0; i < nt; ++i) preps[tnm[g0 + i]].g_tn_len[tnt[g0 + i]] = len[i];
+    }
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+    for (RunPrep &rp : preps) rp.post_given = true;
+    return VLS_OK;
+}
+
 // Tunnel-loop passes of every handle loop and, with VLS_REFINE_PASS, the
 // refinement pass of every tunnel, after the initial pass (vls_run only).
 // As many passes run at once as there are co-resident workgroups and slots
@@ -1091,7 +1220,18 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
     HIPCHK(ctx, hipStreamSynchronize(stream));
     vls_result *r = &R;
     r->nv = nv;
-    if (vls_status ps = post_passes(ctx, rp, c, *r)) return ps;
+    if (rp.post_given) {
+        r->node_pos = std::move(rp.g_node_pos);
+        r->tn = std::move(rp.g_tn);
+        r->tn_off = std::move(rp.g_tn_off);
+        r->tn_v = std::move(rp.g_tn_v);
+        r->tn_len = std::move(rp.g_tn_len);
+        r->tn_pts.resize(r->tn_v.size() * 3);
+        for (size_t q = 0; q < r->tn_v.size(); ++q)
+            std::memcpy(r->tn_pts.data() + 3 * q, m->xyz.data() + 3 * (size_t)r->tn_v[q], 3 * sizeof(double));
+    } else if (vls_status ps = post_passes(ctx, rp, c, *r)) {
+        return ps;
+    }
     if (c.status == 0)
         if (vls_status ps = run_passes(ctx, rp, p, c, *r)) return ps;
     float ms_k = 0.f, ms_t = 0.f;
@@ -1462,6 +1602,14 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
     (void)hipEventElapsedTime(&ms_b, b0, b1);
     (void)hipEventDestroy(b0);
     (void)hipEventDestroy(b1);
+    {
+        std::vector<Ctl> cs(n);
+        for (int32_t i = 0; i < n; ++i)
+            HIPCHK(ctx, hipMemcpyAsync(&cs[i], preps[i].s.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+        if (vls_status ps = batch_post_passes(ctx, meshes, preps, cs, (const DMesh *)dm, (const DState *)ds, stream))
+            return ps;
+    }
     vls_status first = VLS_OK;
     for (int32_t i = 0; i < n; ++i) {
         HIPCHK(ctx, hipEventRecord(preps[i].e2, stream));

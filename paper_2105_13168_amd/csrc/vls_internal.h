@@ -230,6 +230,20 @@ hipError_t launch_reeb_fill(const DMesh &m, const DState &s, int ev0, int n_even
 hipError_t launch_reeb_mean(const DMesh &m, int n_events, const int64_t *off, const int64_t *cnt,
                             int32_t *buf, double *pos, hipStream_t st);
 hipError_t launch_tunnel_count(const DState &s, int n_tunnels, int64_t *cnt, hipStream_t st);
+// the same post-passes over the events / tunnels of many meshes at once:
+// entry g is event eve[g] (tunnel tnt[g]) of mesh evm[g] (tnm[g]) of the
+// device arrays ms / ss
+hipError_t launch_reeb_count_multi(const DMesh *ms, const DState *ss, const int32_t *evm, const int32_t *eve, int n,
+                                   int64_t *cnt, int32_t *ck, int64_t *meta, hipStream_t st);
+hipError_t launch_reeb_fill_multi(const DMesh *ms, const DState *ss, const int32_t *evm, const int32_t *eve, int g0,
+                                  int n, const int64_t *off, const int64_t *cnt, const int32_t *ck,
+                                  const int64_t *meta, int32_t *buf, hipStream_t st);
+hipError_t launch_reeb_mean_multi(const DMesh *ms, const int32_t *evm, int g0, int n, const int64_t *off,
+                                  const int64_t *cnt, int32_t *buf, double *pos, hipStream_t st);
+hipError_t launch_tunnel_count_multi(const DState *ss, const int32_t *tnm, const int32_t *tnt, int n, int64_t *cnt,
+                                     hipStream_t st);
+hipError_t launch_tunnel_fill_multi(const DMesh *ms, const DState *ss, const int32_t *tnm, const int32_t *tnt, int g0,
+                                    int n, const int64_t *off, int32_t *out, double *len, hipStream_t st);
 hipError_t launch_tunnel_fill(const DMesh &m, const DState &s, int t0, int n_tunnels, const int64_t *off, int32_t *out,
                               double *len, hipStream_t st);
 

@@ -2656,11 +2656,9 @@ hipError_t launch_steps(const DMesh &m, const DState &s, const DParams &p, int g
 // segments in parallel.  meta[ev][q] = {length, stride, checkpoints, offset
 // of the loop's entries}; cnt[ev] = 3 * total length.
 #define RCK 64
-__global__ void k_reeb_count(DMesh m, DState s, int ev0, int n_events, int64_t *cnt, int32_t *ck, int64_t *meta) {
-    // events ev0 .. ev0+n_events-1; cnt, ck, meta indexed from ev0
-    if ((int)blockIdx.x >= n_events) return;
-    const int ev = ev0 + (int)blockIdx.x;
-    const int64_t rel = blockIdx.x;
+// event ev of the mesh (m, s); its outputs at index rel of cnt, ck, meta
+__device__ __forceinline__ void reeb_count_one(const DMesh &m, const DState &s, int ev, int64_t rel, int64_t *cnt,
+                                               int32_t *ck, int64_t *meta) {
     const int lane = threadIdx.x;
     const int64_t *rec = s.ev + 16 * (int64_t)ev;
     const int32_t v = (int32_t)rec[1];
@@ -2701,17 +2699,31 @@ __global__ void k_reeb_count(DMesh m, DState s, int ev0, int n_events, int64_t *
     if (lane == 63) cnt[rel] = 3 * inc;
 }
 
+__global__ void k_reeb_count(DMesh m, DState s, int ev0, int n_events, int64_t *cnt, int32_t *ck, int64_t *meta) {
+    // events ev0 .. ev0+n_events-1; cnt, ck, meta indexed from ev0
+    if ((int)blockIdx.x >= n_events) return;
+    reeb_count_one(m, s, ev0 + (int)blockIdx.x, blockIdx.x, cnt, ck, meta);
+}
+
+// many meshes' events in one launch: entry g is event eve[g] of mesh evm[g]
+__global__ void k_reeb_count_multi(const DMesh *ms, const DState *ss, const int32_t *evm, const int32_t *eve, int n,
+                                   int64_t *cnt, int32_t *ck, int64_t *meta) {
+    const int g = (int)blockIdx.x;
+    if (g >= n) return;
+    const int i = evm[g];
+    reeb_count_one(ms[i], ss[i], eve[g], g, cnt, ck, meta);
+}
+
 // Fill pass: a workgroup per event; every (loop, checkpoint) segment is
 // re-walked by one thread, writing the three vertices of each front
 // triangle; then the segment's padding up to its power of two.  The order
 // of the entries does not matter (they are sorted before the mean).
 // Events ev0 .. ev0+n_events-1: off[] (n_events+1 entries) is relative to
 // this launch, cnt/ck/meta are the count pass's arrays shifted to ev0.
-__global__ void k_reeb_fill(DMesh m, DState s, int ev0, int n_events, const int64_t *off, const int64_t *cnt,
-                            const int32_t *ck, const int64_t *meta, int32_t *buf) {
-    if ((int)blockIdx.x >= n_events) return;
-    const int64_t rel = blockIdx.x;
-    const int64_t *rec = s.ev + 16 * (int64_t)(ev0 + (int)rel);
+__device__ __forceinline__ void reeb_fill_one(const DMesh &m, const DState &s, int ev, int64_t rel, const int64_t *off,
+                                              const int64_t *cnt, const int32_t *ck, const int64_t *meta,
+                                              int32_t *buf) {
+    const int64_t *rec = s.ev + 16 * (int64_t)ev;
     const int32_t v = (int32_t)rec[1];
     const int sN = (int)rec[4] < 16 ? (int)rec[4] : 16;
     const uint64_t kv = s.key[v];
@@ -2737,6 +2749,23 @@ __global__ void k_reeb_fill(DMesh m, DState s, int ev0, int n_events, const int6
     for (int64_t i = off[rel] + cnt[rel] + threadIdx.x; i < off[rel + 1]; i += blockDim.x) buf[i] = 0x7fffffff;
 }
 
+__global__ void k_reeb_fill(DMesh m, DState s, int ev0, int n_events, const int64_t *off, const int64_t *cnt,
+                            const int32_t *ck, const int64_t *meta, int32_t *buf) {
+    if ((int)blockIdx.x >= n_events) return;
+    reeb_fill_one(m, s, ev0 + (int)blockIdx.x, blockIdx.x, off, cnt, ck, meta, buf);
+}
+
+// entries g0 .. g0+n-1 of a multi-mesh event list; off (n+1 entries) is
+// relative to g0, cnt / ck / meta are the count pass's arrays shifted to g0
+__global__ void k_reeb_fill_multi(const DMesh *ms, const DState *ss, const int32_t *evm, const int32_t *eve, int g0,
+                                  int n, const int64_t *off, const int64_t *cnt, const int32_t *ck,
+                                  const int64_t *meta, int32_t *buf) {
+    const int rel = (int)blockIdx.x;
+    if (rel >= n) return;
+    const int i = evm[g0 + rel];
+    reeb_fill_one(ms[i], ss[i], eve[g0 + rel], rel, off, cnt, ck, meta, buf);
+}
+
 template <typename K>
 __device__ void block_bitonic_t(K *a, int64_t np) {
     for (int64_t k = 2; k <= np; k <<= 1) {
@@ -2755,10 +2784,13 @@ __device__ void block_bitonic_t(K *a, int64_t np) {
 }
 
 #define MEANCAP 16384
-__global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const int64_t *off,
-                                                   const int64_t *cnt, int32_t *buf, double *pos) {
-    __shared__ uint32_t a[MEANCAP];
+// Reeb positions of n_events events: entry ev's mesh positions are
+// xyz_of(ev) (one mesh, or the mesh of entry ev of a multi-mesh list)
+template <typename XyzOf>
+__device__ __forceinline__ void reeb_mean_all(XyzOf xyz_of, int n_events, const int64_t *off, const int64_t *cnt,
+                                              int32_t *buf, double *pos, uint32_t *a) {
     for (int ev = blockIdx.x; ev < n_events; ev += gridDim.x) {
+        const double *xyz = xyz_of(ev);
         const int64_t o = off[ev], np = off[ev + 1] - off[ev], n = cnt[ev];
         uint32_t *arr;
         if (np <= MEANCAP) {
@@ -2785,7 +2817,7 @@ __global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const i
                 if (i < n) {
                     first = i == 0 || arr[i] != arr[i - 1];
                     if (first) {
-                        const double *x = m.xyz + 3 * (int64_t)arr[i];
+                        const double *x = xyz + 3 * (int64_t)arr[i];
                         x0 = x[0];
                         x1 = x[1];
                         x2 = x[2];
@@ -2810,6 +2842,20 @@ __global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const i
         }
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(NT) k_reeb_mean(DMesh m, int n_events, const int64_t *off,
+                                                   const int64_t *cnt, int32_t *buf, double *pos) {
+    __shared__ uint32_t a[MEANCAP];
+    const double *xyz = m.xyz;
+    reeb_mean_all([=](int) { return xyz; }, n_events, off, cnt, buf, pos, a);
+}
+
+__global__ void __launch_bounds__(NT) k_reeb_mean_multi(const DMesh *ms, const int32_t *evm, int g0, int n,
+                                                         const int64_t *off, const int64_t *cnt, int32_t *buf,
+                                                         double *pos) {
+    __shared__ uint32_t a[MEANCAP];
+    reeb_mean_all([=](int ev) { return ms[evm[g0 + ev]].xyz; }, n, off, cnt, buf, pos, a);
 }
 
 hipError_t launch_reeb_count(const DMesh &m, const DState &s, int ev0, int n_events, int64_t *cnt, int32_t *ck,
@@ -2860,6 +2906,30 @@ __device__ int64_t tunnel_path(const DState &s, int i, int32_t *out) {
     return n + up + 1 + down;
 }
 
+// tunnel of entry g of a multi-mesh list: tunnel tnt[g] of mesh tnm[g]
+__global__ void k_tunnel_count_multi(const DState *ss, const int32_t *tnm, const int32_t *tnt, int n, int64_t *cnt) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x)
+        cnt[g] = tunnel_path(ss[tnm[g]], tnt[g], nullptr);
+}
+// entries g0 .. g0+n-1; off (n+1 entries) and len are relative to g0
+__global__ void k_tunnel_fill_multi(const DMesh *ms, const DState *ss, const int32_t *tnm, const int32_t *tnt, int g0,
+                                    int n, const int64_t *off, int32_t *out, double *len) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int mi = tnm[g0 + i];
+        const int64_t nn = tunnel_path(ss[mi], tnt[g0 + i], out + off[i]);
+        const int32_t *c = out + off[i];
+        const double *xyz = ms[mi].xyz;
+        double L = 0.0;
+        for (int64_t q = 0; q < nn; ++q) {
+            const double *pa = xyz + 3 * (int64_t)c[q];
+            const double *pb = xyz + 3 * (int64_t)c[(q + 1) % nn];
+            const double dx = pb[0] - pa[0], dy = pb[1] - pa[1], dz = pb[2] - pa[2];
+            L = L + sqrt((dx * dx + dy * dy) + dz * dz);
+        }
+        len[i] = L;
+    }
+}
+
 __global__ void k_tunnel_count(DState s, int nt, int64_t *cnt) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x)
         cnt[i] = tunnel_path(s, i, nullptr);
@@ -2879,6 +2949,40 @@ __global__ void k_tunnel_fill(DMesh m, DState s, int t0, int nt, const int64_t *
         len[i] = L;
     }
 }
+hipError_t launch_reeb_count_multi(const DMesh *ms, const DState *ss, const int32_t *evm, const int32_t *eve, int n,
+                                   int64_t *cnt, int32_t *ck, int64_t *meta, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reeb_count_multi, dim3(n), dim3(64), 0, st, ms, ss, evm, eve, n, cnt, ck, meta);
+    return hipGetLastError();
+}
+hipError_t launch_reeb_fill_multi(const DMesh *ms, const DState *ss, const int32_t *evm, const int32_t *eve, int g0,
+                                  int n, const int64_t *off, const int64_t *cnt, const int32_t *ck,
+                                  const int64_t *meta, int32_t *buf, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reeb_fill_multi, dim3(n), dim3(NT), 0, st, ms, ss, evm, eve, g0, n, off, cnt, ck, meta, buf);
+    return hipGetLastError();
+}
+hipError_t launch_reeb_mean_multi(const DMesh *ms, const int32_t *evm, int g0, int n, const int64_t *off,
+                                  const int64_t *cnt, int32_t *buf, double *pos, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = n < 1024 ? n : 1024;
+    hipLaunchKernelGGL(k_reeb_mean_multi, dim3(blocks), dim3(NT), 0, st, ms, evm, g0, n, off, cnt, buf, pos);
+    return hipGetLastError();
+}
+hipError_t launch_tunnel_count_multi(const DState *ss, const int32_t *tnm, const int32_t *tnt, int n, int64_t *cnt,
+                                     hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tunnel_count_multi, dim3((n + 63) / 64), dim3(64), 0, st, ss, tnm, tnt, n, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_tunnel_fill_multi(const DMesh *ms, const DState *ss, const int32_t *tnm, const int32_t *tnt, int g0,
+                                    int n, const int64_t *off, int32_t *out, double *len, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tunnel_fill_multi, dim3((n + 63) / 64), dim3(64), 0, st, ms, ss, tnm, tnt, g0, n, off, out,
+                       len);
+    return hipGetLastError();
+}
+
 hipError_t launch_tunnel_count(const DState &s, int n_tunnels, int64_t *cnt, hipStream_t st) {
     if (n_tunnels <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tunnel_count, dim3((n_tunnels + 63) / 64), dim3(64), 0, st, s, n_tunnels, cnt);
