@@ -954,23 +954,41 @@ static vls_status post_passes(vls_context *ctx, RunPrep &rp, const Ctl &c, vls_r
     return VLS_OK;
 }
 
-// Post-passes of a whole batch: the events (and tunnels) of every mesh are
-// listed together and each pass is one launch over a chunk of that list, so
-// the meshes' short dependent walks run side by side instead of mesh after
-// mesh with a synchronisation between each.  The outputs are those of
-// post_passes (the same kernels' bodies, one entry per block or thread),
-// handed to finish_run through the RunPreps.  dm / ds: the batch's device
-// arrays of meshes and run states; cs: each run's control block.
+// Post-passes of many runs at once (a batch, or the server's completed
+// requests): the events (and tunnels) of every run are listed together and
+// each pass is one launch over a chunk of that list, so the runs' short
+// dependent walks run side by side instead of run after run with a
+// synchronisation between each.  The outputs are those of post_passes (the
+// same kernels' bodies, one entry per block or thread), handed to
+// finish_run through the RunPreps.  dm / ds: device arrays of the runs'
+// meshes and states; cs: each run's control block.  Scratch: chunk arrays of
+// fixed size, a fill buffer and a path buffer (multi_post_bytes), from A.
 constexpr int kMultiEvents = 4096;
 constexpr int kMultiTunnels = 65536;
-static vls_status batch_post_passes(vls_context *ctx, const vls_mesh *const *meshes, std::vector<RunPrep> &preps,
-                                    const std::vector<Ctl> &cs, const DMesh *dm, const DState *ds,
-                                    hipStream_t stream) {
+static void multi_post_caps(const std::vector<const vls_mesh *> &meshes, size_t &fill_cap, size_t &path_cap) {
+    fill_cap = (size_t)1 << 22;
+    path_cap = (size_t)1 << 22;
+    for (const vls_mesh *m : meshes) {
+        fill_cap = std::max(fill_cap, post_fill_entries(m));
+        path_cap = std::max(path_cap, (size_t)(2 * m->nv + 2));
+    }
+}
+static size_t multi_post_bytes(size_t fill_cap, size_t path_cap) {
+    const size_t C = kMultiEvents, TC = kMultiTunnels;
+    return DevArena::padded(C * 4) * 2 + DevArena::padded((C + 1) * 8) * 2 + DevArena::padded(C * 16 * 64 * 4) +
+           DevArena::padded(C * 16 * 4 * 8) + DevArena::padded(C * 3 * 8) + DevArena::padded((fill_cap + 16) * 4) +
+           DevArena::padded(TC * 4) * 2 + DevArena::padded((TC + 1) * 8) * 2 + DevArena::padded(TC * 8) +
+           DevArena::padded((path_cap + 16) * 4);
+}
+static vls_status multi_post_passes(vls_context *ctx, const std::vector<const vls_mesh *> &meshes,
+                                    const std::vector<RunPrep *> &preps, const std::vector<Ctl> &cs, const DMesh *dm,
+                                    const DState *ds, DevArena &A, hipStream_t stream) {
     const int n = (int)preps.size();
     std::vector<int32_t> evm, eve, tnm, tnt;
-    size_t fill_cap = (size_t)1 << 22, path_cap = (size_t)1 << 22;
+    size_t fill_cap, path_cap;
+    multi_post_caps(meshes, fill_cap, path_cap);
     for (int i = 0; i < n; ++i) {
-        RunPrep &rp = preps[i];
+        RunPrep &rp = *preps[i];
         const int nev = cs[i].n_events, ntn = cs[i].n_tunnels;
         rp.g_node_pos.assign((size_t)nev * 3, 0.0);
         rp.g_tn.resize((size_t)ntn * 4);
@@ -979,38 +997,37 @@ static vls_status batch_post_passes(vls_context *ctx, const vls_mesh *const *mes
         rp.g_tn_v.clear();
         for (int e = 0; e < nev; ++e) { evm.push_back(i); eve.push_back(e); }
         for (int e = 0; e < ntn; ++e) { tnm.push_back(i); tnt.push_back(e); }
-        fill_cap = std::max(fill_cap, post_fill_entries(meshes[i]));
-        path_cap = std::max(path_cap, (size_t)(2 * meshes[i]->nv + 2));
         if (ntn)
             HIPCHK(ctx, hipMemcpyAsync(rp.g_tn.data(), rp.s.tn, (size_t)ntn * 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
                                        stream));
     }
     const int E = (int)evm.size(), T = (int)tnm.size();
-    DevArena A;
-    const int C = kMultiEvents;
+    const int C = kMultiEvents, TC = kMultiTunnels;
     int32_t *devm = nullptr, *deve = nullptr, *dtnm = nullptr, *dtnt = nullptr, *dck = nullptr, *dbuf = nullptr,
             *dpath = nullptr;
     int64_t *dcnt = nullptr, *doff = nullptr, *dmeta = nullptr, *dtcnt = nullptr, *dtoff = nullptr;
     double *dpos = nullptr, *dlen = nullptr;
-    struct Rel { DevArena *a; ~Rel() { a->release(); } } rel{&A};
-    if (A.get(&devm, E) || A.get(&deve, E) || A.get(&dtnm, T) || A.get(&dtnt, T) || A.get(&dcnt, C + 1) ||
-        A.get(&doff, C + 1) || A.get(&dck, (size_t)C * 16 * 64) || A.get(&dmeta, (size_t)C * 16 * 4) ||
-        A.get(&dpos, (size_t)C * 3) || A.get(&dbuf, fill_cap + 16) || A.get(&dtcnt, kMultiTunnels + 1) ||
-        A.get(&dtoff, kMultiTunnels + 1) || A.get(&dlen, kMultiTunnels) || A.get(&dpath, path_cap + 16))
-        return set_err(ctx, VLS_E_OUT_OF_MEMORY, "batch post-pass buffers");
-    if (E) {
-        HIPCHK(ctx, hipMemcpyAsync(devm, evm.data(), (size_t)E * 4, hipMemcpyHostToDevice, stream));
-        HIPCHK(ctx, hipMemcpyAsync(deve, eve.data(), (size_t)E * 4, hipMemcpyHostToDevice, stream));
-    }
-    if (T) {
-        HIPCHK(ctx, hipMemcpyAsync(dtnm, tnm.data(), (size_t)T * 4, hipMemcpyHostToDevice, stream));
-        HIPCHK(ctx, hipMemcpyAsync(dtnt, tnt.data(), (size_t)T * 4, hipMemcpyHostToDevice, stream));
-    }
+    const size_t mark = A.used;
+    struct Rel {
+        DevArena *a;
+        size_t mark;
+        ~Rel() {
+            if (a->mode == DevArena::MALLOC) a->release();
+            a->used = mark;
+        }
+    } rel{&A, mark};
+    if (A.get(&devm, C) || A.get(&deve, C) || A.get(&dcnt, C + 1) || A.get(&doff, C + 1) ||
+        A.get(&dck, (size_t)C * 16 * 64) || A.get(&dmeta, (size_t)C * 16 * 4) || A.get(&dpos, (size_t)C * 3) ||
+        A.get(&dbuf, fill_cap + 16) || A.get(&dtnm, TC) || A.get(&dtnt, TC) || A.get(&dtcnt, TC + 1) ||
+        A.get(&dtoff, TC + 1) || A.get(&dlen, TC) || A.get(&dpath, path_cap + 16))
+        return set_err(ctx, VLS_E_OUT_OF_MEMORY, "multi-run post-pass buffers");
     std::vector<int64_t> cnt(C + 1), np(C), off;
     std::vector<double> pos((size_t)C * 3);
     for (int g0 = 0; g0 < E; g0 += C) {
         const int nc = std::min(C, E - g0);
-        HIPCHK(ctx, launch_reeb_count_multi(dm, ds, devm + g0, deve + g0, nc, dcnt, dck, dmeta, stream));
+        HIPCHK(ctx, hipMemcpyAsync(devm, evm.data() + g0, (size_t)nc * 4, hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, hipMemcpyAsync(deve, eve.data() + g0, (size_t)nc * 4, hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, launch_reeb_count_multi(dm, ds, devm, deve, nc, dcnt, dck, dmeta, stream));
         HIPCHK(ctx, hipMemcpyAsync(cnt.data(), dcnt, nc * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
         for (int i = 0; i < nc; ++i) {
@@ -1026,10 +1043,9 @@ static vls_status batch_post_passes(vls_context *ctx, const vls_mesh *const *mes
             off.assign(b - a + 1, 0);
             for (int i = a; i < b; ++i) off[i - a + 1] = off[i - a] + np[i];
             HIPCHK(ctx, hipMemcpyAsync(doff, off.data(), (b - a + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-            HIPCHK(ctx, launch_reeb_fill_multi(dm, ds, devm, deve, g0 + a, b - a, doff, dcnt + a,
-                                               dck + (size_t)a * 16 * 64, dmeta + (size_t)a * 16 * 4, dbuf, stream));
-            HIPCHK(ctx, launch_reeb_mean_multi(dm, devm, g0 + a, b - a, doff, dcnt + a, dbuf, dpos + 3 * (size_t)a,
-                                               stream));
+            HIPCHK(ctx, launch_reeb_fill_multi(dm, ds, devm, deve, a, b - a, doff, dcnt + a, dck + (size_t)a * 16 * 64,
+                                               dmeta + (size_t)a * 16 * 4, dbuf, stream));
+            HIPCHK(ctx, launch_reeb_mean_multi(dm, devm, a, b - a, doff, dcnt + a, dbuf, dpos + 3 * (size_t)a, stream));
             // the offsets are re-uploaded by the next sub-chunk: wait for this one
             HIPCHK(ctx, hipStreamSynchronize(stream));
             a = b;
@@ -1037,15 +1053,17 @@ static vls_status batch_post_passes(vls_context *ctx, const vls_mesh *const *mes
         HIPCHK(ctx, hipMemcpyAsync(pos.data(), dpos, (size_t)nc * 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
         for (int i = 0; i < nc; ++i)
-            std::memcpy(preps[evm[g0 + i]].g_node_pos.data() + 3 * (size_t)eve[g0 + i], pos.data() + 3 * (size_t)i,
+            std::memcpy(preps[evm[g0 + i]]->g_node_pos.data() + 3 * (size_t)eve[g0 + i], pos.data() + 3 * (size_t)i,
                         3 * sizeof(double));
     }
-    std::vector<int64_t> tc(kMultiTunnels + 1), toff;
+    std::vector<int64_t> tc(TC + 1), toff;
     std::vector<int32_t> path;
-    std::vector<double> len(kMultiTunnels);
-    for (int g0 = 0; g0 < T; g0 += kMultiTunnels) {
-        const int nt = std::min(kMultiTunnels, T - g0);
-        HIPCHK(ctx, launch_tunnel_count_multi(ds, dtnm + g0, dtnt + g0, nt, dtcnt, stream));
+    std::vector<double> len(TC);
+    for (int g0 = 0; g0 < T; g0 += TC) {
+        const int nt = std::min(TC, T - g0);
+        HIPCHK(ctx, hipMemcpyAsync(dtnm, tnm.data() + g0, (size_t)nt * 4, hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, hipMemcpyAsync(dtnt, tnt.data() + g0, (size_t)nt * 4, hipMemcpyHostToDevice, stream));
+        HIPCHK(ctx, launch_tunnel_count_multi(ds, dtnm, dtnt, nt, dtcnt, stream));
         HIPCHK(ctx, hipMemcpyAsync(tc.data(), dtcnt, nt * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
         for (int a = 0; a < nt;) {
@@ -1056,13 +1074,13 @@ static vls_status batch_post_passes(vls_context *ctx, const vls_mesh *const *mes
             toff.assign(b - a + 1, 0);
             for (int i = a; i < b; ++i) toff[i - a + 1] = toff[i - a] + tc[i];
             HIPCHK(ctx, hipMemcpyAsync(dtoff, toff.data(), (b - a + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-            HIPCHK(ctx, launch_tunnel_fill_multi(dm, ds, dtnm, dtnt, g0 + a, b - a, dtoff, dpath, dlen + a, stream));
+            HIPCHK(ctx, launch_tunnel_fill_multi(dm, ds, dtnm, dtnt, a, b - a, dtoff, dpath, dlen + a, stream));
             path.resize((size_t)toff[b - a]);
             HIPCHK(ctx, hipMemcpyAsync(path.data(), dpath, path.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
             HIPCHK(ctx, hipStreamSynchronize(stream));
-            // tunnels of one mesh are consecutive in the list and in order
+            // tunnels of one run are consecutive in the list and in order
             for (int i = a; i < b; ++i) {
-                RunPrep &rp = preps[tnm[g0 + i]];
+                RunPrep &rp = *preps[tnm[g0 + i]];
                 const int k = tnt[g0 + i];
                 rp.g_tn_off[k + 1] = rp.g_tn_off[k] + tc[i];
                 rp.g_tn_v.insert(rp.g_tn_v.end(), path.begin() + toff[i - a], path.begin() + toff[i - a + 1]);
@@ -1071,10 +1089,10 @@ static vls_status batch_post_passes(vls_context *ctx, const vls_mesh *const *mes
         }
         HIPCHK(ctx, hipMemcpyAsync(len.data(), dlen, nt * sizeof(double), hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
-        for (int i = 0; i < nt; ++i) preps[tnm[g0 + i]].g_tn_len[tnt[g0 + i]] = len[i];
+        for (int i = 0; i < nt; ++i) preps[tnm[g0 + i]]->g_tn_len[tnt[g0 + i]] = len[i];
     }
     HIPCHK(ctx, hipStreamSynchronize(stream));
-    for (RunPrep &rp : preps) rp.post_given = true;
+    for (RunPrep *rp : preps) rp->post_given = true;
     return VLS_OK;
 }
 
@@ -1607,7 +1625,11 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
         for (int32_t i = 0; i < n; ++i)
             HIPCHK(ctx, hipMemcpyAsync(&cs[i], preps[i].s.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HIPCHK(ctx, hipStreamSynchronize(stream));
-        if (vls_status ps = batch_post_passes(ctx, meshes, preps, cs, (const DMesh *)dm, (const DState *)ds, stream))
+        std::vector<const vls_mesh *> mv(meshes, meshes + n);
+        std::vector<RunPrep *> pv(n);
+        for (int32_t i = 0; i < n; ++i) pv[i] = &preps[i];
+        DevArena A;
+        if (vls_status ps = multi_post_passes(ctx, mv, pv, cs, (const DMesh *)dm, (const DState *)ds, A, stream))
             return ps;
     }
     vls_status first = VLS_OK;
@@ -1907,6 +1929,11 @@ struct vls_server {
     size_t pooled = 0, pool_cap = 0;
     void *post_buf = nullptr;
     size_t post_cap = 0;
+    // completions taken together: their meshes and run states on the device
+    // (kCompleteBatch entries), and the multi-run post-pass scratch in
+    // post_buf (grown when needed)
+    DMesh *cdm = nullptr;
+    DState *cds = nullptr;
     // host time of the scheduler's phases (ms): admissions, launches incl.
     // their wait; and of the completion thread's work
     double t_admit_ms = 0.0, t_launch_ms = 0.0, t_complete_ms = 0.0;
@@ -1923,6 +1950,8 @@ struct vls_server {
         for (void *q : {dm, ds, dp, dord, dnext, ddone, dtg, dsl}) if (q) (void)hipFree(q);
         pool.clear();
         if (post_buf) (void)hipFree(post_buf);
+        if (cdm) (void)hipFree(cdm);
+        if (cds) (void)hipFree(cds);
         if (ctx.own_stream && ctx.stream) (void)hipStreamDestroy(ctx.stream);
         if (cctx.own_stream && cctx.stream) (void)hipStreamDestroy(cctx.stream);
     }
@@ -1948,7 +1977,7 @@ struct vls_server {
         pool[m].push_back(std::move(rb));
     }
     void finish(SrvReq *q, vls_status st, vls_result *r);
-    void complete(SrvReq *q);
+    void complete(std::vector<SrvReq *> &qs);
     bool admit_one(SrvReq *q);
     bool launch_slice();
     void loop();
@@ -1973,43 +2002,86 @@ void vls_server::finish(SrvReq *q, vls_status st, vls_result *r) {
     completed += 1;
 }
 
-// a request whose step kernel finished: post-passes, results to the host
-void vls_server::complete(SrvReq *q) {
-    // the request's device work ended with the slice that finished it; the
-    // post-passes and copies go on the completion stream
-    q->prep->stream = cctx.stream;
-    // post-pass scratch: the server's reusable block
-    const size_t need = post_bytes(q->m);
+// requests whose step kernels finished: post-passes of all of them
+// together, then each one's results to the host
+constexpr int kCompleteBatch = 256;
+void vls_server::complete(std::vector<SrvReq *> &qs) {
+    const int k = (int)qs.size();
+    auto fail_all = [&](vls_status st) {
+        for (SrvReq *q : qs) finish(q, st, nullptr);
+    };
+    // the requests' device work ended with the slices that finished them;
+    // the post-passes and copies go on the completion stream
+    std::vector<const vls_mesh *> mv(k);
+    std::vector<RunPrep *> pv(k);
+    std::vector<DMesh> hm(k);
+    std::vector<DState> hs(k);
+    std::vector<Ctl> cs(k);
+    hipStream_t st = cctx.stream;
+    for (int i = 0; i < k; ++i) {
+        RunPrep &rp = *qs[i]->prep;
+        rp.stream = st;
+        mv[i] = qs[i]->m;
+        pv[i] = &rp;
+        hm[i] = qs[i]->m->d;
+        hs[i] = rp.s;
+        if (hipMemcpyAsync(&cs[i], rp.s.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st) != hipSuccess) {
+            fail_all(VLS_E_DEVICE);
+            return;
+        }
+    }
+    size_t fill_cap, path_cap;
+    multi_post_caps(mv, fill_cap, path_cap);
+    const size_t need = multi_post_bytes(fill_cap, path_cap);
     if (need > post_cap) {
         if (post_buf) (void)hipFree(post_buf);
         post_buf = nullptr;
         post_cap = 0;
-        if (hipMalloc(&post_buf, need) != hipSuccess) { post_buf = nullptr; finish(q, VLS_E_OUT_OF_MEMORY, nullptr); return; }
+        if (hipMalloc(&post_buf, need) != hipSuccess) { post_buf = nullptr; fail_all(VLS_E_OUT_OF_MEMORY); return; }
         post_cap = need;
     }
-    q->prep->post.mode = DevArena::CARVE;
-    q->prep->post.base = (char *)post_buf;
-    q->prep->post.cap = post_cap;
-    q->prep->post.used = 0;
-    auto r = std::make_unique<vls_result>();
-    vls_status rs = finish_run(&cctx, *q->prep, &q->p, 0, 256, -1.0, *r);
-    if (rs != VLS_OK && !is_run_status(rs)) { finish(q, rs, nullptr); return; }
-    finish(q, rs, r.release());
+    if ((!cdm && hipMalloc(&cdm, kCompleteBatch * sizeof(DMesh)) != hipSuccess) ||
+        (!cds && hipMalloc(&cds, kCompleteBatch * sizeof(DState)) != hipSuccess)) {
+        fail_all(VLS_E_OUT_OF_MEMORY);
+        return;
+    }
+    if (hipMemcpyAsync(cdm, hm.data(), k * sizeof(DMesh), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(cds, hs.data(), k * sizeof(DState), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        fail_all(VLS_E_DEVICE);
+        return;
+    }
+    DevArena A;
+    A.mode = DevArena::CARVE;
+    A.base = (char *)post_buf;
+    A.cap = post_cap;
+    if (vls_status ps = multi_post_passes(&cctx, mv, pv, cs, cdm, cds, A, st)) {
+        fail_all(ps);
+        return;
+    }
+    for (SrvReq *q : qs) {
+        auto r = std::make_unique<vls_result>();
+        vls_status rs = finish_run(&cctx, *q->prep, &q->p, 0, 256, -1.0, *r);
+        if (rs != VLS_OK && !is_run_status(rs)) { finish(q, rs, nullptr); continue; }
+        finish(q, rs, r.release());
+    }
 }
 
 void vls_server::complete_loop() {
     (void)hipSetDevice(cctx.device);
     for (;;) {
-        SrvReq *q = nullptr;
+        std::vector<SrvReq *> qs;
         {
             std::unique_lock<std::mutex> lk(mu);
             ccv.wait(lk, [&] { return cstop || !cq.empty(); });
             if (cq.empty()) break;
-            q = cq.front();
-            cq.pop_front();
+            while (!cq.empty() && (int)qs.size() < kCompleteBatch) {
+                qs.push_back(cq.front());
+                cq.pop_front();
+            }
         }
         const auto t0 = Clock::now();
-        complete(q);
+        complete(qs);
         const double ms = ms_between(t0, Clock::now());
         {
             std::lock_guard<std::mutex> lk(mu);
