@@ -1936,14 +1936,39 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         kl->Lm[i] = mask;
         s.key[x] = tk | (uint64_t)rv;
         s.parent[x] = par;
-        if (rv == 0 && ppos >= 0) {
-            // the parent was inside before step t: its half-edge to x and
-            // its depth are final already
-            kl->Lt[i] = ldg(s.lid + ldg(m.rev + b + ppos));
-            kl->Ld[i] = ldg(s.depth + par) + 1;
-        }
         if (cls != 1) atomicOr(&sh->event, 1);
         if (nlow == 0 || d > MAXDEG) atomicOr(&sh->event, 2);
+    }
+    // the tag of the half-edge (parent -> x) and the depth of round-0
+    // vertices, whose parents were inside before step t (both final
+    // already): every entry of the thread at once, so its loads are two
+    // round trips in all rather than two per entry (CAP / NT entries at most)
+    {
+        constexpr int PE = CAP / NT;
+        int32_t he[PE], pp[PE], rh[PE], tg[PE], dp[PE];
+#pragma unroll
+        for (int q = 0; q < PE; ++q) {
+            const int i = tid + q * NT;
+            he[q] = -1;
+            pp[q] = -1;
+            if (i < nL && kl->Lr[i] == 0 && kl->Lq[i] >= 0) {
+                he[q] = kl->Lb[i] + kl->Lq[i];
+                pp[q] = kl->Lp[i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PE; ++q) rh[q] = he[q] >= 0 ? ldg(m.rev + he[q]) : -1;
+#pragma unroll
+        for (int q = 0; q < PE; ++q) {
+            tg[q] = rh[q] >= 0 ? ldg(s.lid + rh[q]) : 0;
+            dp[q] = pp[q] >= 0 ? ldg(s.depth + pp[q]) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PE; ++q)
+            if (he[q] >= 0) {
+                kl->Lt[tid + q * NT] = tg[q];
+                kl->Ld[tid + q * NT] = dp[q] + 1;
+            }
     }
     __syncthreads();
     k3 = DCLK();
