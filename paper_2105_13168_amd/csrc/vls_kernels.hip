@@ -1748,6 +1748,23 @@ __device__ __forceinline__ bool load_lrow(const DMesh &m, int32_t x, int32_t *nb
     return true;
 }
 
+// the link of x (ids, then their keys) from its 64 B link row, for a vertex
+// of at most ELL_W - 1 neighbours: four 16 B loads for the ids instead of
+// one load per id (the topology workgroup's gathers are bound by the number
+// of memory instructions its CU issues more than by their latency)
+__device__ __forceinline__ void gather_link_row(const DMesh &m, const uint64_t *key, int32_t x, int32_t *nb,
+                                                uint64_t *kn) {
+    const GLOBAL_AS v4i *row = (const GLOBAL_AS v4i *)(m.lrow + (int64_t)x * ELL_W);
+#pragma unroll
+    for (int q = 0; q < ELL_W / 4; ++q) {
+        const v4i w = row[q];
+        nb[4 * q] = w.x; nb[4 * q + 1] = w.y; nb[4 * q + 2] = w.z; nb[4 * q + 3] = w.w;
+    }
+    nb[ELL_W - 1] = -1;   // that slot holds the first half-edge index
+#pragma unroll
+    for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(key + nb[j]) : KEY_OUT;
+}
+
 template <int CM, int CAP>
 __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, const DParams &p, int64_t t,
                                KSh *sh, KL<CAP> *kl, uint64_t *lsort, int nc, int np) {
@@ -1899,6 +1916,8 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
             if (i == tid && cached) {
 #pragma unroll
                 for (int j = 0; j < GB; ++j) { nb[j] = cnb[j]; kn[j] = ckn[j]; }
+            } else if (d < ELL_W) {
+                gather_link_row(m, s.key, x, nb, kn);
             } else {
                 gather_link(m, s.key, b, d, c0, nb, kn);
             }
