@@ -1821,6 +1821,22 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
             for (int j = 0; j < GB; ++j) kn[j] = nb[j] >= 0 ? ldg(s.key + nb[j]) : KEY_OUT;
 #pragma unroll
             for (int j = 0; j < GB; ++j) hit = hit || kn[j] < tk;
+            // for the classification: which neighbours were inside before
+            // step t (keys that this step does not change) and the
+            // smallest-ranked of them, so that phase 3 needs no key loads;
+            // kept in Lc (bit 24 marks it valid; phase 2 overwrites Lc)
+            // until phase 3 replaces it with its own output
+            uint32_t om = 0;
+            int jm = 31;
+            int32_t um = -1;
+            uint64_t km = KEY_OUT;
+#pragma unroll
+            for (int j = 0; j < GB; ++j)
+                if (nb[j] >= 0 && kn[j] < tk) {
+                    om |= 1u << j;
+                    if (um < 0 || rank_lt(kn[j], nb[j], km, um)) { jm = j; um = nb[j]; km = kn[j]; }
+                }
+            kl->Lc[i] = (int32_t)(om | ((uint32_t)jm << 16) | (1u << 24));
             if (i == tid) {
 #pragma unroll
                 for (int j = 0; j < GB; ++j) { cnb[j] = nb[j]; ckn[j] = kn[j]; }
@@ -1910,6 +1926,51 @@ __device__ __forceinline__ void phase_topo_lds(const DMesh &m, const DState &s, 
         uint64_t kp = KEY_OUT;
         bool first = false, prev = false;
         uint64_t mask = 0;
+        const int pc = kl->Lc[i];
+        if (!(i == tid && cached) && d < ELL_W && ((pc >> 24) & 1)) {
+            // phase 1 recorded the neighbours inside before step t and the
+            // smallest-ranked of them (the parent when there is one: every
+            // earlier vertex ranks below this step's); only the link's ids
+            // are loaded, from its row
+            int32_t nb[GB];
+            {
+                const GLOBAL_AS v4i *row = (const GLOBAL_AS v4i *)(m.lrow + (int64_t)x * ELL_W);
+#pragma unroll
+                for (int q = 0; q < ELL_W / 4; ++q) {
+                    const v4i w = row[q];
+                    nb[4 * q] = w.x; nb[4 * q + 1] = w.y; nb[4 * q + 2] = w.z; nb[4 * q + 3] = w.w;
+                }
+            }
+            const uint32_t om = (uint32_t)pc & 0xffffu;
+            const int jm = (pc >> 16) & 31;
+#pragma unroll
+            for (int j = 0; j < GB; ++j) {
+                if (j >= d) continue;
+                const int32_t u = nb[j];
+                bool low;
+                uint64_t ku = KEY_OUT;
+                if ((om >> j) & 1u) {
+                    low = true;
+                } else {
+                    const int q = hfind(kl, u);
+                    const int ru = q >= 0 ? kl->Lr[q] : -1;
+                    low = ru >= 0 && (ru < rv || (ru == rv && u < x));
+                    ku = tk | (uint64_t)(ru < 0 ? 0 : ru);
+                }
+                if (low) {
+                    nlow++;
+                    mask |= 1ull << j;
+                    if (j > 0 && !prev) runs++;
+                    if (jm != 31) {
+                        if (j == jm) { par = u; ppos = j; }
+                    } else if (par < 0 || rank_lt(ku, u, kp, par)) {
+                        par = u; kp = ku; ppos = j;
+                    }
+                }
+                if (j == 0) first = low;
+                prev = low;
+            }
+        } else
         for (int c0 = 0; c0 < d; c0 += GB) {
             int32_t nb[GB];
             uint64_t kn[GB];
