@@ -53,7 +53,7 @@ def test_traffic_record_matching(tmp_path, monkeypatch):
 
 def test_committed_records_name_their_grid():
     root = os.path.dirname(HERE)
-    for name in ("pretzel256", "dense_lattice10_512"):
+    for name in ("lattice10_1024", "pretzel256", "dense_lattice10_1024"):
         rec = json.load(open(os.path.join(root, "profiles", f"k_steps_{name}_traffic.json")))
         assert isinstance(rec.get("grid"), int) and rec["hbm_bytes_per_launch"] > 0
         assert rec["fetch_factor"] > 0 and rec["write_factor"] > 0
