@@ -120,19 +120,38 @@ __device__ __forceinline__ void fail(const DState &s, int code, int detail) {
     __hip_atomic_store(&s.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// successor of crossed half-edge e=(u->x) along its loop, in the state where
-// the inside set is {y : rank(y) < rank(v)} (plus v itself when post): the
-// triangle (u, x, y) holding directed edge u->x has one more crossed edge,
-// (y,x) if y is inside, else (u,y).
-// One 16 B record per half-edge gives succ[e], nin[e] and y in one load,
-// so a walk step is two dependent loads (record, then the key of y).
-__device__ __forceinline__ int32_t he_next(const DMesh &m, const uint64_t *__restrict__ key,
-                                           int32_t e, uint64_t kv, int32_t v, bool post) {
-    const v4i r = *(const GLOBAL_AS v4i *)(m.hrec + 4 * (int64_t)e);
-    const int32_t y = r.z;
+// Walks along a loop of crossed half-edges, in the state where the inside
+// set is {y : rank(y) < rank(v)} (plus v itself when post): the triangle
+// (u, x, y) holding directed edge e = u->x has one more crossed edge, (y,x)
+// (= nin[e]) if y is inside, else (u,y) (= succ[e]).  One 16 B record per
+// half-edge gives succ[e], nin[e], y and x.
+// A walk along a loop with its next step's loads issued together: the state
+// holds the current half-edge, its owner and its record, and a step loads
+// the key of y and both candidate successors' records at once (which one
+// follows depends on that key), so a step costs one round trip instead of
+// two.  The owner of the successor needs no load: y for nin[e], the same
+// owner for succ[e].
+struct Walk {
+    int32_t e, src;
+    v4i r;
+};
+__device__ __forceinline__ Walk walk_at(const DMesh &m, int32_t e) {
+    Walk w;
+    w.e = e;
+    w.src = ldg(m.src + e);
+    w.r = *(const GLOBAL_AS v4i *)(m.hrec + 4 * (int64_t)e);
+    return w;
+}
+__device__ __forceinline__ void walk_step(const DMesh &m, const uint64_t *__restrict__ key, Walk &w, uint64_t kv,
+                                          int32_t v, bool post) {
+    const int32_t y = w.r.z;
     const uint64_t ky = ldg(key + y);
+    const v4i ra = *(const GLOBAL_AS v4i *)(m.hrec + 4 * (int64_t)w.r.y);
+    const v4i rb = *(const GLOBAL_AS v4i *)(m.hrec + 4 * (int64_t)w.r.x);
     const bool in = rank_lt(ky, y, kv, v) || (post && y == v);
-    return in ? r.y : r.x;
+    w.e = in ? w.r.y : w.r.x;
+    w.src = in ? y : w.src;
+    w.r = in ? ra : rb;
 }
 
 // ---------------------------------------------------------------------------
@@ -1095,7 +1114,7 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
         int nck = 0;
         if (lane < sN) {
             e0 = m.rev[b + sh->srep[lane]];
-            int32_t e = e0;
+            Walk w = walk_at(m, e0);
             do {
                 if ((n & (K - 1)) == 0) {
                     if (nck == WCK) {
@@ -1103,13 +1122,13 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
                         nck = WCK / 2;
                         K *= 2;
                     }
-                    if ((n & (K - 1)) == 0) ck[nck++] = e;
+                    if ((n & (K - 1)) == 0) ck[nck++] = w.e;
                 }
-                const long long key = (long long)m.src[e] * m.nv + m.cyc[e];
+                const long long key = (long long)w.src * m.nv + w.r.w;
                 if (key < best) { best = key; bestidx = n; }
                 n++;
-                e = he_next(m, s.key, e, kv, v, false);
-            } while (e != e0 && n <= m.nnz);
+                walk_step(m, s.key, w, kv, v, false);
+            } while (w.e != e0 && n <= m.nnz);
             if (n > m.nnz) fail(s, ST_INVARIANT, 4);
             sh->lplen[lane] = n;
             sh->lpmin[lane] = bestidx;
@@ -1148,17 +1167,17 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
             const int ncq = sh->lpnck[q];
             const int32_t *ckq = s.wck + (int64_t)q * WCK;
             for (int c = lane; c < ncq; c += WAVE) {
-                int32_t e = ckq[c];
+                Walk w = walk_at(m, ckq[c]);
                 const long long i0 = (long long)c * Kq;
                 const long long i1 = i0 + Kq < nq ? i0 + Kq : nq;
                 for (long long i = i0; i < i1; ++i) {
                     const long long rel = i - bq;
                     const long long pos = off + (rel < 0 ? rel + nq : rel);
-                    const int32_t uu = m.src[e], xx = m.cyc[e];
+                    const int32_t uu = w.src, xx = w.r.w;
                     s.lp_he[2 * pos] = uu;
                     s.lp_he[2 * pos + 1] = xx;
                     crossing_point<CM>(m, rho, uu, xx, p.tau, s.lp_pts + 3 * pos);
-                    e = he_next(m, s.key, e, kv, v, false);
+                    walk_step(m, s.key, w, kv, v, false);
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -1206,7 +1225,10 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
         if (lane < d && !low && (ostartm >> lane & 1ull)) sh->ostart[sh->runid[lane]] = lane;
         __builtin_amdgcn_wave_barrier();
         __threadfence_block();
-        int32_t e = lane < k ? b + sh->oend[lane] : -1;
+        Walk w;
+        w.e = -1;
+        w.src = -1;
+        if (lane < k) w = walk_at(m, b + sh->oend[lane]);
         bool done = lane >= k;
         int steps = 0, tgt = -1;
         // checkpoints of each walker's arc (same scheme as the merge walks),
@@ -1214,12 +1236,12 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
         int32_t *ckw = s.wck + (int64_t)lane * WCK;
         long long K = 1;
         int nck = 0;
-        if (lane < k) ckw[nck++] = e;
+        if (lane < k) ckw[nck++] = w.e;
         for (;;) {
             const unsigned long long act = __ballot(!done) & ((k == 64) ? ~0ull : ((1ull << k) - 1ull));
             if (__popcll(act) <= 1) break;
             if (!done) {
-                e = he_next(m, s.key, e, kv, v, true);
+                walk_step(m, s.key, w, kv, v, true);
                 steps++;
                 if ((steps & (K - 1)) == 0) {
                     if (nck == WCK) {
@@ -1227,9 +1249,9 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
                         nck = WCK / 2;
                         K *= 2;
                     }
-                    if ((steps & (K - 1)) == 0) ckw[nck++] = e;
+                    if ((steps & (K - 1)) == 0) ckw[nck++] = w.e;
                 }
-                if (m.src[e] == v) { done = true; tgt = sh->runid[e - b]; }
+                if (w.src == v) { done = true; tgt = sh->runid[w.e - b]; }
                 if (steps > m.nnz) { fail(s, ST_INVARIANT, 7); done = true; tgt = 0; }
             }
         }
@@ -1327,12 +1349,12 @@ __device__ __forceinline__ void resolve_event(const DMesh &m, const DState &s, c
             const int nco = sh->lpnck[o];
             const int32_t *cko = s.wck + (int64_t)o * WCK;
             for (int c = lane; c < nco; c += WAVE) {
-                int32_t ee = cko[c];
+                Walk w = walk_at(m, cko[c]);
                 const long long i0 = (long long)c * Ko;
                 const long long i1 = i0 + Ko < so ? i0 + Ko : so;
                 for (long long i = i0; i < i1; ++i) {
-                    if (i >= 1) s.lid[ee] = tg;
-                    ee = he_next(m, s.key, ee, kv, v, true);
+                    if (i >= 1) s.lid[w.e] = tg;
+                    walk_step(m, s.key, w, kv, v, true);
                 }
             }
         }
@@ -2774,7 +2796,7 @@ __device__ __forceinline__ void reeb_count_one(const DMesh &m, const DState &s, 
     if (lane < sN && lane < 16) {
         int32_t *cq = ck + (rel * 16 + lane) * RCK;
         const int32_t e0 = m.rev[b + s.ev_rep[16 * (int64_t)ev + lane]];
-        int32_t e = e0;
+        Walk w = walk_at(m, e0);
         long long K = 1;
         int nck = 0;
         do {
@@ -2784,11 +2806,11 @@ __device__ __forceinline__ void reeb_count_one(const DMesh &m, const DState &s, 
                     nck = RCK / 2;
                     K *= 2;
                 }
-                if ((n & (K - 1)) == 0) cq[nck++] = e;
+                if ((n & (K - 1)) == 0) cq[nck++] = w.e;
             }
             n++;
-            e = he_next(m, s.key, e, kv, v, false);
-        } while (e != e0 && n <= m.nnz);
+            walk_step(m, s.key, w, kv, v, false);
+        } while (w.e != e0 && n <= m.nnz);
         int64_t *mq = meta + (rel * 16 + lane) * 4;
         mq[0] = n;
         mq[1] = K;
@@ -2838,17 +2860,15 @@ __device__ __forceinline__ void reeb_fill_one(const DMesh &m, const DState &s, i
         const int64_t *mq = meta + (rel * 16 + q) * 4;
         if (c >= (int)mq[2]) continue;
         const int64_t nq = mq[0], Kq = mq[1], base = mq[3];
-        int32_t e = ck[(rel * 16 + q) * RCK + c];
+        Walk w = walk_at(m, ck[(rel * 16 + q) * RCK + c]);
         const int64_t i0 = (int64_t)c * Kq;
         const int64_t i1 = i0 + Kq < nq ? i0 + Kq : nq;
         for (int64_t i = i0; i < i1; ++i) {
-            const v4i r = *(const GLOBAL_AS v4i *)(m.hrec + 4 * (int64_t)e);
             const int64_t o = 3 * (base + i);
-            out[o] = ldg(m.src + e);
-            out[o + 1] = r.w;
-            out[o + 2] = r.z;
-            const uint64_t ky = ldg(s.key + r.z);
-            e = rank_lt(ky, r.z, kv, v) ? r.y : r.x;
+            out[o] = w.src;
+            out[o + 1] = w.r.w;
+            out[o + 2] = w.r.z;
+            walk_step(m, s.key, w, kv, v, false);
         }
     }
     for (int64_t i = off[rel] + cnt[rel] + threadIdx.x; i < off[rel + 1]; i += blockDim.x) buf[i] = 0x7fffffff;
