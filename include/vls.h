@@ -254,7 +254,7 @@ vls_status vls_result_wait(struct vls_result *r);
  * hipMalloc, hipFree, event or stream creation happens in this call or in
  * the wait; the result and its arrays are host memory.  The mesh (created
  * beforehand) and the result are the caller's inputs and outputs.
- *   - Meshes whose vls_workspace_size exceeds 64 MiB (about 150k vertices)
+ *   - Meshes whose vls_workspace_size exceeds 64 MiB (about 120-150k vertices)
  *     fail with VLS_E_BUFFER_TOO_SMALL.
  *   - Every call on one device shares that device's array: a call made
  *     while an earlier call's result has not been waited for (or
