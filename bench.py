@@ -326,7 +326,7 @@ def batch_leg(ctx, n, seq_sample, tune=False):
     }
 
 
-def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=False):
+def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=False, gang_vertices=0):
     """Serving: Poisson arrivals at ``rate``/s, each request an initial pass
     of a mesh drawn from the uneven batch distribution or, with probability
     ``lattice_share``, from two strut lattices of 2-8M triangles; meshes are
@@ -359,7 +359,7 @@ def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=Fals
     t = srv.submit(M[0], seed_vertex=meshes[0].seed)
     while srv.poll(t) is None:
         time.sleep(0.001)
-    lat_ms, queue_ms, ok = [], [], True
+    lat_ms, queue_ms, lat_of, ok = [], [], [], True
     outstanding = {}
     start = time.perf_counter()
     nxt = 0
@@ -369,6 +369,7 @@ def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=Fals
         while nxt < n_req and arrivals[nxt] <= now:
             i = int(pick[nxt])
             p = vls.default_params(seed_vertex=meshes[i].seed)
+            p.gang_vertices = gang_vertices
             tk = C.c_uint64()
             st = vls.vls_server_submit(srv.h, M[i].h, C.byref(p), C.byref(tk))
             if st != 0:
@@ -386,6 +387,7 @@ def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=Fals
             ok = ok and st == 0 and sm.n_handles == genus[i]
             lat_ms.append(sm.server_latency_ms)
             queue_ms.append(sm.server_queue_ms)
+            lat_of.append(i >= len(pool))
             vls.vls_result_destroy(h)
             last_done = time.perf_counter()
         time.sleep(0.0005)
@@ -413,14 +415,23 @@ def serve_leg(ctx, n_req, rate, lattice_share, slice_us, seed=0, two_per_cu=Fals
         x.close()
     lat_ms = np.array(lat_ms)
     seq_lat = np.array(seq_lat)
+    is_lat = np.array(lat_of, dtype=bool)
+    by_class = {}
+    for name, sel in (("lattice", is_lat), ("pool", ~is_lat)):
+        if sel.any():
+            by_class[name] = {"requests": int(sel.sum()), "p50_ms": float(np.percentile(lat_ms[sel], 50)),
+                              "p99_ms": float(np.percentile(lat_ms[sel], 99)), "max_ms": float(lat_ms[sel].max())}
+    by_class["lattice_solo_service_ms"] = [round(1e3 * service[i], 1) for i in sorted(service) if i >= len(pool)]
     return {
         "requests": int(n_req), "rate_per_s": rate, "lattice_share": lattice_share,
         "lattice_requests": int((pick >= len(pool)).sum()), "slice_us": slice_us,
+        "gang_vertices": int(gang_vertices) if gang_vertices > 0 else 65536,
         "all_handles_equal_genus": bool(ok),
         "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
         "mean_ms": float(lat_ms.mean()), "mean_queue_ms": float(np.mean(queue_ms)),
         "meshes_per_s": n_req / makespan, "makespan_s": makespan, "launches": stats["launches"],
         "scheduler_ms": {k: round(stats[k], 1) for k in ("admit_ms", "launch_ms", "complete_ms")},
+        "by_class": by_class,
         "sequential": {"p50_ms": float(np.percentile(seq_lat, 50)), "p99_ms": float(np.percentile(seq_lat, 99)),
                        "meshes_per_s": n_req / (free_at - 0.0) if free_at > 0 else None,
                        "service_ms_mean": 1e3 * float(np.mean([service[int(i)] for i in pick]))},
@@ -551,6 +562,8 @@ def main():
     ap.add_argument("--serve-lattice-share", type=float, default=0.05)
     ap.add_argument("--serve-slice-us", type=int, default=20000)
     ap.add_argument("--serve-two-per-cu", action="store_true", help="server step launches at two workgroups per CU")
+    ap.add_argument("--serve-gang-vertices", type=int, default=0,
+                    help="vertices per gang workgroup of a served request (0: the library's 65536)")
     ap.add_argument("--dense-workload", default="same",
                     help="mesh of the dense-step leg ('same': the main workload's mesh; 'none': skip)")
     ap.add_argument("--dense-steps", type=int, default=200)
@@ -711,7 +724,8 @@ def main():
     if args.serve > 0:
         if left() > 80:
             out["serving"] = serve_leg(ctx, args.serve, args.serve_rate, args.serve_lattice_share,
-                                       args.serve_slice_us, two_per_cu=args.serve_two_per_cu)
+                                       args.serve_slice_us, two_per_cu=args.serve_two_per_cu,
+                                       gang_vertices=args.serve_gang_vertices)
             out["serving"]["workgroups_per_cu"] = 2 if args.serve_two_per_cu else 1
             log(f"serving leg done ({time.time() - t_start:.0f}s since start)")
         else:

@@ -124,9 +124,9 @@ typedef struct vls_params {
                                   one per 34k vertices, 16..128, at most what is co-resident;
                                   vls_batch_run: pool size of per_mesh[0]                 */
     int32_t block;             /* threads per workgroup: 256 (0 = default)                */
-    int64_t gang_vertices;     /* vls_batch_run / server (per_mesh[0] for a batch): a mesh
-                                  gets one workgroup per this many vertices (at least 2 to
-                                  form a gang, at most 64); 0 = 65536                     */
+    int64_t gang_vertices;     /* vls_batch_run (per_mesh[0], for every mesh) and each server
+                                  request (its own): a mesh gets one workgroup per this many
+                                  vertices (at least 2 to form a gang, at most 64); 0 = 65536 */
     int32_t pass_slots;        /* tunnel-loop / refinement passes run at once (each on one
                                   workgroup with its own per-vertex state, about 100 B per
                                   vertex); 0 = as many as co-resident workgroups and half of

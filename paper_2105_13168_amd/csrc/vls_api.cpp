@@ -1323,7 +1323,8 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
 }
 
 // Launch plan of the batched kernel.  Tasks (meshes) run largest first; a
-// mesh of nv vertices wants a gang of nv / kGangVerts workgroups (at most
+// mesh of nv vertices wants a gang of nv / gv workgroups (gv its gang
+// granularity, kGangVerts when 0; at most
 // kGangMax, and at least 2 to be a gang).  Gangs are granted in task order
 // (largest first, the longest runs) while they fit in three quarters of the
 // pool; a task whose full gang no longer fits gets what is left if that is
@@ -1341,8 +1342,7 @@ struct BatchPlan {
     int nslots = 0, grid = 0;
 };
 
-void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp, int64_t gang_verts = kGangVerts) {
-    if (gang_verts <= 0) gang_verts = kGangVerts;
+void plan_batch(const std::vector<int64_t> &nv, const std::vector<int64_t> &gv, int pool, BatchPlan &bp) {
     const int n = (int)nv.size();
     bp.order.resize(n);
     for (int i = 0; i < n; ++i) bp.order[i] = i;
@@ -1350,7 +1350,8 @@ void plan_batch(const std::vector<int64_t> &nv, int pool, BatchPlan &bp, int64_t
     bp.task_g.assign(n, 1);
     int64_t left = (int64_t)pool * 3 / 4;
     for (int w = 0; w < n; ++w) {
-        const int64_t want = std::min<int64_t>(kGangMax, nv[bp.order[w]] / gang_verts);
+        const int64_t gw = gv[bp.order[w]] > 0 ? gv[bp.order[w]] : kGangVerts;
+        const int64_t want = std::min<int64_t>(kGangMax, nv[bp.order[w]] / gw);
         const int64_t g = std::min(want, left);
         if (g >= 2) { bp.task_g[w] = (int32_t)g; left -= g; }
     }
@@ -1584,7 +1585,7 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
     std::vector<int64_t> nvs(n);
     for (int32_t i = 0; i < n; ++i) nvs[i] = meshes[i]->nv;
     BatchPlan bp;
-    plan_batch(nvs, pool, bp, per_mesh[0].gang_vertices);
+    plan_batch(nvs, std::vector<int64_t>(n, per_mesh[0].gang_vertices), pool, bp);
     const int grid = bp.grid;
     void *dm = nullptr, *ds = nullptr, *dpp = nullptr, *dord = nullptr, *dnext = nullptr, *dtg = nullptr,
          *dsl = nullptr;
@@ -1904,7 +1905,6 @@ struct vls_server {
     int max_slots = 0;
     int occ = 1;                     // workgroups per CU of the step launches
     int cm = 0;                      // 1: gangs share through coherent atomics
-    int64_t gang_verts = 0;          // vertices per gang workgroup (0 = default)
     unsigned long long slice_ticks = 0;
     std::mutex mu;
     std::condition_variable cv;
@@ -2132,19 +2132,20 @@ bool vls_server::launch_slice() {
     std::vector<DMesh> hm(n);
     std::vector<DState> hs(n);
     std::vector<DParams> hp(n);
-    std::vector<int64_t> nvs(n);
+    std::vector<int64_t> nvs(n), gvs(n);
     size_t lds = 0;
     for (int i = 0; i < n; ++i) {
         hm[i] = active[i]->m->d;
         hs[i] = active[i]->prep->s;
         hp[i] = active[i]->prep->dp;
         nvs[i] = active[i]->m->nv;
+        gvs[i] = active[i]->p.gang_vertices;
     }
     lds = batch_lds_bytes(occ);
     const int maxg = max_coresident_batch(lds, occ);
     if (maxg <= 0) return false;
     BatchPlan bp;
-    plan_batch(nvs, maxg, bp, gang_verts);
+    plan_batch(nvs, gvs, maxg, bp);
     if (bp.nslots > cap + 4096) return false;      // slot buffer holds cap + 4096 slots
     const std::vector<int32_t> &order = bp.order;
     hipStream_t st = ctx.stream;

@@ -192,6 +192,40 @@ def test_server_gangs_resize_and_switch(oracle_mod, two_per_cu):
         ctx.close()
 
 
+def test_server_request_gang_granularity(oracle_mod):
+    """Each request's own gang_vertices sets its gang: the same meshes
+    submitted at 2048, 8192 and the default 65536 vertices per gang
+    workgroup (gangs of up to a few dozen workgroups, and one workgroup) in
+    one mix give results equal to each other and to the oracle's."""
+    import paper_2105_13168_amd as vls
+    ctx = vls.Context(0)
+    ms = [mg.torus_grid(96, 48, rng_seed=7), mg.multi_torus(4, 40, rng_seed=4), mg.pretzel(40, rng_seed=5)]
+    M = [vls.Mesh(ctx, m.xyz, m.tri) for m in ms]
+    srv = vls.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=64, slice_us=300)
+    try:
+        reqs = []
+        for gv in (2048, 8192, 0):
+            for i, (m, h) in enumerate(zip(ms, M)):
+                assert m.nv // 2048 >= 2
+                reqs.append((i, srv.submit(h, seed_vertex=m.seed, gang_vertices=gv)))
+        res = _wait(srv, [t for _, t in reqs])
+        first = {}
+        for (i, _), r in zip(reqs, res):
+            if i not in first:
+                m = ms[i]
+                o = oracle_mod.run(m.xyz, m.tri, seed_vertex=m.seed)
+                bad = compare(r, o, m.nv)
+                assert not bad, (m.name, bad)
+                first[i] = r
+            else:
+                _same(r, first[i])
+    finally:
+        srv.close()
+        for x in M:
+            x.close()
+        ctx.close()
+
+
 def test_server_stalled_request_in_the_mix(oracle_mod):
     """A request that stops at its step limit returns VLS_E_STALLED with the
     partial results the oracle gives for the same limit, including the field
