@@ -1324,14 +1324,18 @@ static vls_status finish_run(vls_context *ctx, RunPrep &rp, const vls_params *p,
 
 // Launch plan of the batched kernel.  Tasks (meshes) run largest first; a
 // mesh of nv vertices wants a gang of nv / gv workgroups (gv its gang
-// granularity, kGangVerts when 0; at most
-// kGangMax, and at least 2 to be a gang).  Gangs are granted in task order
-// (largest first, the longest runs) while they fit in three quarters of the
-// pool; a task whose full gang no longer fits gets what is left if that is
-// at least 2, else one workgroup.  So all gangs run at once, and the tail of
-// the launch is not set by a large mesh on one workgroup.  The slot list
-// holds every gang member first (rank 0 first), then the one-workgroup
-// tasks.
+// granularity, kGangVerts when 0; at most kGangMax, and at least 2 to be a
+// gang).  Gangs are granted in task order (largest first, the longest runs)
+// while they fit in the pool less a reserve for the tasks too small for a
+// gang (a quarter of the pool, or one workgroup each when there are fewer
+// of them); a task whose full gang no longer fits gets what is left if that
+// is at least 2.  Otherwise it runs on one workgroup, or, with defer (a
+// launch that a later one continues) once some gang is granted, it sits the
+// launch out (task_g 0): a mesh that wants a gang advances too slowly on one
+// workgroup to repay the L2 its band takes from the others.  So all gangs
+// run at once, and the tail of the launch is not set by a large mesh on one
+// workgroup.  The slot list holds every gang member first (rank 0 first),
+// then the one-workgroup tasks.
 namespace {
 constexpr int64_t kGangVerts = 65536;
 constexpr int kGangMax = 64;
@@ -1342,25 +1346,36 @@ struct BatchPlan {
     int nslots = 0, grid = 0;
 };
 
-void plan_batch(const std::vector<int64_t> &nv, const std::vector<int64_t> &gv, int pool, BatchPlan &bp) {
+void plan_batch(const std::vector<int64_t> &nv, const std::vector<int64_t> &gv, int pool, BatchPlan &bp,
+                bool defer = false) {
     const int n = (int)nv.size();
     bp.order.resize(n);
     for (int i = 0; i < n; ++i) bp.order[i] = i;
     std::stable_sort(bp.order.begin(), bp.order.end(), [&](int32_t a, int32_t b) { return nv[a] > nv[b]; });
     bp.task_g.assign(n, 1);
-    int64_t left = (int64_t)pool * 3 / 4;
+    std::vector<int64_t> want(n);
+    int64_t small = 0;
     for (int w = 0; w < n; ++w) {
         const int64_t gw = gv[bp.order[w]] > 0 ? gv[bp.order[w]] : kGangVerts;
-        const int64_t want = std::min<int64_t>(kGangMax, nv[bp.order[w]] / gw);
-        const int64_t g = std::min(want, left);
-        if (g >= 2) { bp.task_g[w] = (int32_t)g; left -= g; }
+        want[w] = std::min<int64_t>(kGangMax, nv[bp.order[w]] / gw);
+        small += want[w] < 2;
     }
+    int64_t left = (int64_t)pool - std::min<int64_t>(small, pool / 4);
+    bool granted = false;
+    for (int w = 0; w < n; ++w) {
+        if (want[w] < 2) continue;
+        const int64_t g = std::min(want[w], left);
+        if (g >= 2) { bp.task_g[w] = (int32_t)g; left -= g; granted = true; }
+    }
+    if (defer && granted)
+        for (int w = 0; w < n; ++w)
+            if (want[w] >= 2 && bp.task_g[w] < 2) bp.task_g[w] = 0;
     bp.slots.clear();
     for (int w = 0; w < n; ++w)
         if (bp.task_g[w] >= 2)
             for (int r = 0; r < bp.task_g[w]; ++r) { bp.slots.push_back(w); bp.slots.push_back(r); }
     for (int w = 0; w < n; ++w)
-        if (bp.task_g[w] < 2) { bp.slots.push_back(w); bp.slots.push_back(0); }
+        if (bp.task_g[w] == 1) { bp.slots.push_back(w); bp.slots.push_back(0); }
     bp.nslots = (int)(bp.slots.size() / 2);
     bp.grid = std::max(1, std::min(pool, bp.nslots));
 }
@@ -2145,7 +2160,7 @@ bool vls_server::launch_slice() {
     const int maxg = max_coresident_batch(lds, occ);
     if (maxg <= 0) return false;
     BatchPlan bp;
-    plan_batch(nvs, gvs, maxg, bp);
+    plan_batch(nvs, gvs, maxg, bp, true);
     if (bp.nslots > cap + 4096) return false;      // slot buffer holds cap + 4096 slots
     const std::vector<int32_t> &order = bp.order;
     hipStream_t st = ctx.stream;
@@ -2172,7 +2187,7 @@ bool vls_server::launch_slice() {
     std::vector<SrvReq *> still;
     std::vector<SrvReq *> fin;
     std::vector<int32_t> flag(n, 0);
-    for (int w = 0; w < n; ++w) flag[order[w]] = hdone[w];
+    for (int w = 0; w < n; ++w) flag[order[w]] = bp.task_g[w] > 0 && hdone[w];   // task_g 0: not visited
     for (int i = 0; i < n; ++i) (flag[i] ? fin : still).push_back(active[i]);
     active.swap(still);
     for (SrvReq *q : fin) {

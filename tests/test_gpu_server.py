@@ -159,11 +159,11 @@ def test_server_destroy_with_work_in_flight():
 @pytest.mark.parametrize("two_per_cu", [False, True])
 def test_server_gangs_resize_and_switch(oracle_mod, two_per_cu):
     """Many large requests at once: the planner grants meshes of >= 2^17
-    vertices gangs of workgroups, largest first, within three quarters of
-    the pool (256 or 512 workgroups at one or two per CU); the requests that
-    no longer fit run on one workgroup.  As requests finish the rest are
-    re-planned, so a request's visits switch from one workgroup to a gang.
-    Every result equals the oracle's."""
+    vertices gangs of workgroups, largest first, within the pool less the
+    reserve for small meshes (256 or 512 workgroups at one or two per CU);
+    the requests that no longer fit sit the launch out.  As requests finish
+    the rest are re-planned, so a request waits, then runs in gangs of
+    changing sizes.  Every result equals the oracle's."""
     import paper_2105_13168_amd as vls
     ctx = vls.Context(0)
     big = [mg.pretzel(72, rng_seed=s) for s in (0, 1)] + [mg.pretzel(96, rng_seed=2), mg.lattice(3, 96, rng_seed=3)]
