@@ -48,7 +48,8 @@ class _Params(C.Structure):
                 ("seed_radius", C.c_int32), ("seed_vertex", C.c_int64),
                 ("max_steps", C.c_int64), ("stall_steps", C.c_int64),
                 ("dense", C.c_int32), ("n_ckpt", C.c_int32),
-                ("ckpt_steps", C.POINTER(C.c_int64)), ("fem", C.c_int32)]
+                ("ckpt_steps", C.POINTER(C.c_int64)), ("fem", C.c_int32),
+                ("n_seed_set", C.c_int64), ("seed_set", C.POINTER(C.c_int32))]
 
 
 _lib = None
@@ -166,7 +167,7 @@ class OracleResult:
 def default_params(**kw):
     p = dict(tau=0.5, mu=0.25, a=1.0 / 25.0, w=(1.0 / 25.0) / 5.0, e=1.0 / 30.0,
              dt_mode=0, seed_radius=2, seed_vertex=0, max_steps=10_000_000,
-             stall_steps=200_000, dense=0, ckpt_steps=(), fem=0)
+             stall_steps=200_000, dense=0, ckpt_steps=(), fem=0, seed_set=())
     p.update(kw)
     return p
 
@@ -177,10 +178,12 @@ def run(xyz, tri, **kw) -> OracleResult:
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     tri = np.ascontiguousarray(tri, dtype=np.int32)
     ck = np.ascontiguousarray(np.asarray(p["ckpt_steps"], dtype=np.int64).reshape(-1))
+    ss = np.ascontiguousarray(np.asarray(p["seed_set"], dtype=np.int32).reshape(-1))
     cp = _Params(p["tau"], p["mu"], p["a"], p["w"], p["e"], int(p["dt_mode"]),
                  int(p["seed_radius"]), int(p["seed_vertex"]), int(p["max_steps"]),
                  int(p["stall_steps"]), int(p["dense"]), int(ck.size),
-                 ck.ctypes.data_as(C.POINTER(C.c_int64)) if ck.size else None, int(p["fem"]))
+                 ck.ctypes.data_as(C.POINTER(C.c_int64)) if ck.size else None, int(p["fem"]),
+                 int(ss.size), ss.ctypes.data_as(C.POINTER(C.c_int32)) if ss.size else None)
     h = lib.orc_run(xyz.shape[0], xyz.ctypes.data, tri.shape[0], tri.ctypes.data, C.byref(cp))
     if not h:
         raise MemoryError("oracle allocation failed")
@@ -293,3 +296,32 @@ def field_step_numpy(rho, ell, deg, dmax_mesh, dt_mode=0, a=1.0 / 25.0,
     d = (a * lap + w * (2.0 * r - 1.0)) + e * np.sqrt(r * (1.0 - r))
     x = r + c * d
     return np.minimum(np.maximum(x, 0.0), 1.0)
+
+
+def refinement_seed_set(result) -> np.ndarray:
+    """The seed set of the Reeb refinement pass: the inside endpoints of the
+    first kept handle loop's crossed edges, ascending (empty without one)."""
+    loops = result.handle_loops()
+    if not loops:
+        return np.zeros(0, dtype=np.int32)
+    return np.unique(np.asarray(loops[0][2])[:, 0]).astype(np.int32)
+
+
+def reeb_refined(xyz, tri, **kw):
+    """Reeb junction refinement (Section "Reeb Graph Extraction": the second
+    pass relocates the junctions).  Reading: the initial pass is run again
+    from the first kept handle loop instead of a random point (the diffusion
+    initiated at a detected handle loop, Section "Introduction"): its
+    initial region is every vertex within seed_radius hops of the loop's
+    inside vertices, ranked by hop distance inside that region from its
+    smallest vertex.  The refined Reeb graph is that pass's graph, junctions
+    at its band means.  Returns (first pass, second pass or None)."""
+    first = run(xyz, tri, **kw)
+    ss = refinement_seed_set(first) if first.status == 0 else np.zeros(0, dtype=np.int32)
+    if ss.size == 0:
+        return first, None
+    kw2 = dict(kw)
+    kw2["seed_set"] = ss
+    kw2["seed_vertex"] = int(ss[0])
+    return first, run(xyz, tri, **kw2)
+

@@ -75,6 +75,8 @@ typedef struct {
     int32_t n_ckpt;
     const int64_t *ckpt_steps;
     int32_t fem;          /* 1: cotangent finite-element operator           */
+    int64_t n_seed_set;   /* > 0: the initial region grows from this set    */
+    const int32_t *seed_set;
 } orc_params;
 
 /* growable arrays */
@@ -694,16 +696,24 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
-/* seed: hop ball of radius r0 around the seed vertex                        */
+/* seed: hop ball of radius r0 around the seed vertex; or, from a seed set   */
+/* S (the Reeb refinement's second pass starts at a handle loop), the        */
+/* vertices within r0 hops of S, ranked by their hop distance inside that    */
+/* region from s = min S.  S = {s} gives the ball.                           */
 /* ------------------------------------------------------------------------ */
-static int seed_init(orc *o, int64_t s, int32_t r0) {
+static int seed_init(orc *o, int64_t s, int32_t r0, const int32_t *set, int64_t nset) {
     int64_t nv = o->nv;
     int32_t *hop = (int32_t *)malloc((size_t)nv * sizeof(int32_t));
     int32_t *q = (int32_t *)malloc((size_t)nv * sizeof(int32_t));
     if (!hop || !q) { free(hop); free(q); return ORC_E_OUT_OF_MEMORY; }
     for (int64_t v = 0; v < nv; ++v) hop[v] = -1;
     int64_t qh = 0, qt = 0;
-    q[qt++] = (int32_t)s; hop[s] = 0;
+    if (nset > 0) {
+        for (int64_t i = 0; i < nset; ++i)
+            if (hop[set[i]] < 0) { hop[set[i]] = 0; q[qt++] = set[i]; }
+    } else {
+        q[qt++] = (int32_t)s; hop[s] = 0;
+    }
     while (qh < qt) {
         int32_t v = q[qh++];
         if (hop[v] >= r0) continue;
@@ -711,6 +721,26 @@ static int seed_init(orc *o, int64_t s, int32_t r0) {
             int32_t u = o->adj[i];
             if (hop[u] < 0) { hop[u] = hop[v] + 1; q[qt++] = u; }
         }
+    }
+    if (nset > 0) {
+        /* re-rank the region by hop distance from s inside it: q becomes
+           that breadth-first order, hop that distance */
+        int32_t *d = (int32_t *)malloc((size_t)nv * sizeof(int32_t));
+        if (!d) { free(hop); free(q); return ORC_E_OUT_OF_MEMORY; }
+        for (int64_t v = 0; v < nv; ++v) d[v] = hop[v] >= 0 ? -1 : -2;
+        int64_t n_region = qt;
+        qh = 0; qt = 0;
+        q[qt++] = (int32_t)s; d[s] = 0;
+        while (qh < qt) {
+            int32_t v = q[qh++];
+            for (int64_t i = o->rp[v]; i < o->rp[v + 1]; ++i) {
+                int32_t u = o->adj[i];
+                if (d[u] == -1) { d[u] = d[v] + 1; q[qt++] = u; }
+            }
+        }
+        for (int64_t v = 0; v < nv; ++v) hop[v] = d[v];
+        free(d);
+        if (qt != n_region) { free(hop); free(q); return ORC_E_SEED_INVALID; }
     }
     for (int64_t i = 0; i < qt; ++i) {
         int32_t v = q[i];
@@ -828,8 +858,20 @@ static int run(orc *o, const orc_params *p) {
     for (int64_t v = 0; v < nv; ++v) { o->T[v] = T_OUT; o->parent[v] = -1; mark[v] = -1; cmark[v] = -1; }
     for (int64_t i = 0; i < o->nnz; ++i) o->lid[i] = -1;
     int rc;
-    if (p->seed_vertex < 0 || p->seed_vertex >= nv || p->seed_radius < 0) { rc = ORC_E_INVALID_ARG; goto out; }
-    rc = seed_init(o, p->seed_vertex, p->seed_radius);
+    if (p->seed_vertex < 0 || p->seed_vertex >= nv || p->seed_radius < 0 || p->n_seed_set < 0) {
+        rc = ORC_E_INVALID_ARG; goto out;
+    }
+    if (p->n_seed_set > 0) {
+        /* the region's root is the smallest vertex of the set */
+        int64_t mn = nv;
+        for (int64_t i = 0; i < p->n_seed_set; ++i) {
+            if (p->seed_set[i] < 0 || p->seed_set[i] >= nv) { rc = ORC_E_INVALID_ARG; goto out; }
+            if (p->seed_set[i] < mn) mn = p->seed_set[i];
+        }
+        rc = seed_init(o, mn, p->seed_radius, p->seed_set, p->n_seed_set);
+    } else {
+        rc = seed_init(o, p->seed_vertex, p->seed_radius, NULL, 0);
+    }
     if (rc) goto out;
     if (o->n_inside == nv) { o->steps = 0; goto out; }
     /* initial update set: everything within one hop of a non-quiescent vertex */
