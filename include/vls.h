@@ -95,6 +95,17 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
                                     0.25) over its largest absolute row sum; see vls_mesh_prepare_fem.
                                     Not with VLS_DENSE_FIELD, the passes, vls_batch_run or the server
                                     (VLS_E_INVALID_ARG) */
+#define VLS_REEB_REFINE 1024u    /* vls_run only: Reeb junction refinement (Section "Reeb Graph
+                                    Extraction": a second pass improves where the junctions sit;
+                                    Section "Introduction": a Reeb graph from a diffusion initiated at
+                                    a detected handle loop).  When the pass ends with a handle loop,
+                                    the initial pass runs again from the first kept one: its initial
+                                    region is every vertex within seed_radius hops of the loop's inside
+                                    vertices, ranked by hop distance inside that region from the
+                                    smallest of them.  That second result (its Reeb graph has the
+                                    refined junctions at its band means) is read with
+                                    vls_result_refined.  The passes, field checkpoints and deferral of
+                                    the first result do not apply to it */
 #define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]) and the server (creation
                                     flags): two workgroups per CU, each with a 1024-candidate LDS
                                     topology path and one list entry per field thread; default: one
@@ -455,6 +466,10 @@ vls_status vls_server_destroy(struct vls_server *srv);
    device state at a time.  A deferred result must be fetched or destroyed
    before its context is destroyed. */
 vls_status vls_result_fetch(struct vls_result *r);
+/* The second pass of VLS_REEB_REFINE (Section "Reeb Graph Extraction"): *second is a result owned by
+   r (read it with the accessors above; destroyed with r, never by the caller), or NULL when the flag
+   was not given or the pass found no handle loop. */
+vls_status vls_result_refined(const struct vls_result *r, const struct vls_result **second);
 /* Frees a result; a deferred result that was never fetched is discarded
    without copying it. */
 vls_status vls_result_destroy(struct vls_result *r);

@@ -38,6 +38,7 @@ VLS_DENSE_FIELD = 64
 VLS_TUNNEL_PASS = 128
 VLS_REFINE_PASS = 256
 VLS_FEM_LAPLACIAN = 512
+VLS_REEB_REFINE = 1024
 NODE_SEED, NODE_SPLIT, NODE_MERGE, NODE_VANISH, NODE_DEGENERATE = range(5)
 
 
@@ -128,6 +129,7 @@ _sig = {
     "vls_result_field": (C.c_int32, [_P, C.c_int64, _P]),
     "vls_result_vertices": (C.c_int32, [_P, _P, _P, _P]),
     "vls_result_fetch": (C.c_int32, [_P]),
+    "vls_result_refined": (C.c_int32, [_P, C.POINTER(C.c_void_p)]),
     "vls_result_destroy": (C.c_int32, [_P]),
     "vls_server_create": (C.c_int32, [_P, C.c_size_t, C.c_int32, C.c_int64, C.c_uint32, _PP]),
     "vls_server_submit": (C.c_int32, [_P, _P, C.POINTER(vls_params), C.POINTER(C.c_uint64)]),
@@ -261,7 +263,7 @@ class Mesh:
 class Result:
     """Host copies of a run's outputs as numpy arrays."""
 
-    def __init__(self, h, mesh: Mesh, ckpt_steps):
+    def __init__(self, h, mesh: Mesh, ckpt_steps, own: bool = True):
         self.h = h
         self.mesh = mesh
         s = vls_summary()
@@ -339,7 +341,13 @@ class Result:
         self.reeb_nodes = [(n.type, n.vertex, n.step, n.in_deg, n.out_deg, n.extra_cycles,
                             n.xyz[0], n.xyz[1], n.xyz[2]) for n in nodes[:nn.value]]
         self.reeb_edges = [(e.src, e.dst, e.front_id) for e in edges[:ne.value]]
-        vls_result_destroy(h)
+        # the Reeb refinement's second pass (VLS_REEB_REFINE), owned by h
+        h2 = C.c_void_p()
+        self.refined = None
+        if vls_result_refined(h, C.byref(h2)) == VLS_OK and h2.value:
+            self.refined = Result(h2, mesh, np.zeros(0, dtype=np.int64), own=False)
+        if own:
+            vls_result_destroy(h)
         self.h = None
 
     def handle_loops(self):

@@ -99,6 +99,7 @@ struct vls_result {
     std::vector<PassResult> pres[2];
     std::vector<int32_t> pout[2];
     std::vector<double> pass_xyz;        // mesh positions, kept when the passes ran
+    vls_result *refined = nullptr;       // VLS_REEB_REFINE: the pass from the first handle loop (owned)
 };
 
 static vls_status set_err(vls_context *ctx, vls_status s, const char *fmt, ...) {
@@ -729,7 +730,8 @@ struct RunPrep {
 // run state, checkpoints and post-pass scratch are carved from (no
 // allocation, no events).
 static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p, RunPrep &rp,
-                              RunBuffers *priv = nullptr, DevArena *ws = nullptr) {
+                              RunBuffers *priv = nullptr, DevArena *ws = nullptr,
+                              const int32_t *d_seed_set = nullptr, int32_t n_seed_set = 0) {
     if (p->struct_size != sizeof(vls_params)) return set_err(ctx, VLS_E_INVALID_ARG, "vls_params.struct_size mismatch");
     if (!priv && !ws && m->pending) {
         vls_status fs = fetch_results(m->pending);
@@ -746,8 +748,9 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     if ((p->flags & VLS_DENSE_FIELD) && nv >= (int64_t)1 << 29)
         return set_err(ctx, VLS_E_INVALID_ARG, "VLS_DENSE_FIELD needs fewer than 2^29 vertices");
     if (p->n_ckpt < 0 || p->pass_slots < 0) return set_err(ctx, VLS_E_INVALID_ARG, "n_ckpt / pass_slots");
-    if ((p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS)) && (priv || ws))
-        return set_err(ctx, VLS_E_INVALID_ARG, "the tunnel-loop and refinement passes run with vls_run only");
+    if ((p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS | VLS_REEB_REFINE)) && (priv || ws))
+        return set_err(ctx, VLS_E_INVALID_ARG,
+                       "the tunnel-loop, refinement and Reeb refinement passes run with vls_run only");
     const bool fem = (p->flags & VLS_FEM_LAPLACIAN) != 0;
     if (fem) {
         if (p->flags & (VLS_DENSE_FIELD | VLS_TUNNEL_PASS | VLS_REFINE_PASS))
@@ -822,6 +825,8 @@ static vls_status prepare_run(vls_context *ctx, vls_mesh *m, const vls_params *p
     dp.lockstep = (p->flags & VLS_LOCKSTEP) ? 1 : 0;
     dp.dense = (p->flags & VLS_DENSE_FIELD) ? 1 : 0;
     dp.fem = fem ? 1 : 0;
+    dp.n_seed_set = n_seed_set;
+    dp.seed_set = d_seed_set;
     if (!ws) {
         HIPCHK(ctx, hipEventCreate(&rp.e0));
         HIPCHK(ctx, hipEventCreate(&rp.e1));
@@ -1383,6 +1388,57 @@ void plan_batch(const std::vector<int64_t> &nv, const std::vector<int64_t> &gv, 
 
 extern "C" {
 
+// Reeb junction refinement (Section "Reeb Graph Extraction": a second pass
+// improves where the junctions sit; Section "Introduction": a Reeb graph from
+// a diffusion initiated at a detected handle loop).  The initial pass runs
+// again from the first kept handle loop of r: its initial region is every
+// vertex within seed_radius hops of the loop's inside vertices, ranked by hop
+// distance inside that region from the smallest of them.  That pass's result
+// (events, Reeb graph with band-mean junctions, loops) is kept in r->refined;
+// nothing is run when r has no handle loop.
+static int solo_grid(const vls_mesh *m, const vls_params *p);
+static vls_status reeb_refine(vls_context *ctx, vls_mesh *m, const vls_params *p, vls_result &r) {
+    if (vls_status fs = ensure(&r)) return fs;
+    const int64_t nl = (int64_t)r.lp.size() / 8;
+    std::vector<int32_t> set;
+    for (int64_t q = 0; q < nl; ++q) {
+        if (!r.lp[8 * q + 2]) continue;
+        const int64_t off = r.lp[8 * q + 3], n = r.lp[8 * q + 4];
+        for (int64_t k = 0; k < n; ++k) set.push_back(r.lp_he[2 * (off + k)]);
+        break;
+    }
+    if (set.empty()) return VLS_OK;
+    std::sort(set.begin(), set.end());
+    set.erase(std::unique(set.begin(), set.end()), set.end());
+    vls_params p2 = *p;
+    p2.flags &= ~(VLS_REEB_REFINE | VLS_TUNNEL_PASS | VLS_REFINE_PASS | VLS_RECORD_FIELD | VLS_DEFER_RESULTS);
+    p2.n_ckpt = 0;
+    p2.ckpt_steps = nullptr;
+    p2.seed_vertex = set[0];
+    int32_t *d_set = nullptr;
+    HIPCHK(ctx, hipMalloc(&d_set, set.size() * sizeof(int32_t)));
+    struct Free { int32_t *q; ~Free() { if (q) (void)hipFree(q); } } guard{d_set};
+    HIPCHK(ctx, hipMemcpy(d_set, set.data(), set.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    RunPrep rp;
+    vls_status st = prepare_run(ctx, m, &p2, rp, nullptr, nullptr, d_set, (int32_t)set.size());
+    if (st) return st;
+    const int grid = solo_grid(m, &p2);
+    if (grid <= 0) return set_err(ctx, VLS_E_DEVICE, "occupancy query failed");
+    hipError_t le = launch_steps(m->d, rp.s, rp.dp, grid, 256, ctx->stream);
+    if (le != hipSuccess) return set_err(ctx, VLS_E_DEVICE, "step kernel launch: %s", hipGetErrorString(le));
+    HIPCHK(ctx, hipEventRecord(rp.e2, ctx->stream));
+    auto r2 = std::make_unique<vls_result>();
+    vls_status rs = finish_run(ctx, rp, &p2, grid, 256, -1.0, *r2);
+    if (rs != VLS_OK && !is_run_status(rs)) {
+        if (m->pending == r2.get()) m->pending = nullptr;
+        return rs;
+    }
+    if (vls_status fs = ensure(r2.get())) return fs;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    r.refined = r2.release();
+    return VLS_OK;
+}
+
 // launch shape of a one-mesh run: p->grid if set, else about one workgroup
 // per 34k vertices, 16..128.  The field's share of a step grows with the
 // band, but every field workgroup also loads the memory system the
@@ -1418,6 +1474,14 @@ vls_status vls_run(vls_context *ctx, const vls_mesh *mc, const vls_params *p, vl
     if (rs != VLS_OK && !is_run_status(rs)) {
         if (m->pending == r.get()) m->pending = nullptr;
         return rs;
+    }
+    if (rs == VLS_OK && (p->flags & VLS_REEB_REFINE)) {
+        vls_status fs = reeb_refine(ctx, m, p, *r);
+        if (fs) {
+            if (m->pending == r.get()) m->pending = nullptr;
+            (void)vls_result_destroy(r.release());
+            return fs;
+        }
     }
     *out = r.release();
     return rs;
@@ -1572,8 +1636,9 @@ vls_status vls_batch_run(vls_context *ctx, int32_t n, const vls_mesh *const *mes
             if (meshes[j] == meshes[i]) return set_err(ctx, VLS_E_INVALID_ARG, "mesh %d appears twice in the batch", i);
     }
     for (int32_t i = 0; i < n; ++i) {
-        if (per_mesh[i].flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS))
-            return set_err(ctx, VLS_E_INVALID_ARG, "the tunnel-loop and refinement passes run with vls_run only");
+        if (per_mesh[i].flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS | VLS_REEB_REFINE))
+            return set_err(ctx, VLS_E_INVALID_ARG,
+                           "the tunnel-loop, refinement and Reeb refinement passes run with vls_run only");
         if (per_mesh[i].flags & VLS_FEM_LAPLACIAN)
             return set_err(ctx, VLS_E_INVALID_ARG, "VLS_FEM_LAPLACIAN runs with vls_run and the workspace calls only");
     }
@@ -1863,8 +1928,18 @@ vls_status vls_result_fetch(vls_result *r) {
     return fetch_results(r);
 }
 
+vls_status vls_result_refined(const vls_result *r, const vls_result **second) {
+    if (!r || !second) return VLS_E_INVALID_ARG;
+    *second = r->refined;
+    return VLS_OK;
+}
+
 vls_status vls_result_destroy(vls_result *r) {
     if (!r) return VLS_E_INVALID_ARG;
+    if (r->refined) {
+        (void)vls_result_destroy(r->refined);
+        r->refined = nullptr;
+    }
     if (r->launched) {
         // enqueued and never waited for: let the device work end first (it
         // uses the caller's workspace)
@@ -2287,7 +2362,7 @@ vls_status vls_server_create(vls_context *ctx, size_t hbm_budget_bytes, int32_t 
 vls_status vls_server_submit(vls_server *srv, const vls_mesh *m, const vls_params *p, uint64_t *ticket) {
     if (!srv || !m || !p || !ticket) return VLS_E_INVALID_ARG;
     if (p->struct_size != sizeof(vls_params)) return VLS_E_INVALID_ARG;
-    if (p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS | VLS_FEM_LAPLACIAN)) return VLS_E_INVALID_ARG;
+    if (p->flags & (VLS_TUNNEL_PASS | VLS_REFINE_PASS | VLS_REEB_REFINE | VLS_FEM_LAPLACIAN)) return VLS_E_INVALID_ARG;
     auto q = std::make_unique<SrvReq>();
     q->m = const_cast<vls_mesh *>(m);
     q->p = *p;

@@ -143,6 +143,8 @@ struct DParams {
     int32_t lockstep;        // 1: one grid barrier per step instead of the decoupled kernel
     int32_t dense;           // 1: the field step updates every vertex (no update list)
     int32_t fem;             // 1: the finite-element operator (m.fem_g) in place of the graph Laplacian
+    int32_t n_seed_set;      // > 0: the initial region grows from seed_set (ascending, unique; seed = its first)
+    const int32_t *seed_set; // device
 };
 
 // ---------------------------------------------------------------------------

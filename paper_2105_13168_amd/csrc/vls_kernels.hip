@@ -197,7 +197,10 @@ hipError_t launch_init(const DMesh &m, const DState &s, int64_t nnz, hipStream_t
 // ---------------------------------------------------------------------------
 // seed: hop ball B(s, r0) inside, field 1 on B; the update list of step 1 is
 // every vertex within r0+2 hops; initial loops numbered by their smallest
-// crossed half-edge key (inside*nv + outside)
+// crossed half-edge key (inside*nv + outside).  With a seed set S (the Reeb
+// refinement's pass from a handle loop) the region is every vertex within r0
+// hops of S, its vertices ranked by hop distance inside the region from
+// s = min S; S = {s} gives the ball.
 // ---------------------------------------------------------------------------
 struct SeedSh {
     int n;           // vertices listed so far
@@ -207,6 +210,7 @@ struct SeedSh {
     unsigned long long ne, nf;
     int nloops;
     int bad;
+    int nregion;     // seed-set mode: region size
 };
 
 __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
@@ -215,12 +219,22 @@ __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
     __shared__ int loopstart[64];
     const int tid = threadIdx.x;
     int32_t *list = s.L;       // BFS order, hop in Lrnd
+    const int nset = p.n_seed_set;
     if (tid == 0) {
-        sh.n = 1; sh.layer_beg = 0; sh.layer_end = 1; sh.nball = 0; sh.ne = 0; sh.nf = 0;
-        sh.nloops = 0; sh.bad = 0; sh.add = 0;
-        list[0] = (int32_t)p.seed;
-        s.Lrnd[0] = 0;
-        s.cstamp[p.seed] = -2;
+        const int n0 = nset > 0 ? nset : 1;
+        sh.n = n0; sh.layer_beg = 0; sh.layer_end = n0; sh.nball = 0; sh.ne = 0; sh.nf = 0;
+        sh.nloops = 0; sh.bad = 0; sh.add = 0; sh.nregion = 0;
+        if (nset <= 0) {
+            list[0] = (int32_t)p.seed;
+            s.Lrnd[0] = 0;
+            s.cstamp[p.seed] = -2;
+        }
+    }
+    for (int i = tid; i < nset; i += NT) {
+        const int32_t v = p.seed_set[i];
+        list[i] = v;
+        s.Lrnd[i] = 0;
+        s.cstamp[v] = -2;
     }
     __syncthreads();
     for (int h = 1; h <= p.r0 + 2; ++h) {
@@ -241,13 +255,46 @@ __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
         __syncthreads();
     }
     const int ntot = sh.n;
+    if (nset > 0) {
+        // hop distance from s inside the region (depth, -1 until reached),
+        // breadth first with the queue in cand[0]
+        int myreg = 0;
+        for (int i = tid; i < ntot; i += NT)
+            if (s.Lrnd[i] <= p.r0) { s.depth[list[i]] = -1; myreg++; }
+        atomicAdd(&sh.nregion, myreg);
+        __syncthreads();
+        int32_t *q = s.cand[0];
+        if (tid == 0) {
+            q[0] = (int32_t)p.seed;
+            s.depth[p.seed] = 0;
+            sh.add = 1; sh.layer_beg = 0; sh.layer_end = 1;
+        }
+        __syncthreads();
+        for (int h = 1;; ++h) {
+            const int beg = sh.layer_beg, end = sh.layer_end;
+            if (beg == end) break;
+            for (int i = beg + tid; i < end; i += NT) {
+                const int32_t v = q[i];
+                for (int32_t j = m.rp[v]; j < m.rp[v + 1]; ++j) {
+                    const int32_t u = m.adj[j];
+                    if (s.depth[u] == -1 && atomicCAS(&s.depth[u], -1, h) == -1) q[atomicAdd(&sh.add, 1)] = u;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) { sh.layer_beg = end; sh.layer_end = sh.add; }
+            __syncthreads();
+        }
+        if (tid == 0 && sh.add != sh.nregion) sh.bad = 4;
+        __syncthreads();
+    }
     // ball membership, field, update list of step 1 (stamp 1)
     int myball = 0;
     for (int i = tid; i < ntot; i += NT) {
         const int32_t v = list[i];
         const int h = s.Lrnd[i];
         if (h <= p.r0) {
-            s.key[v] = (uint64_t)h;      // step 0, round = hop
+            // step 0, round = hop (from s inside the region with a seed set)
+            s.key[v] = nset > 0 ? (uint64_t)(s.depth[v] < 0 ? 0 : s.depth[v]) : (uint64_t)h;
             s.rho0[v] = 1.0;
             s.rho1[v] = 1.0;
             myball++;
@@ -276,7 +323,7 @@ __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
             if (ku != KEY_OUT && ky != KEY_OUT && v < u && v < y) my_nf++;
         }
         s.parent[v] = par;
-        s.depth[v] = h;
+        s.depth[v] = nset > 0 ? (int32_t)kv : h;
     }
     atomicAdd(&sh.ne, (unsigned long long)my_ne);
     atomicAdd(&sh.nf, (unsigned long long)my_nf);
@@ -340,6 +387,7 @@ __global__ void __launch_bounds__(NT) k_seed(DMesh m, DState s, DParams p) {
         c->cnt_act[1] = ntot;
         c->last_insert = 0;
         if (sh.bad == 2) { c->status = ST_CAPACITY; c->err_code = 1; c->done = 1; }
+        else if (sh.bad == 4) { c->status = ST_SEED_INVALID; c->done = 1; }
         else if (sh.bad) { c->status = ST_INVARIANT; c->err_code = 2; c->done = 1; }
         else if (nl < 1 || 2 - chi - nl != 0) { c->status = ST_SEED_INVALID; c->done = 1; }
         else if (sh.nball == nvv) { c->done = 1; }
