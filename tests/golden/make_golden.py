@@ -54,6 +54,10 @@ FULL_CASES = {
     # the finite-element operator variant on a relaxed 128^3 pretzel
     "pretzel128_relaxed_fem_s0": (lambda: mg.relaxed(mg.pretzel(128, rng_seed=0), mg.pretzel_sdf(), 10),
                                   {"fem": 1}),
+    # the Reeb junction refinement's second pass (from the first kept handle
+    # loop of the ordinary pass): digests of that second pass
+    "pretzel256_refined_s0": (lambda: mg.pretzel(256, rng_seed=0), {"reeb_refine": 1}),
+    "lattice10_256_refined_s0": (lambda: mg.lattice(10, 256, rng_seed=0), {"reeb_refine": 1}),
 }
 
 
@@ -89,10 +93,16 @@ def main(full: bool = True, only=None):
         t0 = time.time()
         m = make()
         t1 = time.time()
-        r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed, **kw)
+        if kw.get("reeb_refine"):
+            _first, r = oracle.reeb_refined(m.xyz, m.tri, seed_vertex=m.seed)
+        else:
+            r = oracle.run(m.xyz, m.tri, seed_vertex=m.seed, **kw)
         t2 = time.time()
         d = digests(canon_oracle(r))
-        if kw:
+        if kw.get("reeb_refine"):
+            d["refined_seed_vertex"] = int(oracle.refinement_seed_set(_first)[0])
+            d["run_kwargs"] = kw
+        elif kw:
             d["run_kwargs"] = kw
             d["xyz_sha256"] = xyz_digest(m.xyz)
         d["nv"] = int(m.nv)

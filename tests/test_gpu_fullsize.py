@@ -98,3 +98,29 @@ def test_pretzel128_relaxed_fem_digests_match_oracle():
     s = g.summary
     assert s["run_status"] == 0 and s["n_handles"] == 3 and s["n_tunnels"] == 3
     _check(d, gold)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("pretzel256_refined_s0", lambda: mg.pretzel(256, rng_seed=0)),
+    ("lattice10_256_refined_s0", lambda: mg.lattice(10, 256, rng_seed=0)),
+])
+def test_reeb_refined_pass_digests_match_oracle(name, make):
+    """The Reeb junction refinement's second pass at full size: started from
+    the first kept handle loop of the ordinary pass, every output of that
+    pass equals the oracle's."""
+    import paper_2105_13168_amd as vls
+    if name not in GOLD:
+        pytest.skip(f"no oracle digest recorded for {name} (tests/golden/make_golden.py --full {name})")
+    gold = GOLD[name]
+    m = make()
+    assert m.nv == gold["nv"] and m.seed == gold["seed_vertex"]
+    ctx = vls.Context(0)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    try:
+        g = M.run(seed_vertex=m.seed, flags=vls.VLS_REEB_REFINE)
+    finally:
+        M.close()
+        ctx.close()
+    assert g.refined is not None
+    assert g.refined.summary["seed_vertex"] == gold["refined_seed_vertex"]
+    _check(digests(canon_gpu(g.refined)), gold)
