@@ -104,8 +104,11 @@ enum { VLS_NODE_SEED = 0, VLS_NODE_SPLIT = 1, VLS_NODE_MERGE = 2, VLS_NODE_VANIS
                                     vertices, ranked by hop distance inside that region from the
                                     smallest of them.  That second result (its Reeb graph has the
                                     refined junctions at its band means) is read with
-                                    vls_result_refined.  The passes, field checkpoints and deferral of
-                                    the first result do not apply to it */
+                                    vls_result_refined.  The first result is fetched before the second
+                                    pass starts, so VLS_DEFER_RESULTS has no effect; the secondary
+                                    passes and field checkpoints apply to the first pass only.  Not with
+                                    vls_batch_run, the server or the workspace calls
+                                    (VLS_E_INVALID_ARG) */
 #define VLS_BATCH_TWO_PER_CU 32u /* vls_batch_run (flags of per_mesh[0]) and the server (creation
                                     flags): two workgroups per CU, each with a 1024-candidate LDS
                                     topology path and one list entry per field thread; default: one
