@@ -232,6 +232,48 @@ def pass_leg(ctx, workload, steps, fem=False):
                          "kernel": "k_steps_dec<0, true>" if fem else "k_steps_dec"}}
 
 
+def refine_leg(ctx, workload):
+    """The Reeb junction refinement (VLS_REEB_REFINE): the ordinary pass,
+    then the initial pass again from its first kept handle loop; one
+    warm-up run, one timed run.  Reports both passes' step kernels and the
+    second pass's algorithmic bandwidth."""
+    import ctypes as C
+    import torch
+    import paper_2105_13168_amd as vls
+    m, desc = make_workload(workload)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    p = vls.default_params(seed_vertex=m.seed, flags=vls.VLS_REEB_REFINE)
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = C.c_void_p()
+        st = vls.vls_run(ctx.h, M.h, C.byref(p), C.byref(h))
+        if st != 0:
+            raise vls.VLSError(st, ctx.last_error())
+        wall = (time.perf_counter() - t0) * 1e3
+        h2 = C.c_void_p()
+        vls.vls_result_refined(h, C.byref(h2))
+        s1, s2 = vls.vls_summary(), vls.vls_summary()
+        vls.vls_result_summary(h, C.byref(s1))
+        vls.vls_result_summary(h2, C.byref(s2))
+        vls.vls_result_destroy(h)
+    M.close()
+    first = {f: getattr(s1, f) for f, _ in vls.vls_summary._fields_}
+    second = {f: getattr(s2, f) for f, _ in vls.vls_summary._fields_}
+    assert second["n_handles"] == second["euler_genus"] == first["n_handles"]
+    ab = alg_bytes(second["active_vertex_updates"], second["active_degree_sum"])
+    return {"workload": desc, "nv": m.nv, "ms_both_passes": wall,
+            "first_pass": {"diffusion_steps": first["steps"], "events": first["n_events"],
+                           "step_kernel_ms": first["kernel_ms"]},
+            "second_pass": {"root_vertex": second["seed_vertex"], "diffusion_steps": second["steps"],
+                            "events": second["n_events"], "handles": second["n_handles"],
+                            "reeb_nodes": second["reeb_nodes"], "step_kernel_ms": second["kernel_ms"],
+                            "roofline": {"bound": "hbm", "achieved": ab / (second["kernel_ms"] * 1e-3) / 1e9,
+                                         "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                         "frac": ab / (second["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                         "traffic": None, "kernel": "k_steps_dec"}}}
+
+
 def batch_leg(ctx, n, seq_sample, tune=False):
     """Batch of n uneven meshes in one launch (one workgroup per mesh)
     against the same meshes run one at a time (default launch) on a sample,
@@ -570,6 +612,8 @@ def main():
     ap.add_argument("--dense", action="store_true", help="time the whole pass with the dense field step")
     ap.add_argument("--passes-workload", default="lattice10_256",
                     help="mesh of the tunnel-loop / refinement pass leg ('none': skip)")
+    ap.add_argument("--refine-workload", default="pretzel256",
+                    help="workload of the Reeb refinement leg (none: skip)")
     ap.add_argument("--fem-passes", type=int, default=2,
                     help="timed passes of the relaxed 128^3 pretzel with the finite-element operator (0: skip)")
     args = ap.parse_args()
@@ -742,6 +786,12 @@ def main():
             log(f"finite-element leg done ({time.time() - t_start:.0f}s since start)")
         else:
             skipped.append("fem_pass")
+    if args.refine_workload != "none":
+        if left() > 30:
+            out["reeb_refine"] = refine_leg(ctx, args.refine_workload)
+            log(f"Reeb refinement leg done ({time.time() - t_start:.0f}s since start)")
+        else:
+            skipped.append("reeb_refine")
     if skipped:
         out["skipped_for_time_budget"] = skipped
     if args.copy_calibration:
