@@ -84,3 +84,23 @@ def test_refinement_only_through_vls_run():
     finally:
         M.close()
         ctx.close()
+
+
+def test_refined_pass_with_the_finite_element_operator(oracle_mod):
+    """The second pass inherits the field operator: with VLS_FEM_LAPLACIAN
+    both passes equal the oracle's finite-element runs."""
+    import paper_2105_13168_amd as vls
+    m = mg.relaxed(mg.pretzel(32, rng_seed=2), mg.pretzel_sdf(), 10)
+    ctx = vls.Context(0)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    try:
+        g = M.run(seed_vertex=m.seed, flags=vls.VLS_REEB_REFINE | vls.VLS_FEM_LAPLACIAN)
+    finally:
+        M.close()
+        ctx.close()
+    first, second = oracle_mod.reeb_refined(m.xyz, m.tri, seed_vertex=m.seed, fem=1)
+    assert not compare(g, first, m.nv)
+    assert second is not None and g.refined is not None
+    assert second.n_handles == 3
+    bad = compare(g.refined, second, m.nv)
+    assert not bad, bad
