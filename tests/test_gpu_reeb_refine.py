@@ -104,3 +104,27 @@ def test_refined_pass_with_the_finite_element_operator(oracle_mod):
     assert second.n_handles == 3
     bad = compare(g.refined, second, m.nv)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("radius", [0, 1, 3])
+def test_refined_pass_seed_radius(oracle_mod, radius):
+    """The seed radius sets how far the second pass's initial region reaches
+    around the loop's inside vertices (0: the vertices themselves); the
+    result equals the oracle's for each."""
+    import paper_2105_13168_amd as vls
+    m = mg.multi_torus(2, 28, rng_seed=3)
+    ctx = vls.Context(0)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    try:
+        g = M.run(seed_vertex=m.seed, flags=vls.VLS_REEB_REFINE, seed_radius=radius, raise_on_error=False)
+    finally:
+        M.close()
+        ctx.close()
+    first, second = oracle_mod.reeb_refined(m.xyz, m.tri, seed_vertex=m.seed, seed_radius=radius)
+    assert not compare(g, first, m.nv)
+    if second is None:
+        assert g.refined is None
+        return
+    assert g.refined is not None
+    bad = compare(g.refined, second, m.nv)
+    assert not bad, bad
