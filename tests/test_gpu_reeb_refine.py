@@ -128,3 +128,24 @@ def test_refined_pass_seed_radius(oracle_mod, radius):
     assert g.refined is not None
     bad = compare(g.refined, second, m.nv)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("variant", ["VLS_TOPO_GLOBAL_PATH", "VLS_DENSE_FIELD", "VLS_LOCKSTEP", "VLS_COHERENT_SHARING"])
+def test_refined_pass_kernel_variants(oracle_mod, variant):
+    """The second pass runs with the first pass's kernel variant (global
+    topology path, dense field step, lockstep, coherent sharing); every
+    variant gives the oracle's result."""
+    import paper_2105_13168_amd as vls
+    m = mg.pretzel(40, rng_seed=5)
+    ctx = vls.Context(0)
+    M = vls.Mesh(ctx, m.xyz, m.tri)
+    try:
+        g = M.run(seed_vertex=m.seed, flags=vls.VLS_REEB_REFINE | getattr(vls, variant))
+    finally:
+        M.close()
+        ctx.close()
+    first, second = oracle_mod.reeb_refined(m.xyz, m.tri, seed_vertex=m.seed)
+    assert not compare(g, first, m.nv)
+    assert g.refined is not None
+    bad = compare(g.refined, second, m.nv)
+    assert not bad, (variant, bad)
