@@ -58,6 +58,7 @@ FULL_CASES = {
     # loop of the ordinary pass): digests of that second pass
     "pretzel256_refined_s0": (lambda: mg.pretzel(256, rng_seed=0), {"reeb_refine": 1}),
     "lattice10_256_refined_s0": (lambda: mg.lattice(10, 256, rng_seed=0), {"reeb_refine": 1}),
+    "lattice10_512_refined_s0": (lambda: mg.lattice(10, 512, rng_seed=0), {"reeb_refine": 1}),
 }
 
 

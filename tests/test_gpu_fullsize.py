@@ -103,6 +103,7 @@ def test_pretzel128_relaxed_fem_digests_match_oracle():
 @pytest.mark.parametrize("name,make", [
     ("pretzel256_refined_s0", lambda: mg.pretzel(256, rng_seed=0)),
     ("lattice10_256_refined_s0", lambda: mg.lattice(10, 256, rng_seed=0)),
+    ("lattice10_512_refined_s0", lambda: mg.lattice(10, 512, rng_seed=0)),
 ])
 def test_reeb_refined_pass_digests_match_oracle(name, make):
     """The Reeb junction refinement's second pass at full size: started from
